@@ -1,0 +1,169 @@
+"""Pins of the oracle's Lanczos square root, adjoint and drift (CPU only).
+
+* Lanczos [Sec. 3.3]: with as many iterations as unknowns the Krylov space is
+  the whole space, so the result must equal the exact symmetric root from a
+  full eigendecomposition; the root squared must give back M; the small
+  tridiagonal root is checked against scipy's Schur-based ``sqrtm`` (a
+  different algorithm); the norm identity |y_k|^2 = W^T M W holds at every k.
+* Fluctuation-dissipation [eq. (fdt), Sec. 4]: Z = M^{-1/2} M^{1/2} W is
+  standard normal (Kolmogorov-Smirnov test).
+* Adjoint: the analytic gradient equals the complex-step derivative of the
+  dense forward map, and dL/dF is M g.
+* Drift [eq. (rfd), Sec. 4]: random finite differences average to the
+  (zero) divergence within their standard error.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.stats
+
+from oracle import drift, gradient, lanczos, mobility as mob
+
+A, ETA = 1.0, 1 / (6 * math.pi)
+
+
+def _system(n, side, seed):
+    rng = np.random.default_rng(seed)
+    x = (rng.random((n, 3)) - 0.5) * side
+    return x, rng
+
+
+@pytest.mark.parametrize("angular", [False, True])
+def test_full_krylov_space_gives_exact_root(angular):
+    x, rng = _system(5, 3.0, 21)
+    m = mob.grand_mobility(x, A, ETA, angular)
+    w = rng.standard_normal(m.shape[0])
+    y, info = lanczos.lanczos_sqrt(lambda v: m @ v, w, tol=0.0, maxit=m.shape[0])
+    exact = lanczos.exact_sqrt_mdot_w(m, w)
+    np.testing.assert_allclose(y, exact, rtol=0, atol=1e-12 * np.abs(exact).max())
+    # the exact root really is a square root of M
+    q = np.stack([lanczos.exact_sqrt_mdot_w(m, e) for e in np.eye(m.shape[0])], 1)
+    np.testing.assert_allclose(q @ q, m, atol=1e-13)
+    np.testing.assert_allclose(q, q.T, atol=1e-14)
+
+
+def test_tridiagonal_root_matches_schur_sqrtm():
+    rng = np.random.default_rng(2)
+    k = 9
+    al = 2 + rng.random(k)
+    be = 0.5 * rng.random(k - 1)
+    s, lam = lanczos.tridiagonal_sqrt_e1(al, be)
+    t = np.diag(al) + np.diag(be, 1) + np.diag(be, -1)
+    ref = scipy.linalg.sqrtm(t).real[:, 0]
+    np.testing.assert_allclose(s, ref, atol=1e-13)
+
+
+def test_converged_lanczos_close_to_exact_root_and_norm_identity():
+    x, rng = _system(150, 11.0, 22)
+    m = mob.grand_mobility(x, A, ETA)
+    w = rng.standard_normal(m.shape[0])
+    y, info = lanczos.lanczos_sqrt(lambda v: m @ v, w, tol=1e-6)
+    assert info.converged and not info.not_spd and 2 <= info.iters < 150
+    exact = lanczos.exact_sqrt_mdot_w(m, w)
+    err = np.linalg.norm(y - exact) / np.linalg.norm(exact)
+    assert err < 1e-5, err
+    # |y_k|^2 = beta0^2 e1^T T_k e1 = W^T M W while the basis stays orthonormal
+    assert abs(y @ y - w @ m @ w) <= 1e-12 * (w @ m @ w)
+    # matched-iteration rerun reproduces the same iterate bit for bit
+    y2, info2 = lanczos.lanczos_sqrt(lambda v: m @ v, w, iters=info.iters)
+    np.testing.assert_array_equal(y, y2)
+
+
+def test_lanczos_prefactor_zero_vector_and_not_converged_flag():
+    x, rng = _system(20, 6.0, 23)
+    m = mob.grand_mobility(x, A, ETA)
+    w = rng.standard_normal(60)
+    y1, _ = lanczos.lanczos_sqrt(lambda v: m @ v, w, tol=1e-8)
+    y2, _ = lanczos.lanczos_sqrt(lambda v: m @ v, w, tol=1e-8, prefactor=0.25)
+    np.testing.assert_allclose(y2, 0.25 * y1, rtol=1e-15)
+    z, info = lanczos.lanczos_sqrt(lambda v: m @ v, np.zeros(60))
+    assert not z.any() and info.iters == 0
+    _, info = lanczos.lanczos_sqrt(lambda v: m @ v, w, tol=0.0, maxit=3)
+    assert not info.converged and info.iters == 3
+
+
+def test_lanczos_flags_indefinite_operator():
+    rng = np.random.default_rng(4)
+    q, _ = np.linalg.qr(rng.standard_normal((12, 12)))
+    m = q @ np.diag(np.r_[-1.0, np.ones(11)]) @ q.T
+    _, info = lanczos.lanczos_sqrt(lambda v: m @ v, rng.standard_normal(12), tol=1e-10)
+    assert info.not_spd
+
+
+def test_fluctuation_dissipation_ks():
+    x, rng = _system(8, 4.0, 24)
+    m = mob.grand_mobility(x, A, ETA, True)
+    inv_sqrt = lanczos.exact_inv_sqrt(m)
+    zs = []
+    for _ in range(400):
+        w = rng.standard_normal(m.shape[0])
+        y, _ = lanczos.lanczos_sqrt(lambda v: m @ v, w, tol=1e-10)
+        zs.append(inv_sqrt @ y)
+    z = np.concatenate(zs)
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-3
+    cov = np.cov(np.stack(zs).T)
+    assert np.abs(cov - np.eye(m.shape[0])).max() < 0.35
+
+
+@pytest.mark.parametrize("angular", [False, True])
+def test_adjoint_matches_complex_step(angular):
+    x, rng = _system(9, 3.2, 25)               # several overlapping pairs
+    F = rng.standard_normal((9, 3))
+    T = rng.standard_normal((9, 3)) if angular else None
+    gu = rng.standard_normal((9, 3))
+    gw = rng.standard_normal((9, 3)) if angular else None
+
+    def loss(xc):
+        u, w = mob.mdot_dense(xc, F.astype(xc.dtype), None if T is None else T.astype(xc.dtype), A, ETA)
+        val = (u * gu).sum()
+        if angular:
+            val = val + (w * gw).sum()
+        return val
+
+    dx, df, dt = gradient.mdot_vjp(x, F, T, gu, gw, A, ETA)
+    cs = gradient.complex_step_grad(loss, x, range(27)).reshape(9, 3)
+    np.testing.assert_allclose(dx, cs, rtol=0, atol=1e-12 * np.abs(cs).max())
+    # dL/dF: the loss is linear in F, so the complex step is exact as well
+    def loss_f(fc):
+        u, w = mob.mdot_dense(x.astype(fc.dtype), fc, None if T is None else T.astype(fc.dtype), A, ETA)
+        return (u * gu).sum() + ((w * gw).sum() if angular else 0.0)
+    csf = gradient.complex_step_grad(loss_f, F, range(27)).reshape(9, 3)
+    np.testing.assert_allclose(df, csf, rtol=0, atol=1e-13 * np.abs(csf).max())
+    rows = np.array([0, 4, 7])
+    dxr, dfr, dtr = gradient.mdot_vjp_rows(x, F, T, gu, gw, A, ETA, rows)
+    np.testing.assert_allclose(dxr, dx[rows], atol=1e-13)
+    np.testing.assert_allclose(dfr, df[rows], atol=1e-13)
+
+
+def test_adjoint_central_difference_of_quadratic_loss():
+    x, rng = _system(30, 6.0, 26)
+    F = rng.standard_normal((30, 3))
+    ustar = mob.mdot_dense(x + 0.1 * rng.standard_normal(x.shape), F, None, A, ETA)[0]
+    def L(xx):
+        u = mob.mdot_dense(xx, F, None, A, ETA)[0]
+        return 0.5 * ((u - ustar) ** 2).sum()
+    g = mob.mdot_dense(x, F, None, A, ETA)[0] - ustar
+    dx, df, _ = gradient.mdot_vjp(x, F, None, g, None, A, ETA)
+    h = 1e-4
+    for c in rng.choice(90, 12, replace=False):
+        xp = x.copy(); xp.flat[c] += h
+        xm = x.copy(); xm.flat[c] -= h
+        fd = (L(xp) - L(xm)) / (2 * h)
+        assert abs(fd - dx.flat[c]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_random_finite_differences_average_to_zero():
+    x, rng = _system(6, 3.0, 27)
+    samples = []
+    for _ in range(600):
+        w = rng.standard_normal(18)
+        lin, _ = drift.rfd_sample(x, w, 1e-4, A, ETA)
+        samples.append(lin.reshape(-1))
+    s = np.array(samples)
+    mean = s.mean(0)
+    se = s.std(0, ddof=1) / math.sqrt(len(s))
+    assert np.all(np.abs(mean) <= 5 * se)
+    det = drift.divergence_fd(x, 1e-4, A, ETA)
+    assert np.abs(det - 0).max() < 1e-8

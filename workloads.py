@@ -1,0 +1,177 @@
+"""Seeded synthetic inputs for the open-boundary RPY mobility path.
+
+This module only draws random numbers and lays them out; it holds none of the
+mobility arithmetic.  Both the HIP path (through its tests and the benchmark)
+and the CPU oracle are fed from here, so the two sides always see the same
+numbers.
+
+Recipe shared by every workload:
+
+* generator ``numpy.random.default_rng(seed)`` (PCG64);
+* draw order: positions, then forces, then torques, then the noise vector W,
+  then any subset / perturbation indices;
+* particles of radius ``a`` are placed uniformly in a cube centred at the
+  origin, ``[-L/2, L/2)^3`` with ``L = (N (4/3) pi a^3 / phi)^(1/3)``;
+  overlaps are allowed, as in the paper's timing benchmark (Sec. 5.5);
+* forces, torques and W are i.i.d. standard normal;
+* float32 arrays are the float64 draws rounded once.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Unit choice of every workload: radius 1 and viscosity 1/(6 pi), so that the
+# single-particle translational mobility 1/(6 pi eta a) equals 1.
+RADIUS = 1.0
+VISCOSITY = 1.0 / (6.0 * math.pi)
+
+
+def cube_side(n: int, phi: float, a: float = RADIUS) -> float:
+    """Side of the cube holding ``n`` spheres of radius ``a`` at volume fraction ``phi``."""
+    return (n * (4.0 / 3.0) * math.pi * a ** 3 / phi) ** (1.0 / 3.0)
+
+
+@dataclass
+class Suspension:
+    """One synthetic system: float64 draws, with float32 copies made on demand."""
+    name: str
+    pos: np.ndarray                       # (N, 3) float64
+    forces: np.ndarray                    # (N, 3) float64
+    torques: np.ndarray | None = None     # (N, 3) float64
+    w: np.ndarray | None = None           # (3N,) or (6N,) float64
+    radius: float = RADIUS
+    viscosity: float = VISCOSITY
+    box: float = 0.0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+    def as_dtype(self, dtype) -> "Suspension":
+        """Copy with every array rounded to ``dtype`` (float32 rounds once)."""
+        cast = (lambda a: None if a is None else np.ascontiguousarray(a, dtype=dtype))
+        return Suspension(self.name, cast(self.pos), cast(self.forces), cast(self.torques),
+                          cast(self.w), self.radius, self.viscosity, self.box,
+                          {k: (cast(v) if isinstance(v, np.ndarray) and v.dtype.kind == "f" else v)
+                           for k, v in self.extra.items()})
+
+    def rounded64(self, dtype=np.float32) -> "Suspension":
+        """The arrays rounded to ``dtype`` and promoted back to float64."""
+        s = self.as_dtype(dtype)
+        return s.as_dtype(np.float64)
+
+
+def uniform_cube(n: int, phi: float, seed: int, *, torques: bool = False,
+                 w: bool = False, angular_w: bool = False,
+                 a: float = RADIUS, name: str = "") -> Suspension:
+    """Uniform random suspension; draw order positions, forces, torques, W."""
+    rng = np.random.default_rng(seed)
+    side = cube_side(n, phi, a)
+    pos = (rng.random((n, 3)) - 0.5) * side
+    forces = rng.standard_normal((n, 3))
+    tq = rng.standard_normal((n, 3)) if torques else None
+    wv = rng.standard_normal(6 * n if angular_w else 3 * n) if w else None
+    s = Suspension(name or f"cube_n{n}_phi{phi}_s{seed}", pos, forces, tq, wv,
+                   radius=a, box=side)
+    s.extra["rng"] = rng
+    return s
+
+
+# ---------------------------------------------------------------------------
+# The named workloads
+# ---------------------------------------------------------------------------
+
+def c1_small_fp64() -> Suspension:
+    """N=1024, phi=0.1, seed 1001: translational product in float64."""
+    return uniform_cube(1024, 0.1, 1001, name="c1_n1024_phi0.1")
+
+
+def c2_suspension(n: int = 65536) -> Suspension:
+    """N=65,536, phi=0.1, seed 1002: forces, torques and a 6N noise vector.
+
+    ``extra['subset']`` holds 4096 target indices drawn without replacement
+    (drawn last, after W).
+    """
+    s = uniform_cube(n, 0.1, 1002, torques=True, w=True, angular_w=True,
+                     name=f"c2_n{n}_phi0.1")
+    rng = s.extra.pop("rng")
+    s.extra["subset"] = np.sort(rng.choice(n, size=min(4096, n), replace=False))
+    return s
+
+
+def c3_gradient(n: int = 16384) -> Suspension:
+    """N=16,384, phi=0.2, seed 1003: loss 0.5*||M(X)F - U*||^2.
+
+    After positions and forces the generator draws the perturbation
+    ``delta ~ N(0, (0.1 a)^2)`` (N x 3) that defines the target configuration
+    X + delta, then 64 (particle, axis) coordinates and 64 force coordinates
+    (flat indices into N x 3, without replacement).
+    """
+    rng = np.random.default_rng(1003)
+    side = cube_side(n, 0.2)
+    pos = (rng.random((n, 3)) - 0.5) * side
+    forces = rng.standard_normal((n, 3))
+    delta = 0.1 * RADIUS * rng.standard_normal((n, 3))
+    fd_pos = rng.choice(3 * n, size=64, replace=False)
+    fd_force = rng.choice(3 * n, size=64, replace=False)
+    s = Suspension(f"c3_n{n}_phi0.2", pos, forces, None, None, box=side)
+    s.extra.update(delta=delta, fd_pos=fd_pos, fd_force=fd_force)
+    return s
+
+
+def c4_systems(n_systems: int = 512, seed: int = 1004,
+               n_min: int = 64, n_max: int = 8192) -> list[Suspension]:
+    """Independent systems with N log-uniform in [n_min, n_max] and phi in [0.05, 0.3].
+
+    One generator draws, in order: every N_s, every phi_s, then for each
+    system its positions, forces and 3N noise vector.
+    """
+    rng = np.random.default_rng(seed)
+    ns = np.rint(np.exp(rng.uniform(math.log(n_min), math.log(n_max), n_systems))).astype(np.int64)
+    phis = rng.uniform(0.05, 0.3, n_systems)
+    out = []
+    for k in range(n_systems):
+        n = int(ns[k])
+        side = cube_side(n, float(phis[k]))
+        pos = (rng.random((n, 3)) - 0.5) * side
+        forces = rng.standard_normal((n, 3))
+        wv = rng.standard_normal(3 * n)
+        s = Suspension(f"c4_sys{k}_n{n}", pos, forces, None, wv, box=side)
+        s.extra["phi"] = float(phis[k])
+        out.append(s)
+    return out
+
+
+def c5_chains(n_chains: int = 4096, beads: int = 256, bond: float = 2.1,
+              phi: float = 0.05, seed: int = 1005) -> Suspension:
+    """Random-walk bead chains: 4096 x 256 beads at bead volume fraction 0.05.
+
+    Bond vectors have length ``bond`` (2.1 a) and directions from normalised
+    N(0, I3) draws; each chain is centred on its centroid and then shifted to
+    a centre uniform in the cube.  Draw order: bond directions, chain
+    centres, forces, torques, W (6N).
+    """
+    rng = np.random.default_rng(seed)
+    n = n_chains * beads
+    side = cube_side(n, phi)
+    dirs = rng.standard_normal((n_chains, beads - 1, 3))
+    dirs /= np.linalg.norm(dirs, axis=2, keepdims=True)
+    chain = np.concatenate([np.zeros((n_chains, 1, 3)), np.cumsum(bond * dirs, axis=1)], axis=1)
+    chain -= chain.mean(axis=1, keepdims=True)
+    centres = (rng.random((n_chains, 1, 3)) - 0.5) * side
+    pos = (chain + centres).reshape(n, 3)
+    forces = rng.standard_normal((n, 3))
+    tq = rng.standard_normal((n, 3))
+    wv = rng.standard_normal(6 * n)
+    s = Suspension(f"c5_chains{n_chains}x{beads}", pos, forces, tq, wv, box=side)
+    s.extra["subset"] = np.sort(rng.choice(n, size=min(4096, n), replace=False))
+    return s
+
+
+def scaled_chain_workload(n_chains: int, beads: int = 256, seed: int = 1005) -> Suspension:
+    """Same chain recipe at fewer chains (for tests that cannot afford 1M beads)."""
+    return c5_chains(n_chains=n_chains, beads=beads, seed=seed)
