@@ -1,0 +1,240 @@
+"""Benchmark of the open-boundary RPY mobility hot path on one MI355X.
+
+One step is one pass of the whole single-system hot path over the
+N = 65,536 suspension (uniform cube at volume fraction 0.1, a = 1,
+eta = 1/(6 pi), F, T, W ~ N(0, 1), seed 1002), in the float32 pair mode:
+
+    Mdot(F, T)                      linear + angular product
+    sqrtMdotW(W), tol 1e-6          Lanczos, float64 basis on the device
+    divM()                          thermal drift (zero in open space)
+    Mdot_backward(F, T, gU, gW)     adjoint: dL/dX, dL/dF, dL/dT
+
+value = N^2 x (number of M products in the step: 1 + Lanczos iterations)
+divided by the step time, in pair-interactions/s (the drift and the backward
+pass are inside the timed step but add no M products).  Inputs are resident
+in device memory before timing starts.
+
+Also reported (outside the timed steps, same data): float32 and float64
+pair-interactions/s of one Mdot (translational, and with torques), the
+backward/forward time ratio, the roofline position of the dominant kernel
+(the float32 angular pair kernel, timed with HIP events on its own stream
+inside the timed steps), the max relative error of each result against the
+float64 CPU oracle on sampled particles, and the oracle's own rate on a
+bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "RPY pair-interactions/s for M·F, FP32 vs FP64, N=65,536; backward/forward"
+PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
+PEAK_FP64_TFLOPS = 78.6
+FLOPS_PER_PAIR = {"linear": 34, "angular": 84}
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--n", type=int, default=65536, help="particles (default: the 65,536 workload)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
+    return p.parse_args()
+
+
+def emax(got, ref):
+    import numpy as np
+    got = np.asarray(got, dtype=np.float64).reshape(-1, 3)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1, 3)
+    return float(np.linalg.norm(got - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
+
+
+def timed(fn, reps, stream):
+    """Median milliseconds of fn() over reps runs, HIP events on `stream`."""
+    import torch
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    return times[len(times) // 2]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
+              "the multi-GPU layout is a design note, not an implementation.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2510_02135_amd as rpy
+    from paper_2510_02135_amd import _lib
+    import workloads
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    s = workloads.c2_suspension(args.n)
+    n = s.n
+    rng = np.random.default_rng(4242)
+    g_u, g_w = rng.standard_normal((2, n, 3))
+
+    def dev_t(x, dt):
+        return torch.tensor(np.asarray(x), dtype=dt, device=dev)
+
+    f32 = torch.float32
+    X, F, T, W = (dev_t(v, f32) for v in (s.pos, s.forces, s.torques, s.w))
+    GU, GW = dev_t(g_u, f32), dev_t(g_w, f32)
+    sol = rpy.Solver("open", "open", "open")
+    sol.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius, includeAngular=True)
+    sol.setPositions(X)
+
+    iters = []
+
+    def step():
+        sol.Mdot(forces=F, torques=T)
+        sol.sqrtMdotW(W, prefactor=1.0, tol=1e-6, maxIter=500)
+        iters.append(sol.last_iterations)
+        sol.divM()
+        sol.Mdot_backward(F, T, GU, GW)
+
+    print(f"bench: N={n} warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    iters.clear()
+    _lib.rpy_enable_timing(sol._h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+        print(f"bench: step {k + 1}/{args.steps} done ({iters[-1]} Lanczos iterations)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pair_ms, pair_launches, pair_pairs = _lib.rpy_kernel_time(sol._h, "pair")
+    adj_ms, adj_launches, _ = _lib.rpy_kernel_time(sol._h, "adjoint")
+    _lib.rpy_enable_timing(sol._h, False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    products = sum(1 + k for k in iters)
+    value = float(n) * float(n) * products / elapsed
+
+    # dominant kernel: the float32 angular pair kernel (every M product of the step)
+    avg_pair_ms = pair_ms / max(pair_launches, 1)
+    achieved = FLOPS_PER_PAIR["angular"] * float(n) * float(n) / (avg_pair_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "kernel": "pair_kernel<float, angular>", "avg_launch_ms": round(avg_pair_ms, 4),
+                "launches": pair_launches, "flops_per_pair": FLOPS_PER_PAIR["angular"]}
+
+    # ---- breakdown outside the timed steps -------------------------------
+    print("bench: breakdown (fp32/fp64 Mdot, backward)", file=sys.stderr, flush=True)
+    breakdown = {}
+    results = {}
+    for dt, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+        Xd, Fd, Td = dev_t(s.pos, dt), dev_t(s.forces, dt), dev_t(s.torques, dt)
+        GUd, GWd = dev_t(g_u, dt), dev_t(g_w, dt)
+        for ang in (False, True):
+            so = rpy.Solver()
+            so.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius, includeAngular=ang)
+            so.setPositions(Xd)
+            key = f"{name}_{'angular' if ang else 'linear'}"
+            fwd = lambda: so.Mdot(forces=Fd, torques=Td if ang else None)
+            bwd = lambda: so.Mdot_backward(Fd, Td if ang else None, GUd, GWd if ang else None)
+            fwd()
+            bwd()
+            tf = timed(fwd, 5, stream)
+            tb = timed(bwd, 3, stream)
+            breakdown[key] = {"mdot_ms": round(tf, 4), "pairs_per_s": float(n) * n / (tf * 1e-3),
+                              "backward_ms": round(tb, 4), "backward_over_forward": round(tb / tf, 3)}
+            lin, angv = fwd()
+            gp, gf, gt = bwd()
+            results[key] = (lin.double().cpu().numpy(), None if angv is None else angv.double().cpu().numpy(),
+                            gp.double().cpu().numpy(), gf.double().cpu().numpy())
+            so.close()
+
+    # ---- accuracy against the float64 oracle on sampled particles --------
+    print("bench: oracle check on sampled rows", file=sys.stderr, flush=True)
+    from oracle import gradient, pairloop
+    rows = s.extra["subset"][:256]
+    acc = {}
+    for key, (lin, angv, gp, gf) in results.items():
+        dt = np.float32 if key.startswith("fp32") else np.float64
+        xr = s.pos.astype(dt).astype(np.float64)
+        fr = s.forces.astype(dt).astype(np.float64)
+        tr = s.torques.astype(dt).astype(np.float64) if angv is not None else None
+        u, w = pairloop.mdot_rows(xr, rows, fr, tr, s.radius, s.viscosity)
+        e = emax(lin[rows], u)
+        if angv is not None:
+            e = max(e, emax(angv[rows], w))
+        gur = g_u.astype(dt).astype(np.float64)
+        gwr = g_w.astype(dt).astype(np.float64) if angv is not None else None
+        mg, _ = pairloop.mdot_rows(xr, rows[:64], gur, gwr, s.radius, s.viscosity)
+        gx = gradient.grad_positions(xr, fr, tr, gur, gwr, s.radius, s.viscosity, rows=rows[:8])
+        acc[key] = {"mdot_emax": e, "backward_dF_emax": emax(gf[rows[:64]], mg),
+                    "backward_dX_emax": emax(gp[rows[:8]], gx)}
+
+    # ---- CPU oracle baseline on a bounded sample --------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
+        probe = s.extra["subset"][:64]
+        t1 = time.perf_counter()
+        pairloop.mdot_rows(s.pos, probe, s.forces, s.torques, s.radius, s.viscosity)
+        rate = len(probe) * n / (time.perf_counter() - t1)
+        m = int(min(n, max(64, args.cpu_seconds * rate / n)))
+        sample = np.sort(np.random.default_rng(7).choice(n, size=m, replace=False))
+        t1 = time.perf_counter()
+        pairloop.mdot_rows(s.pos, sample, s.forces, s.torques, s.radius, s.viscosity)
+        dt_cpu = time.perf_counter() - t1
+        cpu = {"value": m * float(n) / dt_cpu, "unit": "pair-interactions/s", "cores": pairloop.threads(),
+               "kind": "oracle",
+               "sample": f"{m} target rows x {n} sources of the same workload, linear+angular Mdot, "
+                         f"float64 C/OpenMP pair loop ({dt_cpu:.1f} s)"}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"uniform-cube suspension N={n}, phi=0.1, a=1, eta=1/(6 pi), seed 1002; "
+                               "float32 pairs: Mdot(F,T) + sqrtMdotW(W, tol 1e-6, float64 Lanczos) + divM + "
+                               "Mdot_backward(F,T,gU,gW)",
+                   "n": n, "lanczos_iterations": iters, "m_products_per_step": products / args.steps},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "breakdown": breakdown,
+        "accuracy_vs_fp64_oracle": acc,
+        "adjoint_kernel_avg_ms": round(adj_ms / max(adj_launches, 1), 4),
+    }
+    sol.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * rpy.h - C interface of the MI355X (gfx950) open-boundary RPY mobility library.
+ *
+ * The library applies the grand mobility matrix M(X) of a suspension of N
+ * equal spheres in an unbounded Stokes fluid (the "NBody" open-boundary
+ * solver of the libMobility paper, Sec. 3.5; blocks of eq. (block_mobility),
+ * Rotne-Prager-Yamakawa pair tensors including the overlap branch), and
+ * builds the terms of the overdamped Langevin equation (eq. (bdhi)) on it:
+ * deterministic displacements M [F; T] (Mdot), fluctuations M^{1/2} W by
+ * Lanczos (sqrtMdotW, Sec. 3.3) and the thermal drift (divM, Sec. 3.4).  The
+ * call sequence follows the paper's solver interface (Sec. 3.2):
+ * constructor with per-axis periodicity, setParameters, initialize,
+ * setPositions, then Mdot / sqrtMdotW / divM.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Arrays are DEVICE pointers owned by the caller and only borrowed for the
+ *   duration of the call (stream-ordered).  Per-particle arrays (positions,
+ *   forces, torques, linear and angular outputs) are N x 3 row-major:
+ *   element (i, k) at offset 3*i + k.  Noise and Lanczos vectors have 3N
+ *   entries (translational only) or 6N entries (first the 3N linear, then
+ *   the 3N angular, each particle-major).
+ * - Every array of a call has the element type given to the most recent
+ *   rpy_set_positions (RPY_F32 = float, RPY_F64 = double).  float inputs
+ *   select the float32 pair evaluation (compensated cross-tile sums);
+ *   double inputs select the float64 one.
+ * - `hip_stream` is a hipStream_t (NULL = the null stream).  Work is
+ *   enqueued on it and the call returns without waiting, except where a
+ *   call says it synchronises.
+ * - Every call returns an rpy_status; no exception crosses the interface.
+ *   rpy_last_error() describes the most recent failure of that solver.
+ *   HIP failures (including asynchronous faults surfacing at a
+ *   synchronising call) return RPY_ERR_HIP.
+ * - A solver handle must not be used from two host threads at once.
+ */
+#ifndef RPY_H
+#define RPY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rpy_solver rpy_solver;
+
+typedef enum {
+    RPY_OK = 0,
+    RPY_ERR_INVALID_ARG = 1,          /* null pointer, N <= 0, eta <= 0, a <= 0, bad tol ... */
+    RPY_ERR_UNSUPPORTED_GEOMETRY = 2, /* any periodicity other than open/open/open        */
+    RPY_ERR_NOT_INITIALIZED = 3,      /* rpy_initialize not called yet                     */
+    RPY_ERR_NO_POSITIONS = 4,         /* rpy_set_positions not called yet                  */
+    RPY_ERR_SIZE_MISMATCH = 5,        /* batch sizes inconsistent                          */
+    RPY_ERR_DTYPE_MISMATCH = 6,       /* dtype other than RPY_F32 / RPY_F64                */
+    RPY_ERR_ANGULAR_DISABLED = 7,     /* torques / angular output without include_angular  */
+    RPY_ERR_NONFINITE = 8,            /* NaN or Inf in positions or noise                  */
+    RPY_ERR_NOT_CONVERGED = 9,        /* Lanczos reached max_iter (last iterate written)    */
+    RPY_ERR_NOT_SPD = 10,             /* Lanczos met a clearly negative Ritz value          */
+    RPY_ERR_OUT_OF_MEMORY = 11,
+    RPY_ERR_HIP = 12
+} rpy_status;
+
+/* Per-axis boundary condition (constructor of Sec. 3.2). */
+typedef enum { RPY_PERIODIC = 0, RPY_OPEN = 1, RPY_SINGLE_WALL = 2, RPY_TWO_WALLS = 3 } rpy_periodicity;
+
+typedef enum { RPY_F32 = 0, RPY_F64 = 1 } rpy_dtype;
+
+/*
+ * Create a solver for the given periodicity of the x, y and z axes
+ * (Sec. 3.2, constructor; Sec. 3.5: the N-body solver is open in x and y).
+ * Only (open, open, open) is built; anything else returns
+ * RPY_ERR_UNSUPPORTED_GEOMETRY and writes NULL.  The caller owns *out and
+ * frees it with rpy_destroy.  Does not touch the GPU.
+ */
+rpy_status rpy_create(rpy_periodicity x, rpy_periodicity y, rpy_periodicity z, rpy_solver **out);
+
+/*
+ * Domain-specific parameter by name (Sec. 3.2, setParameters: e.g. the wall
+ * height of wall geometries).  Open boundaries have none, so every key
+ * returns RPY_ERR_INVALID_ARG.
+ */
+rpy_status rpy_set_parameter(rpy_solver *s, const char *key, double value);
+
+/*
+ * Shared physical parameters (Sec. 3.2, initialize): fluid viscosity eta > 0
+ * and hydrodynamic radius a > 0 (self mobility 1/(6 pi eta a)), and whether
+ * torques / angular velocities are accepted (includeAngular, default off in
+ * the paper because it is cheaper without).  May be called again to change
+ * them; stored positions are kept.  Does not touch the GPU.
+ */
+rpy_status rpy_initialize(rpy_solver *s, double viscosity, double hydrodynamic_radius,
+                          int include_angular);
+
+/*
+ * Store the current positions (Sec. 3.2, setPositions): `pos` is a device
+ * array of n x 3 elements of `dtype`.  The values are copied into
+ * solver-owned storage, so `pos` may be reused after the call.  Checks the
+ * positions for NaN/Inf (RPY_ERR_NONFINITE; nothing is stored) and
+ * therefore synchronises `hip_stream`.  Grows solver buffers as needed
+ * (RPY_ERR_OUT_OF_MEMORY on failure).
+ */
+rpy_status rpy_set_positions(rpy_solver *s, const void *pos, int64_t n, rpy_dtype dtype,
+                             void *hip_stream);
+
+/*
+ * Deterministic displacements (Sec. 3.2, Mdot; first term of eq. (bdhi)):
+ * lin_out = M_uF F + M_uT T and, when ang_out != NULL, ang_out =
+ * M_wF F + M_wT T, with M the grand mobility of eq. (block_mobility) at the
+ * stored positions.  forces and torques are n x 3 (either may be NULL, not
+ * both; a missing one counts as zero).  Torques or ang_out require
+ * include_angular (RPY_ERR_ANGULAR_DISABLED).  Outputs are overwritten.
+ * Asynchronous.
+ */
+rpy_status rpy_mdot(rpy_solver *s, const void *forces, const void *torques,
+                    void *lin_out, void *ang_out, void *hip_stream);
+
+/*
+ * Fluctuating displacements (Sec. 3.2, sqrtMdotW; second term of eq.
+ * (bdhi)) by the Lanczos iteration of Sec. 3.3:
+ * y = prefactor * M^{1/2} w, converging to the symmetric square root.
+ * `w` has 3N entries (6N with include_angular); the caller draws it (the
+ * caller also supplies prefactor = sqrt(2 kT dt)).  Writes the linear part
+ * of y to lin_out (n x 3) and, with include_angular, the angular part to
+ * ang_out (n x 3, required then).  Iterates until the relative change of
+ * successive iterates is below `tol` (0 < tol < 1) or `max_iter` (>= 1)
+ * iterations.  The Krylov basis and tridiagonal matrix are kept in float64
+ * on the device; the products with M use the solver's dtype.  Synchronises
+ * `hip_stream`; *iters_out and *incr_out (may be NULL) receive the number
+ * of iterations and the last relative increment.  Returns
+ * RPY_ERR_NOT_CONVERGED (result still written) at max_iter,
+ * RPY_ERR_NOT_SPD when M is found indefinite, RPY_ERR_NONFINITE for a
+ * non-finite w.  A zero w gives zero output.
+ */
+rpy_status rpy_sqrt_mdot_w(rpy_solver *s, const void *w, double prefactor, double tol,
+                           int max_iter, void *lin_out, void *ang_out, int *iters_out,
+                           double *incr_out, void *hip_stream);
+
+/*
+ * Thermal drift d_X . M (Sec. 3.2, divM; third term of eq. (bdhi)).  In an
+ * unbounded fluid M is translation invariant and isotropic, so the
+ * divergence vanishes (Sec. 2, Sec. 3.4): writes zeros to lin_out (n x 3)
+ * and to ang_out when given (requires include_angular).  Asynchronous.
+ */
+rpy_status rpy_div_m(rpy_solver *s, void *lin_out, void *ang_out, void *hip_stream);
+
+/*
+ * Adjoint of rpy_mdot at the stored positions (an addition beside the
+ * paper's method): for cotangents g_U = grad_lin and g_W = grad_ang of a
+ * scalar loss with respect to the Mdot outputs, writes
+ *   grad_pos    = dL/dX (n x 3),
+ *   grad_forces = M_uF^T g_U + M_wF^T g_W (= the linear rows of M [g_U; g_W]),
+ *   grad_torques= M_uT^T g_U + M_wT^T g_W (angular rows),
+ * each output optional (NULL skips it; at least one required).  forces /
+ * torques are the inputs of the forward call (either may be NULL, not both);
+ * grad_ang / torques / grad_torques require include_angular.  A pair of
+ * coincident particles contributes nothing to grad_pos.  Asynchronous.
+ */
+rpy_status rpy_mdot_backward(rpy_solver *s, const void *forces, const void *torques,
+                             const void *grad_lin, const void *grad_ang, void *grad_pos,
+                             void *grad_forces, void *grad_torques, void *hip_stream);
+
+/* Kernel classes reported by rpy_kernel_time. */
+typedef enum { RPY_KERNEL_PAIR = 0, RPY_KERNEL_ADJOINT = 1 } rpy_kernel;
+
+/*
+ * Instrumentation, not part of the method: with `enable` != 0 the solver
+ * records a HIP event pair around every launch of its pair kernel (forward
+ * products, including those inside sqrtMdotW) and of its adjoint kernel, on
+ * the stream of the call.  Enabling (or re-enabling) clears the records.
+ */
+rpy_status rpy_enable_timing(rpy_solver *s, int enable);
+
+/*
+ * Sum of the recorded launch durations of one kernel class in milliseconds,
+ * the number of launches and the number of ordered particle pairs they
+ * evaluated.  Waits for the recorded events (host blocking).  Any output
+ * pointer may be NULL.
+ */
+rpy_status rpy_kernel_time(rpy_solver *s, rpy_kernel kernel, double *ms_total, int64_t *launches,
+                           double *pairs);
+
+/* Message describing the last failure of `s` ("" if none); owned by `s`. */
+const char *rpy_last_error(const rpy_solver *s);
+
+/* Release the solver and every device buffer it owns.  NULL is ignored. */
+void rpy_destroy(rpy_solver *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPY_H */

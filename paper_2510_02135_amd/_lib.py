@@ -1,0 +1,204 @@
+"""ctypes binding of librpy (include/rpy.h): argument marshalling only.
+
+Each ``rpy_*`` function here has the name and meaning of the C entry point
+it calls; it turns torch device tensors into device pointers, passes torch's
+current HIP stream, and turns a non-OK status into an exception.  Nothing
+here computes: every step runs in the HIP library, and importing this module
+fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import enum
+import os
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librpy.so")
+
+
+class Status(enum.IntEnum):
+    OK = 0
+    INVALID_ARG = 1
+    UNSUPPORTED_GEOMETRY = 2
+    NOT_INITIALIZED = 3
+    NO_POSITIONS = 4
+    SIZE_MISMATCH = 5
+    DTYPE_MISMATCH = 6
+    ANGULAR_DISABLED = 7
+    NONFINITE = 8
+    NOT_CONVERGED = 9
+    NOT_SPD = 10
+    OUT_OF_MEMORY = 11
+    HIP = 12
+
+
+PERIODICITY = {"periodic": 0, "open": 1, "single_wall": 2, "two_walls": 3}
+DTYPE = {torch.float32: 0, torch.float64: 1}
+
+
+class RpyError(RuntimeError):
+    """A non-OK status from librpy; ``status`` holds the code."""
+
+    def __init__(self, status: int, message: str):
+        self.status = Status(status)
+        super().__init__(f"{self.status.name}: {message}")
+
+
+class NotConvergedError(RpyError):
+    """Lanczos hit max_iter; ``result`` holds the last iterate written."""
+
+    def __init__(self, status, message, result=None, iters=0, increment=float("nan")):
+        super().__init__(status, message)
+        self.result = result
+        self.iters = iters
+        self.increment = increment
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """The loaded librpy; raises ImportError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"librpy.so not found at {LIB_PATH}; build it with "
+                          "`python -m paper_2510_02135_amd.build` or __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, d, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+    sig = {
+        "rpy_create": ([i, i, i, ctypes.POINTER(vp)], i),
+        "rpy_set_parameter": ([vp, ctypes.c_char_p, d], i),
+        "rpy_initialize": ([vp, d, d, i], i),
+        "rpy_set_positions": ([vp, vp, i64, i, vp], i),
+        "rpy_mdot": ([vp, vp, vp, vp, vp, vp], i),
+        "rpy_sqrt_mdot_w": ([vp, vp, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
+        "rpy_div_m": ([vp, vp, vp, vp], i),
+        "rpy_mdot_backward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i),
+        "rpy_enable_timing": ([vp, i], i),
+        "rpy_kernel_time": ([vp, i, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(d)], i),
+        "rpy_last_error": ([vp], ctypes.c_char_p),
+        "rpy_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _stream(t: torch.Tensor | None = None):
+    dev = t.device if t is not None else torch.device("cuda", torch.cuda.current_device())
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None, dtype: torch.dtype | None = None, numel: int | None = None,
+         name: str = "tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"DTYPE_MISMATCH: {name} is {t.dtype}, the solver works in {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(h, status: int):
+    if status != 0:
+        raise RpyError(status, load().rpy_last_error(h).decode() if h else "")
+
+
+def rpy_create(x: str = "open", y: str = "open", z: str = "open"):
+    lib = load()
+    out = ctypes.c_void_p()
+    try:
+        codes = [PERIODICITY[p] for p in (x, y, z)]
+    except KeyError as e:
+        raise ValueError(f"unknown periodicity {e.args[0]!r}; one of {sorted(PERIODICITY)}") from None
+    st = lib.rpy_create(*codes, ctypes.byref(out))
+    if st != 0:
+        raise RpyError(st, f"rpy_create({x}, {y}, {z})")
+    return out
+
+
+def rpy_set_parameter(h, key: str, value: float):
+    _check(h, load().rpy_set_parameter(h, key.encode(), float(value)))
+
+
+def rpy_initialize(h, viscosity: float, radius: float, include_angular: bool):
+    _check(h, load().rpy_initialize(h, float(viscosity), float(radius), int(bool(include_angular))))
+
+
+def rpy_set_positions(h, pos: torch.Tensor):
+    if pos.dtype not in DTYPE:
+        raise ValueError(f"DTYPE_MISMATCH: positions must be float32 or float64, got {pos.dtype}")
+    if pos.dim() != 2 or pos.shape[1] != 3:
+        raise ValueError("positions must have shape (N, 3)")
+    p = _ptr(pos, name="positions")
+    _check(h, load().rpy_set_positions(h, p, pos.shape[0], DTYPE[pos.dtype], _stream(pos)))
+
+
+def rpy_mdot(h, forces, torques, lin_out, ang_out, dtype, n):
+    _check(h, load().rpy_mdot(h, _ptr(forces, dtype, 3 * n, "forces"), _ptr(torques, dtype, 3 * n, "torques"),
+                              _ptr(lin_out, dtype, 3 * n, "lin_out"), _ptr(ang_out, dtype, 3 * n, "ang_out"),
+                              _stream(lin_out)))
+
+
+def rpy_sqrt_mdot_w(h, w, prefactor, tol, max_iter, lin_out, ang_out, dtype, n, angular):
+    iters = ctypes.c_int(0)
+    incr = ctypes.c_double(0.0)
+    st = load().rpy_sqrt_mdot_w(h, _ptr(w, dtype, (6 if angular else 3) * n, "W"), float(prefactor),
+                                float(tol), int(max_iter), _ptr(lin_out, dtype, 3 * n, "lin_out"),
+                                _ptr(ang_out, dtype, 3 * n, "ang_out"), ctypes.byref(iters),
+                                ctypes.byref(incr), _stream(lin_out))
+    if st == Status.NOT_CONVERGED:
+        raise NotConvergedError(st, load().rpy_last_error(h).decode(), (lin_out, ang_out),
+                                iters.value, incr.value)
+    _check(h, st)
+    return iters.value, incr.value
+
+
+def rpy_div_m(h, lin_out, ang_out, dtype, n):
+    _check(h, load().rpy_div_m(h, _ptr(lin_out, dtype, 3 * n, "lin_out"),
+                               _ptr(ang_out, dtype, 3 * n, "ang_out"), _stream(lin_out)))
+
+
+def rpy_mdot_backward(h, forces, torques, grad_lin, grad_ang, grad_pos, grad_forces, grad_torques, dtype, n):
+    ref = next(t for t in (grad_pos, grad_forces, grad_torques, grad_lin) if t is not None)
+    _check(h, load().rpy_mdot_backward(
+        h, _ptr(forces, dtype, 3 * n, "forces"), _ptr(torques, dtype, 3 * n, "torques"),
+        _ptr(grad_lin, dtype, 3 * n, "grad_lin"), _ptr(grad_ang, dtype, 3 * n, "grad_ang"),
+        _ptr(grad_pos, dtype, 3 * n, "grad_pos"), _ptr(grad_forces, dtype, 3 * n, "grad_forces"),
+        _ptr(grad_torques, dtype, 3 * n, "grad_torques"), _stream(ref)))
+
+
+def rpy_enable_timing(h, enable: bool = True):
+    _check(h, load().rpy_enable_timing(h, int(bool(enable))))
+
+
+KERNEL = {"pair": 0, "adjoint": 1}
+
+
+def rpy_kernel_time(h, kernel: str = "pair"):
+    """(total milliseconds, launches, pairs) recorded for a kernel class."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    pairs = ctypes.c_double(0.0)
+    _check(h, load().rpy_kernel_time(h, KERNEL[kernel], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(pairs)))
+    return ms.value, n.value, pairs.value
+
+
+def rpy_last_error(h) -> str:
+    return load().rpy_last_error(h).decode()
+
+
+def rpy_destroy(h):
+    if h:
+        load().rpy_destroy(h)

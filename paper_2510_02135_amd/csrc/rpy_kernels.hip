@@ -1,0 +1,393 @@
+// Pair kernels of the open-boundary RPY mobility product (gfx950).
+//
+// U = M(X) [F; T] summed over all ordered pairs, self pair included (the
+// N-body solver of Sec. 3.5, blocks of eq. (block_mobility) with the
+// generalised Rotne-Prager-Yamakawa tensors; the coefficient functions are
+// listed with PairConst in rpy_internal.hpp).
+//
+// Work decomposition
+//   grid.x : target blocks of 256*TM targets (TM targets per lane, strided
+//            by 256 so global loads/stores stay coalesced);
+//   grid.y : source splits, contiguous ranges of the source list.
+//   Each workgroup streams its source range through LDS in tiles of 256
+//   records (one coalesced 16 B (fp32) or 32 B (fp64) load per field per
+//   thread), then every lane walks the tile reading each record by LDS
+//   broadcast and updates its TM targets.  The overlap branch r < 2a, which
+//   also covers the self pair, sits behind a divergent `if` that the wave
+//   skips whenever none of its lanes has such a partner (the common case).
+// Precision
+//   fp32: in-tile plain float sums, folded into per-target (sum, comp)
+//         Neumaier pairs after every tile; the partial pairs of the splits
+//         are combined by the reduce kernel.
+//   fp64: plain double sums; 1/sqrt from the hardware estimate refined by
+//         two Newton steps.
+#include "rpy_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace rpy {
+
+constexpr int kBlock = 256;   // threads per workgroup of the pair kernel
+constexpr int kTile = 256;    // sources per LDS tile (one per thread)
+
+int targets_per_block(int tm) { return kBlock * tm; }
+int source_tile() { return kTile; }
+
+int choose_splits(int64_t n, int tm, bool fp64, bool ang) {
+    (void)fp64;
+    (void)ang;
+    const int64_t tblocks = (n + targets_per_block(tm) - 1) / targets_per_block(tm);
+    const int64_t max_split = std::max<int64_t>(1, (n + kTile - 1) / kTile);
+    const int64_t want = (2048 + tblocks - 1) / tblocks;   // ~8 workgroups per CU
+    return (int)std::max<int64_t>(1, std::min(want, max_split));
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+hipError_t DevBuf::ensure(size_t want) {
+    if (want <= bytes && p) return hipSuccess;
+    release();
+    size_t b = std::max<size_t>(want, 256);
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+        p = nullptr;
+        bytes = 0;
+        return e;
+    }
+    bytes = b;
+    return hipSuccess;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+// ---------------------------------------------------------------------------
+// device math
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// 1/sqrt(x) in double: hardware estimate, then two Newton steps
+// y <- y + y (1 - x y^2) / 2 (quadratic convergence to full precision).
+__device__ __forceinline__ double rsq(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double h = x * y;
+    double e = fma(-h, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    h = x * y;
+    e = fma(-h, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    return y;
+}
+
+// Neumaier's compensated addition of x into (s, c).
+__device__ __forceinline__ void neumaier(float &s, float &c, float x) {
+    const float t = s + x;
+    const float lost = (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+    c += lost;
+    s = t;
+}
+
+template <typename Real>
+__device__ __forceinline__ Real sel_pos(Real r2, Real v) { return r2 > Real(0) ? v : Real(0); }
+
+// One source record (position sp, force sf, torque st) acting on target
+// position (xi, yi, zi): adds its contribution to u (and w).
+template <typename Real, bool ANG>
+__device__ __forceinline__ void interact(Real xi, Real yi, Real zi, const vec4_t<Real> &sp,
+                                         const vec4_t<Real> &sf, const vec4_t<Real> &st,
+                                         const PairConst<Real> &c, Real *u, Real *w) {
+    const Real dx = xi - sp.x, dy = yi - sp.y, dz = zi - sp.z;
+    const Real r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const Real ri = rsq(r2);
+    const Real ri2 = ri * ri;
+    const Real ri3 = ri * ri2;
+    const Real ri5 = ri3 * ri2;
+    Real A = fma(c.two_a2_3, ri3, ri);
+    Real B = fma(c.m_two_a2, ri5, ri3);
+    Real G = ri3, D = Real(-0.5) * ri3, E = Real(1.5) * ri5;
+    if (__builtin_expect(r2 < c.four_a2, 0)) {
+        // overlap branch; at r = 0 (self pair) it gives the Stokes drag
+        const Real rs = sel_pos(r2, ri);
+        const Real r = r2 * rs;
+        A = fma(c.nA1, r, c.nA0);
+        B = c.nB * rs;
+        if constexpr (ANG) {
+            G = fma(c.nG1, r, c.nG0);
+            D = fma(fma(c.nD3, r * r, c.nD1), r, c.nD0);
+            E = fma(c.nE_1, rs, c.nE1 * r);
+        }
+    }
+    const Real dF = fma(dx, sf.x, fma(dy, sf.y, dz * sf.z));
+    const Real s = B * dF;
+    u[0] = fma(A, sf.x, fma(s, dx, u[0]));
+    u[1] = fma(A, sf.y, fma(s, dy, u[1]));
+    u[2] = fma(A, sf.z, fma(s, dz, u[2]));
+    if constexpr (ANG) {
+        // U += G (T x d)
+        const Real tx = st.y * dz - st.z * dy;
+        const Real ty = st.z * dx - st.x * dz;
+        const Real tz = st.x * dy - st.y * dx;
+        u[0] = fma(G, tx, u[0]);
+        u[1] = fma(G, ty, u[1]);
+        u[2] = fma(G, tz, u[2]);
+        // W += G (F x d) + D T + E (d.T) d
+        const Real fx = sf.y * dz - sf.z * dy;
+        const Real fy = sf.z * dx - sf.x * dz;
+        const Real fz = sf.x * dy - sf.y * dx;
+        const Real dT = fma(dx, st.x, fma(dy, st.y, dz * st.z));
+        const Real e = E * dT;
+        w[0] = fma(G, fx, fma(D, st.x, fma(e, dx, w[0])));
+        w[1] = fma(G, fy, fma(D, st.y, fma(e, dy, w[1])));
+        w[2] = fma(G, fz, fma(D, st.z, fma(e, dz, w[2])));
+    }
+}
+
+template <typename Real, bool ANG, int TM>
+__global__ void __launch_bounds__(kBlock)
+pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__restrict__ frc,
+            const vec4_t<Real> *__restrict__ trq, int n, int split_len, PairConst<Real> c,
+            Real *__restrict__ part) {
+    using R4 = vec4_t<Real>;
+    constexpr int NC = ANG ? 6 : 3;                       // output components
+    constexpr bool COMP = std::is_same<Real, float>::value;  // compensated sums
+    __shared__ R4 sp[kTile];
+    __shared__ R4 sf[kTile];
+    __shared__ R4 st[ANG ? kTile : 1];
+
+    const int tid = threadIdx.x;
+    const int tbase = blockIdx.x * (kBlock * TM);
+    Real xi[TM], yi[TM], zi[TM];
+    Real acc[TM][NC];
+    Real sum[TM][COMP ? NC : 1], cmp[TM][COMP ? NC : 1];
+#pragma unroll
+    for (int m = 0; m < TM; ++m) {
+        const int idx = min(tbase + m * kBlock + tid, n - 1);
+        const R4 p = pos[idx];
+        xi[m] = p.x;
+        yi[m] = p.y;
+        zi[m] = p.z;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[m][k] = Real(0);
+        if constexpr (COMP) {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                sum[m][k] = Real(0);
+                cmp[m][k] = Real(0);
+            }
+        }
+    }
+
+    const int s_begin = blockIdx.y * split_len;
+    const int s_end = min(n, s_begin + split_len);
+    const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+    for (int t0 = s_begin; t0 < s_end; t0 += kTile) {
+        const int j = t0 + tid;
+        if (j < s_end) {
+            sp[tid] = pos[j];
+            sf[tid] = frc[j];
+            if constexpr (ANG) st[tid] = trq[j];
+        }
+        __syncthreads();
+        const int cnt = min(kTile, s_end - t0);
+#pragma unroll 2
+        for (int q = 0; q < cnt; ++q) {
+            const R4 a = sp[q];
+            const R4 b = sf[q];
+            R4 d = zero4;
+            if constexpr (ANG) d = st[q];
+#pragma unroll
+            for (int m = 0; m < TM; ++m)
+                interact<Real, ANG>(xi[m], yi[m], zi[m], a, b, d, c, acc[m], acc[m] + 3);
+        }
+        __syncthreads();
+        if constexpr (COMP) {
+#pragma unroll
+            for (int m = 0; m < TM; ++m)
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    neumaier(sum[m][k], cmp[m][k], acc[m][k]);
+                    acc[m][k] = Real(0);
+                }
+        }
+    }
+
+    // partial outputs of this split: [split][component][n]
+    const size_t nn = (size_t)n;
+    Real *base = part + (size_t)blockIdx.y * (COMP ? 2 * NC : NC) * nn;
+#pragma unroll
+    for (int m = 0; m < TM; ++m) {
+        const int idx = tbase + m * kBlock + tid;
+        if (idx < n) {
+#pragma unroll
+            for (int k = 0; k < NC; ++k) {
+                if constexpr (COMP) {
+                    base[(size_t)k * nn + idx] = sum[m][k];
+                    base[(size_t)(NC + k) * nn + idx] = cmp[m][k];
+                } else {
+                    base[(size_t)k * nn + idx] = acc[m][k];
+                }
+            }
+        }
+    }
+}
+
+template <typename Real, bool ANG>
+hipError_t launch_pair(const vec4_t<Real> *pos, const vec4_t<Real> *f, const vec4_t<Real> *t,
+                       int64_t n, const PairConst<Real> &pc, const TileConfig &cfg, int n_split,
+                       Real *part, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int tm = cfg.tm == 1 ? 1 : 2;
+    const int64_t tpb = targets_per_block(tm);
+    int64_t split_len = (n + n_split - 1) / n_split;
+    split_len = (split_len + kTile - 1) / kTile * kTile;
+    dim3 grid((unsigned)((n + tpb - 1) / tpb), (unsigned)n_split);
+    if (tm == 1)
+        hipLaunchKernelGGL((pair_kernel<Real, ANG, 1>), grid, dim3(kBlock), 0, st, pos, f, t, (int)n,
+                           (int)split_len, pc, part);
+    else
+        hipLaunchKernelGGL((pair_kernel<Real, ANG, 2>), grid, dim3(kBlock), 0, st, pos, f, t, (int)n,
+                           (int)split_len, pc, part);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// reduction over source splits + epilogue (x k, AoS store)
+// ---------------------------------------------------------------------------
+template <typename Real, typename Tout, bool ANG>
+__global__ void reduce_kernel(const Real *__restrict__ part, int n_split, int n, double k,
+                              Tout *__restrict__ lin, Tout *__restrict__ ang) {
+    constexpr int NC = ANG ? 6 : 3;
+    constexpr bool COMP = std::is_same<Real, float>::value;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const size_t nn = (size_t)n;
+    const size_t stride = (size_t)(COMP ? 2 * NC : NC) * nn;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        Tout v;
+        if constexpr (COMP) {
+            float s = 0.f, cp = 0.f, extra = 0.f;
+            for (int q = 0; q < n_split; ++q) {
+                neumaier(s, cp, (float)part[q * stride + (size_t)c * nn + i]);
+                extra += (float)part[q * stride + (size_t)(NC + c) * nn + i];
+            }
+            // combine in double, then round once to the output type
+            v = (Tout)(k * ((double)s + ((double)cp + (double)extra)));
+        } else {
+            double s = 0.0;
+            for (int q = 0; q < n_split; ++q) s += (double)part[q * stride + (size_t)c * nn + i];
+            v = (Tout)(k * s);
+        }
+        if (c < 3)
+            lin[3 * (size_t)i + c] = v;
+        else if (ang)
+            ang[3 * (size_t)i + (c - 3)] = v;
+    }
+}
+
+template <typename Real, typename Tout, bool ANG>
+hipError_t launch_reduce(const Real *part, int n_split, int64_t n, double k, Tout *lin, Tout *ang,
+                         hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL((reduce_kernel<Real, Tout, ANG>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       st, part, n_split, (int)n, k, lin, ang);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// staging
+// ---------------------------------------------------------------------------
+template <typename Tin, typename Real>
+__global__ void stage_positions_kernel(const Tin *__restrict__ in, int n, vec4_t<Real> *__restrict__ out,
+                                       unsigned *__restrict__ nonfinite) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Tin x = in[3 * (size_t)i], y = in[3 * (size_t)i + 1], z = in[3 * (size_t)i + 2];
+    if (!(isfinite((double)x) && isfinite((double)y) && isfinite((double)z))) atomicAdd(nonfinite, 1u);
+    vec4_t<Real> v;
+    v.x = (Real)x;
+    v.y = (Real)y;
+    v.z = (Real)z;
+    v.w = Real(0);
+    out[i] = v;
+}
+
+template <typename Tin, typename Real>
+__global__ void stage_vec_kernel(const Tin *__restrict__ in, int n, vec4_t<Real> *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    vec4_t<Real> v;
+    if (in) {
+        v.x = (Real)in[3 * (size_t)i];
+        v.y = (Real)in[3 * (size_t)i + 1];
+        v.z = (Real)in[3 * (size_t)i + 2];
+    } else {
+        v.x = v.y = v.z = Real(0);
+    }
+    v.w = Real(0);
+    out[i] = v;
+}
+
+template <typename Tin, typename Real>
+hipError_t launch_stage_positions(const Tin *pos, int64_t n, vec4_t<Real> *out, unsigned *nonfinite,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL((stage_positions_kernel<Tin, Real>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       st, pos, (int)n, out, nonfinite);
+    return hipGetLastError();
+}
+
+template <typename Tin, typename Real>
+hipError_t launch_stage_vec(const Tin *v, int64_t n, vec4_t<Real> *out, hipStream_t st) {
+    hipLaunchKernelGGL((stage_vec_kernel<Tin, Real>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       v, (int)n, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void fill_zero_kernel(T *p, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = T(0);
+}
+
+template <typename T>
+hipError_t launch_fill_zero(T *p, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL((fill_zero_kernel<T>), dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p,
+                       count);
+    return hipGetLastError();
+}
+
+// explicit instantiations
+template hipError_t launch_stage_positions<float, float>(const float *, int64_t, float4 *, unsigned *, hipStream_t);
+template hipError_t launch_stage_positions<double, double>(const double *, int64_t, double4 *, unsigned *, hipStream_t);
+template hipError_t launch_stage_vec<float, float>(const float *, int64_t, float4 *, hipStream_t);
+template hipError_t launch_stage_vec<double, double>(const double *, int64_t, double4 *, hipStream_t);
+template hipError_t launch_stage_vec<double, float>(const double *, int64_t, float4 *, hipStream_t);
+template hipError_t launch_pair<float, false>(const float4 *, const float4 *, const float4 *, int64_t,
+                                              const PairConst<float> &, const TileConfig &, int, float *,
+                                              hipStream_t);
+template hipError_t launch_pair<float, true>(const float4 *, const float4 *, const float4 *, int64_t,
+                                             const PairConst<float> &, const TileConfig &, int, float *,
+                                             hipStream_t);
+template hipError_t launch_pair<double, false>(const double4 *, const double4 *, const double4 *, int64_t,
+                                               const PairConst<double> &, const TileConfig &, int, double *,
+                                               hipStream_t);
+template hipError_t launch_pair<double, true>(const double4 *, const double4 *, const double4 *, int64_t,
+                                              const PairConst<double> &, const TileConfig &, int, double *,
+                                              hipStream_t);
+template hipError_t launch_reduce<float, float, false>(const float *, int, int64_t, double, float *, float *, hipStream_t);
+template hipError_t launch_reduce<float, float, true>(const float *, int, int64_t, double, float *, float *, hipStream_t);
+template hipError_t launch_reduce<float, double, false>(const float *, int, int64_t, double, double *, double *, hipStream_t);
+template hipError_t launch_reduce<float, double, true>(const float *, int, int64_t, double, double *, double *, hipStream_t);
+template hipError_t launch_reduce<double, double, false>(const double *, int, int64_t, double, double *, double *, hipStream_t);
+template hipError_t launch_reduce<double, double, true>(const double *, int, int64_t, double, double *, double *, hipStream_t);
+template hipError_t launch_fill_zero<float>(float *, int64_t, hipStream_t);
+template hipError_t launch_fill_zero<double>(double *, int64_t, hipStream_t);
+template hipError_t launch_fill_zero<unsigned>(unsigned *, int64_t, hipStream_t);
+
+}  // namespace rpy

@@ -1,0 +1,33 @@
+// Host-side helpers shared by the C interface translation units.
+#pragma once
+
+#include <string>
+
+#include "rpy_internal.hpp"
+
+namespace rpy {
+
+rpy_status fail(rpy_solver *s, rpy_status code, const std::string &msg);
+rpy_status hip_fail(rpy_solver *s, hipError_t e, const char *what);
+rpy_status check_ready(rpy_solver *s);
+rpy_status ensure_vec_buffers(rpy_solver *s, bool ang);
+double k_factor(const rpy_solver *s);
+int splits_for(const rpy_solver *s, bool ang);
+
+// Launch timing: returns the event to record before (after) a launch of
+// kernel class `kind`, or nullptr when timing is off.
+hipEvent_t timing_begin(rpy_solver *s, int kind, double pairs);
+hipEvent_t timing_end(rpy_solver *s, int kind);
+
+// M [F; T] with F (and T) already staged in s->f (s->t); Real is the pair
+// precision, Tout the output element type.  ang_out may be NULL.
+template <typename Real, typename Tout>
+rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *ang_out, hipStream_t st);
+
+}  // namespace rpy
+
+#define HIP_TRY(s, expr)                                                   \
+    do {                                                                   \
+        hipError_t e_ = (expr);                                            \
+        if (e_ != hipSuccess) return ::rpy::hip_fail((s), e_, #expr);      \
+    } while (0)

@@ -1,0 +1,162 @@
+"""Python front-end with the paper's solver interface (Sec. 3.2).
+
+``Solver`` mirrors the libMobility solver classes: constructor with per-axis
+periodicity, ``setParameters``, ``initialize``, ``setPositions``, ``Mdot``,
+``sqrtMdotW`` and ``divM``, each returning (linear, angular).  Only torch
+device tensors are accepted; results are new tensors of the input dtype on
+the same device.  ``mdot`` is the differentiable form: a
+``torch.autograd.Function`` whose backward calls the library's adjoint.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+
+
+class Solver:
+    """Open-boundary RPY N-body mobility solver on one HIP device."""
+
+    def __init__(self, periodicityX: str = "open", periodicityY: str = "open",
+                 periodicityZ: str = "open"):
+        self._h = _lib.rpy_create(periodicityX, periodicityY, periodicityZ)
+        self._n = 0
+        self._dtype = None
+        self._device = None
+        self._angular = False
+        self.viscosity = None
+        self.hydrodynamicRadius = None
+        self.last_iterations = 0
+        self.last_increment = float("nan")
+
+    # -- configuration -----------------------------------------------------
+    def setParameters(self, **params):
+        for k, v in params.items():
+            _lib.rpy_set_parameter(self._h, k, v)
+
+    def initialize(self, viscosity: float, hydrodynamicRadius: float, includeAngular: bool = False):
+        _lib.rpy_initialize(self._h, viscosity, hydrodynamicRadius, includeAngular)
+        self.viscosity = float(viscosity)
+        self.hydrodynamicRadius = float(hydrodynamicRadius)
+        self._angular = bool(includeAngular)
+
+    def setPositions(self, positions: torch.Tensor):
+        pos = positions.reshape(-1, 3)
+        _lib.rpy_set_positions(self._h, pos)
+        self._n = pos.shape[0]
+        self._dtype = pos.dtype
+        self._device = pos.device
+
+    @property
+    def n(self) -> int:
+        return self._n
+
+    @property
+    def dtype(self):
+        return self._dtype
+
+    @property
+    def includeAngular(self) -> bool:
+        return self._angular
+
+    def _empty(self):
+        return torch.empty((self._n, 3), dtype=self._dtype, device=self._device)
+
+    def _as(self, t, name):
+        if t is None:
+            return None
+        t = t.reshape(-1, 3)
+        if t.dtype != self._dtype:
+            raise ValueError(f"DTYPE_MISMATCH: {name} is {t.dtype}, positions are {self._dtype}")
+        return t.contiguous()
+
+    # -- the three terms of eq. (bdhi) --------------------------------------
+    def Mdot(self, forces: torch.Tensor | None = None, torques: torch.Tensor | None = None):
+        """(M_uF F + M_uT T, M_wF F + M_wT T or None)."""
+        f, t = self._as(forces, "forces"), self._as(torques, "torques")
+        lin = self._empty()
+        ang = self._empty() if (self._angular and (t is not None or f is not None)) else None
+        _lib.rpy_mdot(self._h, f, t, lin, ang, self._dtype, self._n)
+        return lin, ang
+
+    def sqrtMdotW(self, W: torch.Tensor | None = None, prefactor: float = 1.0,
+                  tol: float = 1e-6, maxIter: int = 500, generator: torch.Generator | None = None):
+        """prefactor * M^{1/2} W by Lanczos; W ~ N(0, I) is drawn when not given."""
+        dim = (6 if self._angular else 3) * self._n
+        if W is None:
+            W = torch.randn(dim, dtype=self._dtype, device=self._device, generator=generator)
+        w = W.reshape(-1)
+        if w.dtype != self._dtype:
+            raise ValueError(f"DTYPE_MISMATCH: W is {w.dtype}, positions are {self._dtype}")
+        w = w.contiguous()
+        lin = self._empty()
+        ang = self._empty() if self._angular else None
+        it, inc = _lib.rpy_sqrt_mdot_w(self._h, w, prefactor, tol, maxIter, lin, ang, self._dtype,
+                                       self._n, self._angular)
+        self.last_iterations, self.last_increment = it, inc
+        return lin, ang
+
+    def divM(self):
+        """Thermal drift: zero in an unbounded fluid."""
+        lin = self._empty()
+        ang = self._empty() if self._angular else None
+        _lib.rpy_div_m(self._h, lin, ang, self._dtype, self._n)
+        return lin, ang
+
+    def Mdot_backward(self, forces, torques, grad_lin, grad_ang=None, need_pos=True,
+                      need_forces=True, need_torques=True):
+        """(dL/dX, dL/dF, dL/dT) for cotangents of the Mdot outputs."""
+        f, t = self._as(forces, "forces"), self._as(torques, "torques")
+        gl, ga = self._as(grad_lin, "grad_lin"), self._as(grad_ang, "grad_ang")
+        gp = self._empty() if need_pos else None
+        gf = self._empty() if need_forces else None
+        gt = self._empty() if (need_torques and self._angular) else None
+        _lib.rpy_mdot_backward(self._h, f, t, gl, ga, gp, gf, gt, self._dtype, self._n)
+        return gp, gf, gt
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rpy_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _MdotFunction(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, solver, positions, forces, torques):
+        solver.setPositions(positions.detach())
+        lin, ang = solver.Mdot(forces.detach() if forces is not None else None,
+                               torques.detach() if torques is not None else None)
+        ctx.solver = solver
+        ctx.save_for_backward(positions, forces, torques)
+        ctx.has_t = torques is not None
+        if ang is None:
+            ang = torch.zeros_like(lin)
+        return lin, ang
+
+    @staticmethod
+    def backward(ctx, g_lin, g_ang):
+        solver = ctx.solver
+        positions, forces, torques = ctx.saved_tensors
+        solver.setPositions(positions.detach())
+        g_ang = g_ang if (solver.includeAngular and g_ang is not None) else None
+        gl = g_lin.contiguous() if g_lin is not None else torch.zeros_like(positions)
+        gp, gf, gt = solver.Mdot_backward(forces, torques, gl, g_ang,
+                                          need_pos=ctx.needs_input_grad[1],
+                                          need_forces=ctx.needs_input_grad[2],
+                                          need_torques=ctx.needs_input_grad[3] and ctx.has_t)
+        return None, gp, (gf if forces is not None else None), (gt if ctx.has_t else None)
+
+
+def mdot(solver: Solver, positions: torch.Tensor, forces: torch.Tensor | None,
+         torques: torch.Tensor | None = None):
+    """Differentiable (U, Omega) = M(X) [F; T]; gradients flow to X, F and T."""
+    if forces is None and torques is None:
+        raise ValueError("need forces or torques")
+    lin, ang = _MdotFunction.apply(solver, positions, forces, torques)
+    return lin, (ang if solver.includeAngular else None)

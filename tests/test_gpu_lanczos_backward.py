@@ -1,0 +1,197 @@
+"""GPU parity of sqrtMdotW (Lanczos, Sec. 3.3) and of the adjoint against the
+float64 oracle, through the C interface.
+
+* sqrtMdotW: against the oracle's Lanczos run for the same number of
+  iterations (matched-iteration parity), and against the exact symmetric
+  root at tol 1e-6; FDT check (eq. (fdt), Sec. 4) by a KS test.
+* backward: against the oracle's analytic adjoint (itself pinned by complex
+  steps) and, at N = 16,384 / phi = 0.2, against central finite differences
+  of the loss 0.5 |M(X) F - U*|^2 on 64 position coordinates.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.stats
+import torch
+
+import workloads
+from oracle import gradient, lanczos, mobility, pairloop
+from tests.gpu_util import emax, host, rounded, say, to_dev, tol_for
+
+pytestmark = pytest.mark.gpu
+DTYPES = [torch.float64, torch.float32]
+
+
+def _solver(angular, a=1.0, eta=1 / (6 * math.pi)):
+    import paper_2510_02135_amd as rpy
+    s = rpy.Solver("open", "open", "open")
+    s.initialize(viscosity=eta, hydrodynamicRadius=a, includeAngular=angular)
+    return s
+
+
+def _flat(lin, ang):
+    parts = [host(lin).reshape(-1)]
+    if ang is not None:
+        parts.append(host(ang).reshape(-1))
+    return np.concatenate(parts)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("angular", [False, True])
+@pytest.mark.parametrize("n", [1, 7, 130, 600])
+def test_lanczos_matched_iterations(dtype, angular, n):
+    say(f"case lanczos n={n} angular={angular} {dtype}")
+    s = workloads.uniform_cube(n, 0.15, 200 + n, w=True, angular_w=angular)
+    a, eta = s.radius, s.viscosity
+    sol = _solver(angular)
+    sol.setPositions(to_dev(s.pos, dtype))
+    lin, ang = sol.sqrtMdotW(to_dev(s.w, dtype), prefactor=0.5, tol=1e-6)
+    k = sol.last_iterations
+    say(f"  iterations {k}, increment {sol.last_increment:.2e}")
+    xr, wr = rounded(s.pos, dtype), rounded(s.w, dtype)
+    m = mobility.grand_mobility(xr, a, eta, angular)
+    y_ref, info = lanczos.lanczos_sqrt(lambda v: m @ v, wr, iters=k, prefactor=0.5)
+    y = _flat(lin, ang)
+    e = float(np.abs(y - y_ref).max() / np.abs(y_ref).max())
+    say(f"  matched-iteration max rel {e:.3e}")
+    assert e <= (1e-12 if dtype == torch.float64 else 1e-5)
+    exact = lanczos.exact_sqrt_mdot_w(m, wr, 0.5)
+    e2 = float(np.linalg.norm(y - exact) / np.linalg.norm(exact))
+    say(f"  vs exact symmetric root {e2:.3e}")
+    assert e2 <= 1e-5
+
+
+def test_lanczos_zero_noise_and_not_converged():
+    import paper_2510_02135_amd as rpy
+    say("case lanczos edge cases")
+    s = workloads.uniform_cube(200, 0.2, 9, w=True)
+    sol = _solver(False)
+    sol.setPositions(to_dev(s.pos, torch.float64))
+    lin, _ = sol.sqrtMdotW(torch.zeros(600, dtype=torch.float64, device="cuda"))
+    assert not lin.any()
+    with pytest.raises(rpy.NotConvergedError) as ei:
+        sol.sqrtMdotW(to_dev(s.w, torch.float64), tol=1e-12, maxIter=3)
+    assert ei.value.iters == 3
+    bad = to_dev(s.w, torch.float64)
+    bad[5] = float("nan")
+    with pytest.raises(rpy.RpyError):
+        sol.sqrtMdotW(bad)
+
+
+def test_fluctuation_dissipation_ks():
+    say("case FDT KS")
+    n = 10
+    s = workloads.uniform_cube(n, 0.2, 31)
+    a, eta = s.radius, s.viscosity
+    sol = _solver(True)
+    sol.setPositions(to_dev(s.pos, torch.float64))
+    m = mobility.grand_mobility(s.pos, a, eta, True)
+    inv_sqrt = lanczos.exact_inv_sqrt(m)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    zs = []
+    for _ in range(300):
+        lin, ang = sol.sqrtMdotW(tol=1e-8, generator=g)
+        zs.append(inv_sqrt @ _flat(lin, ang))
+    z = np.concatenate(zs)
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-3
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("angular", [False, True])
+@pytest.mark.parametrize("n", [2, 40, 257, 700])
+def test_backward_against_oracle_adjoint(dtype, angular, n):
+    say(f"case backward n={n} angular={angular} {dtype}")
+    rng = np.random.default_rng(300 + n)
+    x = (rng.random((n, 3)) - 0.5) * workloads.cube_side(n, 0.25)
+    F, gu = rng.standard_normal((2, n, 3))
+    T, gw = (rng.standard_normal((2, n, 3)) if angular else (None, None))
+    a, eta = 1.1, 0.8
+    sol = _solver(angular, a, eta)
+    sol.setPositions(to_dev(x, dtype))
+    gp, gf, gt = sol.Mdot_backward(to_dev(F, dtype), to_dev(T, dtype), to_dev(gu, dtype), to_dev(gw, dtype))
+    r = lambda v: rounded(v, dtype)
+    dx, df, dt = gradient.mdot_vjp(r(x), r(F), r(T), r(gu), r(gw), a, eta)
+    e = max(emax(host(gp), dx), emax(host(gf), df))
+    if angular:
+        e = max(e, emax(host(gt), dt))
+    say(f"  e_max {e:.3e}")
+    assert e <= tol_for(dtype)
+
+
+def test_backward_coincident_particles_contribute_nothing():
+    say("case backward coincident")
+    x = np.array([[0.0, 0, 0], [0.0, 0, 0], [1.5, 0, 0], [5.0, 1, 0]])
+    rng = np.random.default_rng(2)
+    F, T, gu, gw = rng.standard_normal((4, 4, 3))
+    sol = _solver(True)
+    sol.setPositions(to_dev(x, torch.float64))
+    gp, gf, gt = sol.Mdot_backward(*(to_dev(v, torch.float64) for v in (F, T, gu, gw)))
+    dx, df, dt = gradient.mdot_vjp(x, F, T, gu, gw, 1.0, 1 / (6 * math.pi))
+    assert emax(host(gp), dx) <= 1e-12 and emax(host(gf), df) <= 1e-12 and emax(host(gt), dt) <= 1e-12
+
+
+def test_autograd_function_and_gradcheck():
+    import paper_2510_02135_amd as rpy
+    say("case autograd gradcheck")
+    rng = np.random.default_rng(8)
+    n = 12
+    x = torch.tensor((rng.random((n, 3)) - 0.5) * 6, dtype=torch.float64, device="cuda", requires_grad=True)
+    F = torch.tensor(rng.standard_normal((n, 3)), dtype=torch.float64, device="cuda", requires_grad=True)
+    T = torch.tensor(rng.standard_normal((n, 3)), dtype=torch.float64, device="cuda", requires_grad=True)
+    sol = _solver(True)
+    fn = lambda xx, ff, tt: rpy.mdot(sol, xx, ff, tt)
+    assert torch.autograd.gradcheck(fn, (x, F, T), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def test_c3_gradient_against_central_differences():
+    """N = 16,384, phi = 0.2: float32 adjoint vs float64 central differences
+    (h = 1e-4) of L = 0.5 |M(X) F - U*|^2 on 64 position coordinates, and
+    dL/dF against the oracle's M g on 64 force coordinates."""
+    s = workloads.c3_gradient()
+    a, eta = s.radius, s.viscosity
+    say(f"case c3 N={s.n}")
+    sol32 = _solver(False)
+    sol64 = _solver(False)
+    x32 = rounded(s.pos, torch.float32)
+    f32 = rounded(s.forces, torch.float32)
+    # U* and g on the device, float64 (U* from the perturbed configuration)
+    sol64.setPositions(to_dev(x32 + s.extra["delta"], torch.float64))
+    ustar, _ = sol64.Mdot(forces=to_dev(f32, torch.float64))
+    sol64.setPositions(to_dev(x32, torch.float64))
+    u, _ = sol64.Mdot(forces=to_dev(f32, torch.float64))
+    g = (u - ustar)
+    sol32.setPositions(to_dev(x32, torch.float32))
+    gp, gf, _ = sol32.Mdot_backward(to_dev(f32, torch.float32), None, g.float())
+    gp64, gf64, _ = sol64.Mdot_backward(to_dev(f32, torch.float64), None, g)
+    h = 1e-4
+    coords = s.extra["fd_pos"]
+    fd = []
+    for c in coords:
+        p, ax = divmod(int(c), 3)
+        vals = []
+        for sgn in (1, -1):
+            xp = x32.copy()
+            xp[p, ax] += sgn * h
+            sol64.setPositions(to_dev(xp, torch.float64))
+            up, _ = sol64.Mdot(forces=to_dev(f32, torch.float64))
+            vals.append(0.5 * float(((up - ustar) ** 2).sum()))
+        fd.append((vals[0] - vals[1]) / (2 * h))
+    fd = np.array(fd)
+    ad32 = host(gp).reshape(-1)[coords]
+    ad64 = host(gp64).reshape(-1)[coords]
+    scale = np.abs(fd).max()
+    say(f"  fd vs adjoint64 {np.abs(fd - ad64).max() / scale:.2e}, vs adjoint32 {np.abs(fd - ad32).max() / scale:.2e}")
+    assert np.abs(fd - ad64).max() <= 1e-5 * scale
+    assert np.abs(fd - ad32).max() <= 1e-4 * scale
+    # dL/dF = M g on sampled rows through the oracle
+    rows = np.unique(s.extra["fd_force"] // 3)
+    mg, _ = pairloop.mdot_rows(x32, rows, host(g), None, a, eta)
+    e = emax(host(gf)[rows], mg)
+    say(f"  dL/dF rows e_max fp32 {e:.2e}")
+    assert e <= 1e-5
+    gx_rows = gradient.grad_positions(x32, f32, None, host(g), None, a, eta, rows=rows[:16])
+    e = emax(host(gp64)[rows[:16]], gx_rows)
+    say(f"  dL/dX rows vs oracle adjoint fp64 {e:.2e}")
+    assert e <= 1e-12

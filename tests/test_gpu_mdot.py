@@ -1,0 +1,153 @@
+"""GPU parity of Mdot and divM against the float64 oracle (through the C
+interface).  float32 runs are compared with the oracle evaluated on the same
+float32-rounded inputs; bars: 1e-12 (float64) and 1e-5 (float32) in
+e_max = max_i |dU_i| / max_i |U_ref,i|."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import mobility, pairloop
+from tests.gpu_util import emax, host, rounded, say, to_dev, tol_for
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float64, torch.float32]
+
+
+def _solver(angular, a=1.0, eta=1 / (6 * math.pi)):
+    import paper_2510_02135_amd as rpy
+    s = rpy.Solver("open", "open", "open")
+    s.initialize(viscosity=eta, hydrodynamicRadius=a, includeAngular=angular)
+    return s
+
+
+def _check(sol, x, F, T, dtype, a, eta, want_ang):
+    xr, Fr = rounded(x, dtype), rounded(F, dtype)
+    Tr = rounded(T, dtype) if T is not None else (np.zeros_like(xr) if want_ang else None)
+    sol.setPositions(to_dev(x, dtype))
+    lin, ang = sol.Mdot(forces=to_dev(F, dtype), torques=to_dev(T, dtype))
+    torch.cuda.synchronize()
+    u_ref, w_ref = mobility.mdot_dense(xr, Fr, Tr, a, eta)
+    e = emax(host(lin), u_ref)
+    if want_ang:
+        e = max(e, emax(host(ang), w_ref))
+    return e
+
+
+def test_c1_float64_translational():
+    s = workloads.c1_small_fp64()
+    say("case c1 N=1024 fp64 linear")
+    sol = _solver(False)
+    e = _check(sol, s.pos, s.forces, None, torch.float64, s.radius, s.viscosity, False)
+    say(f"  e_max {e:.3e}")
+    assert e <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("angular", [False, True])
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 255, 256, 257, 511, 700, 1100])
+def test_small_sizes_and_ragged_tails(dtype, angular, n):
+    say(f"case random n={n} angular={angular} {dtype}")
+    rng = np.random.default_rng(100 + n)
+    side = workloads.cube_side(n, 0.15)
+    x = (rng.random((n, 3)) - 0.5) * side
+    F = rng.standard_normal((n, 3))
+    T = rng.standard_normal((n, 3)) if angular else None
+    a, eta = 1.3, 0.9
+    sol = _solver(angular, a, eta)
+    e = _check(sol, x, F, T, dtype, a, eta, angular)
+    say(f"  e_max {e:.3e}")
+    assert e <= tol_for(dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_torque_only_and_force_only_with_angular_output(dtype):
+    say(f"case torque-only / force-only {dtype}")
+    rng = np.random.default_rng(5)
+    n = 300
+    x = (rng.random((n, 3)) - 0.5) * 12
+    F = rng.standard_normal((n, 3))
+    T = rng.standard_normal((n, 3))
+    sol = _solver(True)
+    a, eta = 1.0, 1 / (6 * math.pi)
+    xr = rounded(x, dtype)
+    sol.setPositions(to_dev(x, dtype))
+    lin, ang = sol.Mdot(torques=to_dev(T, dtype))
+    u, w = mobility.mdot_dense(xr, None, rounded(T, dtype), a, eta)
+    assert max(emax(host(lin), u), emax(host(ang), w)) <= tol_for(dtype)
+    lin, ang = sol.Mdot(forces=to_dev(F, dtype))
+    u, w = mobility.mdot_dense(xr, rounded(F, dtype), np.zeros_like(xr), a, eta)
+    assert max(emax(host(lin), u), emax(host(ang), w)) <= tol_for(dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_degenerate_geometries(dtype):
+    """Coincident particles, pairs exactly at contact and 1 ulp either side,
+    and a pair far apart (self-mobility limit)."""
+    say(f"case degenerate geometries {dtype}")
+    a, eta = 1.0, 1 / (6 * math.pi)
+    np_t = np.float32 if dtype == torch.float32 else np.float64
+    two = np_t(2.0)
+    x = np.array([[0, 0, 0], [0, 0, 0],                                   # coincident
+                  [0, 20, 0], [float(two), 20, 0],                        # exactly 2a
+                  [0, 40, 0], [float(np.nextafter(two, np_t(0))), 40, 0],  # 1 ulp inside
+                  [0, 60, 0], [float(np.nextafter(two, np_t(9))), 60, 0],  # 1 ulp outside
+                  [1e5, 0, 0], [-1e5, 3, 4]], dtype=np.float64)
+    rng = np.random.default_rng(6)
+    F = rng.standard_normal(x.shape)
+    T = rng.standard_normal(x.shape)
+    sol = _solver(True, a, eta)
+    e = _check(sol, x, F, T, dtype, a, eta, True)
+    say(f"  e_max {e:.3e}")
+    assert e <= tol_for(dtype)
+
+
+def test_div_m_is_zero_and_outputs_are_overwritten():
+    say("case divM")
+    sol = _solver(True)
+    x = np.random.default_rng(1).random((50, 3)) * 5
+    sol.setPositions(to_dev(x, torch.float32))
+    lin, ang = sol.divM()
+    assert not lin.any() and not ang.any() and lin.shape == (50, 3)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_repeated_calls_are_bitwise_deterministic(dtype):
+    say(f"case determinism {dtype}")
+    s = workloads.uniform_cube(3000, 0.1, 77, torques=True)
+    sol = _solver(True)
+    sol.setPositions(to_dev(s.pos, dtype))
+    F, T = to_dev(s.forces, dtype), to_dev(s.torques, dtype)
+    a1, b1 = sol.Mdot(F, T)
+    a2, b2 = sol.Mdot(F, T)
+    assert torch.equal(a1, a2) and torch.equal(b1, b2)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_c2_full_size_sampled_rows(dtype):
+    """N = 65,536 at volume fraction 0.1 in the launch configuration the
+    benchmark uses; the oracle evaluates 512 sampled target rows."""
+    s = workloads.c2_suspension()
+    rows = s.extra["subset"][::8]
+    say(f"case c2 N={s.n} {dtype} rows={len(rows)}")
+    sol = _solver(True)
+    sol.setPositions(to_dev(s.pos, dtype))
+    for torques in (None, s.torques):
+        lin, ang = sol.Mdot(forces=to_dev(s.forces, dtype), torques=to_dev(torques, dtype))
+        xr, Fr = rounded(s.pos, dtype), rounded(s.forces, dtype)
+        Tr = rounded(torques, dtype) if torques is not None else np.zeros_like(xr)
+        u, w = pairloop.mdot_rows(xr, rows, Fr, Tr, s.radius, s.viscosity)
+        e = max(emax(host(lin)[rows], u), emax(host(ang)[rows], w))
+        say(f"  torques={torques is not None} e_max {e:.3e}")
+        assert e <= tol_for(dtype)
+    # translational-only solver, as timed by the benchmark
+    sol2 = _solver(False)
+    sol2.setPositions(to_dev(s.pos, dtype))
+    lin, _ = sol2.Mdot(forces=to_dev(s.forces, dtype))
+    u, _ = pairloop.mdot_rows(rounded(s.pos, dtype), rows, rounded(s.forces, dtype), None, s.radius, s.viscosity)
+    e = emax(host(lin)[rows], u)
+    say(f"  linear-only e_max {e:.3e}")
+    assert e <= tol_for(dtype)
