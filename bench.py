@@ -49,6 +49,9 @@ def parse():
     p.add_argument("--n", type=int, default=65536, help="particles (default: the 65,536 workload)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
+    p.add_argument("--no-breakdown", action="store_true", help="skip the per-precision breakdown and oracle check")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return p.parse_args()
 
 
@@ -57,6 +60,30 @@ def emax(got, ref):
     got = np.asarray(got, dtype=np.float64).reshape(-1, 3)
     ref = np.asarray(ref, dtype=np.float64).reshape(-1, 3)
     return float(np.linalg.norm(got - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
+
+
+def hbm_traffic(kernel: str, n: int):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy), or None when
+    the summary is missing, was taken at another N, or the kernel sources
+    have changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "pair_kernel_f32_angular_n65536_hbm.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel") != kernel or d.get("n") != n:
+        return None
+    h = hashlib.sha256()
+    for f in d.get("kernel_sources", []):
+        try:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        except OSError:
+            return None
+    if h.hexdigest() != d.get("kernel_source_sha256"):
+        return None
+    return d.get("traffic_bytes_per_dispatch")
 
 
 def timed(fn, reps, stream):
@@ -140,15 +167,23 @@ def main():
     avg_pair_ms = pair_ms / max(pair_launches, 1)
     achieved = FLOPS_PER_PAIR["angular"] * float(n) * float(n) / (avg_pair_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": hbm_traffic("pair_kernel<float, true, 2>", n),
                 "kernel": "pair_kernel<float, angular>", "avg_launch_ms": round(avg_pair_ms, 4),
                 "launches": pair_launches, "flops_per_pair": FLOPS_PER_PAIR["angular"]}
+
+    if args.calibrate_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- breakdown outside the timed steps -------------------------------
     print("bench: breakdown (fp32/fp64 Mdot, backward)", file=sys.stderr, flush=True)
     breakdown = {}
     results = {}
-    for dt, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+    for dt, name in (() if args.no_breakdown else ((torch.float32, "fp32"), (torch.float64, "fp64"))):
         Xd, Fd, Td = dev_t(s.pos, dt), dev_t(s.forces, dt), dev_t(s.torques, dt)
         GUd, GWd = dev_t(g_u, dt), dev_t(g_w, dt)
         for ang in (False, True):

@@ -26,6 +26,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <string>
 #include <vector>
 
 namespace rpy {
@@ -36,9 +38,9 @@ constexpr int kRedThreads = 256;
 constexpr int kMaxK = 1024;        // largest tridiagonal the eigensolver takes
 constexpr int kEigThreads = 256;
 
-// status block (double): [0] beta0, [1] increment, [2] flags; the host
-// copy also receives [3] beta_k and [4] alpha_k
-enum { ST_BETA0 = 0, ST_INCR = 1, ST_FLAGS = 2, ST_BETAK = 3, ST_ALPHAK = 4, ST_SIZE = 4 };
+// status block (double): [0] beta0, [1] relative increment, [2] flags,
+// [3] running max(|alpha|, beta), [4] first breakdown iteration (0 = none)
+enum { ST_BETA0 = 0, ST_INCR = 1, ST_FLAGS = 2, ST_TSCALE = 3, ST_BREAK = 4, ST_SIZE = 8 };
 enum { FLAG_NOT_SPD = 1, FLAG_NONFINITE = 2 };
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
@@ -82,13 +84,6 @@ __global__ void axpy_dev(double *__restrict__ y, const double *__restrict__ x, c
         y[i] = fma(c, x[i], y[i]);
 }
 
-// dst = src / (*beta)
-__global__ void scale_div(double *__restrict__ dst, const double *__restrict__ src, const double *beta, int64_t n) {
-    const double inv = 1.0 / (*beta);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i] * inv;
-}
-
 // v1 = W / beta0, W in the caller's dtype
 template <typename Tin>
 __global__ void init_basis(double *__restrict__ v, const Tin *__restrict__ w, const double *beta0, int64_t n) {
@@ -109,22 +104,51 @@ __global__ void sumsq_partial(const Tin *__restrict__ w, int64_t n, double *__re
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
 // partial[b * k + j] = sum over block b's rows of V[j][i] w[i], j < k.
-// Block b owns one contiguous slab of rows; its slice of w stays in L1/L2
-// while the k basis columns stream past.
-__global__ void gemv_t_partial(const double *__restrict__ V, int64_t ld, int k, const double *__restrict__ w,
-                               int64_t n, double *__restrict__ partial) {
-    __shared__ double sh[kRedThreads];
+// Block b owns one contiguous slab of rows.  Columns are taken eight at a
+// time: each thread accumulates eight dot products over its rows, the wave
+// reduces them with butterfly shuffles and one barrier combines the waves.
+constexpr int kGemvCols = 8;
+__global__ void __launch_bounds__(kRedThreads)
+gemv_t_partial(const double *__restrict__ V, int64_t ld, int k, const double *__restrict__ w, int64_t n,
+               double *__restrict__ partial) {
+    constexpr int kWaves = kRedThreads / 64;
+    __shared__ double sh[kGemvCols][kWaves];
     int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     chunk = (chunk + blockDim.x - 1) / blockDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * chunk;
     const int64_t i1 = std::min<int64_t>(n, i0 + chunk);
-    for (int j = 0; j < k; ++j) {
-        const double *col = V + (size_t)j * ld;
-        double acc = 0.0;
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) acc = fma(col[i], w[i], acc);
-        const double r = block_sum(acc, sh);
-        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * k + j] = r;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int j0 = 0; j0 < k; j0 += kGemvCols) {
+        double acc[kGemvCols];
+#pragma unroll
+        for (int c = 0; c < kGemvCols; ++c) acc[c] = 0.0;
+        const int nc = std::min(kGemvCols, k - j0);
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+            const double wi = w[i];
+#pragma unroll
+            for (int c = 0; c < kGemvCols; ++c)
+                if (c < nc) acc[c] = fma(V[(size_t)(j0 + c) * ld + i], wi, acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < kGemvCols; ++c) {
+            const double v = wave_sum(acc[c]);
+            if (lane == 0) sh[c][wv] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < nc) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) t += sh[threadIdx.x][q];
+            partial[(size_t)blockIdx.x * k + j0 + threadIdx.x] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -185,37 +209,44 @@ __device__ __forceinline__ double rhyp(double x) {
     return y;
 }
 
-// Eigen-decomposition of the k x k symmetric tridiagonal T (diagonal alpha,
-// off-diagonal beta) by implicit QL with Wilkinson-type shifts (the
-// textbook tql2 scheme), Q accumulated in global memory (row-major k x k,
-// thread r owning row r).  Then s = Q sqrt(lambda) Q^T e_1 and the
-// relative increment against s_prev (length k-1).  One workgroup.
+// Eigen-decomposition of the leading kk x kk block of the symmetric
+// tridiagonal T (diagonal alpha, off-diagonal beta) by implicit QL with
+// Wilkinson-type shifts (the textbook tql2 scheme), then
+// s = Q diag(sqrt(max(lambda, 0))) Q^T e_1.  Workgroup b of the launch
+// handles kk = k - 1 + b, so one launch yields s_{k-1} (block 0) and s_k
+// (block 1).  Q lives column-major in global memory (column j = eigenvector
+// j, one coalesced column per rotation step); thread 0 runs the scalar QL
+// recurrences of one sweep and stores its rotations in LDS, then every
+// thread applies them to its rows, carrying the running column in a
+// register so that the loads of a sweep are independent of its stores.
 __global__ void __launch_bounds__(kEigThreads)
 tridiag_sqrt_kernel(const double *__restrict__ alpha, const double *__restrict__ beta, int k,
-                    const double *__restrict__ s_prev, double *__restrict__ s_out, double *__restrict__ Q,
-                    double *__restrict__ status) {
+                    double *__restrict__ s_out0, double *__restrict__ s_out1, double *__restrict__ Qbuf,
+                    int64_t qstride, double *__restrict__ status) {
     __shared__ double d[kMaxK], e[kMaxK];
     __shared__ double rc[kMaxK], rs[kMaxK];
-    __shared__ int sweep[3];   // l, m (rotations m-1 .. l), done flag
-    __shared__ double red[kEigThreads];
+    __shared__ int sweep[3];   // lo, m (rotations m-1 .. lo), done flag
     const int tid = threadIdx.x;
-    for (int i = tid; i < k; i += blockDim.x) {
+    const int kk = k - 1 + (int)blockIdx.x;
+    double *s_out = blockIdx.x == 0 ? s_out0 : s_out1;
+    if (kk <= 0) return;
+    double *Q = Qbuf + (size_t)blockIdx.x * qstride;
+    for (int i = tid; i < kk; i += blockDim.x) {
         d[i] = alpha[i];
-        e[i] = (i + 1 < k) ? beta[i] : 0.0;
-        for (int j = 0; j < k; ++j) Q[(size_t)i * k + j] = (i == j) ? 1.0 : 0.0;
+        e[i] = (i + 1 < kk) ? beta[i] : 0.0;
     }
+    for (int64_t idx = tid; idx < (int64_t)kk * kk; idx += blockDim.x)
+        Q[idx] = (idx / kk == idx % kk) ? 1.0 : 0.0;
     __syncthreads();
 
-    // Thread 0 runs the scalar QL recurrences; the rotations of each sweep
-    // are then applied to the rows of Q by all threads.
     int l = 0;
     int iter = 0;
     while (true) {
         if (tid == 0) {
             int m = l;
             int done = 0;
-            while (l < k) {
-                for (m = l; m < k - 1; ++m) {
+            while (l < kk) {
+                for (m = l; m < kk - 1; ++m) {
                     const double dd = fabs(d[m]) + fabs(d[m + 1]);
                     if (fabs(e[m]) <= 2.220446049250313e-16 * dd) break;
                 }
@@ -224,42 +255,48 @@ tridiag_sqrt_kernel(const double *__restrict__ alpha, const double *__restrict__
                 ++l;
                 iter = 0;
             }
-            if (l >= k) {
+            if (l >= kk) {
                 done = 1;
             } else {
                 ++iter;
                 double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
                 double r = sqrt(fma(g, g, 1.0));
                 g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
-                double s = 1.0, c = 1.0, p = 0.0;
+                double sn = 1.0, cs = 1.0, p = 0.0;
                 int i;
                 bool underflow = false;
+                double ei = e[m - 1], di = d[m - 1], dip1 = d[m];
                 for (i = m - 1; i >= l; --i) {
-                    const double f = s * e[i];
-                    const double b = c * e[i];
+                    // prefetch the next step's (unmodified) entries
+                    const double e_nx = i > l ? e[i - 1] : 0.0;
+                    const double d_nx = i > l ? d[i - 1] : 0.0;
+                    const double f = sn * ei;
+                    const double b = cs * ei;
                     const double r2 = fma(f, f, g * g);
                     if (r2 == 0.0) {
-                        d[i + 1] -= p;
+                        d[i + 1] = dip1 - p;
                         e[m] = 0.0;
                         underflow = true;
                         break;
                     }
                     const double ri = rhyp(r2);
-                    r = r2 * ri;
-                    e[i + 1] = r;
-                    s = f * ri;
-                    c = g * ri;
-                    g = d[i + 1] - p;
-                    r = (d[i] - g) * s + 2.0 * c * b;
-                    p = s * r;
+                    e[i + 1] = r2 * ri;
+                    sn = f * ri;
+                    cs = g * ri;
+                    g = dip1 - p;
+                    r = (di - g) * sn + 2.0 * cs * b;
+                    p = sn * r;
                     d[i + 1] = g + p;
-                    g = c * r - b;
-                    rc[i] = c;
-                    rs[i] = s;
+                    g = cs * r - b;
+                    rc[i] = cs;
+                    rs[i] = sn;
+                    dip1 = di;
+                    di = d_nx;
+                    ei = e_nx;
                 }
                 const int lo = underflow ? i + 1 : l;
                 if (!underflow) {
-                    d[l] -= p;
+                    d[l] = dip1 - p;
                     e[l] = g;
                     e[m] = 0.0;
                 }
@@ -271,44 +308,91 @@ tridiag_sqrt_kernel(const double *__restrict__ alpha, const double *__restrict__
         __syncthreads();
         if (sweep[2]) break;
         const int lo = sweep[0], m = sweep[1];
-        for (int row = tid; row < k; row += blockDim.x) {
-            double *q = Q + (size_t)row * k;
-            for (int i = m - 1; i >= lo; --i) {
-                const double f = q[i + 1];
-                q[i + 1] = rs[i] * q[i] + rc[i] * f;
-                q[i] = rc[i] * q[i] - rs[i] * f;
+        for (int row = tid; row < kk; row += blockDim.x) {
+            double carry = Q[(size_t)m * kk + row];
+            int i = m - 1;
+            for (; i - 3 >= lo; i -= 4) {
+                const double q0 = Q[(size_t)i * kk + row];
+                const double q1 = Q[(size_t)(i - 1) * kk + row];
+                const double q2 = Q[(size_t)(i - 2) * kk + row];
+                const double q3 = Q[(size_t)(i - 3) * kk + row];
+                double nv;
+                nv = fma(rs[i], q0, rc[i] * carry);
+                carry = fma(rc[i], q0, -rs[i] * carry);
+                Q[(size_t)(i + 1) * kk + row] = nv;
+                nv = fma(rs[i - 1], q1, rc[i - 1] * carry);
+                carry = fma(rc[i - 1], q1, -rs[i - 1] * carry);
+                Q[(size_t)i * kk + row] = nv;
+                nv = fma(rs[i - 2], q2, rc[i - 2] * carry);
+                carry = fma(rc[i - 2], q2, -rs[i - 2] * carry);
+                Q[(size_t)(i - 1) * kk + row] = nv;
+                nv = fma(rs[i - 3], q3, rc[i - 3] * carry);
+                carry = fma(rc[i - 3], q3, -rs[i - 3] * carry);
+                Q[(size_t)(i - 2) * kk + row] = nv;
             }
+            for (; i >= lo; --i) {
+                const double q0 = Q[(size_t)i * kk + row];
+                Q[(size_t)(i + 1) * kk + row] = fma(rs[i], q0, rc[i] * carry);
+                carry = fma(rc[i], q0, -rs[i] * carry);
+            }
+            Q[(size_t)lo * kk + row] = carry;
         }
         __syncthreads();
     }
 
-    // spectrum check and square roots (eigenvalues d[j], eigenvectors = columns of Q)
-    double lmax = -1e308, lmin = 1e308;
-    for (int j = 0; j < k; ++j) {
-        lmax = fmax(lmax, d[j]);
-        lmin = fmin(lmin, d[j]);
+    // spectrum check (largest block only) and the square root applied to e_1
+    if (blockIdx.x == 1 && tid == 0) {
+        double lmax = -1e308, lmin = 1e308;
+        for (int j = 0; j < kk; ++j) {
+            lmax = fmax(lmax, d[j]);
+            lmin = fmin(lmin, d[j]);
+        }
+        status[ST_FLAGS] = (lmin < -1e-10 * fmax(lmax, 0.0)) ? (double)FLAG_NOT_SPD : 0.0;
     }
-    // u_j = sqrt(max(lambda_j, 0)) * Q[0][j]
-    for (int j = tid; j < k; j += blockDim.x) rc[j] = sqrt(fmax(d[j], 0.0)) * Q[j];
+    // u_j = sqrt(max(lambda_j, 0)) * Q[0][j]  (row 0 of column j)
+    for (int j = tid; j < kk; j += blockDim.x) rc[j] = sqrt(fmax(d[j], 0.0)) * Q[(size_t)j * kk];
     __syncthreads();
-    double num = 0.0, den = 0.0;
-    for (int row = tid; row < k; row += blockDim.x) {
-        const double *q = Q + (size_t)row * k;
+    for (int row = tid; row < kk; row += blockDim.x) {
         double acc = 0.0;
-        for (int j = 0; j < k; ++j) acc = fma(q[j], rc[j], acc);
+        for (int j = 0; j < kk; ++j) acc = fma(Q[(size_t)j * kk + row], rc[j], acc);
         s_out[row] = acc;
-        const double prev = (row < k - 1) ? s_prev[row] : 0.0;
-        num = fma(acc - prev, acc - prev, num);
-        den = fma(acc, acc, den);
+    }
+}
+
+// status[ST_INCR] = |s1 - [s0; 0]| / |s1| for s0 of length k-1, s1 of length k.
+__global__ void increment_kernel(const double *__restrict__ s0, const double *__restrict__ s1, int k,
+                                 double *__restrict__ status) {
+    __shared__ double red[kRedThreads];
+    double num = 0.0, den = 0.0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        const double prev = (i < k - 1) ? s0[i] : 0.0;
+        const double dlt = s1[i] - prev;
+        num = fma(dlt, dlt, num);
+        den = fma(s1[i], s1[i], den);
     }
     num = block_sum(num, red);
     den = block_sum(den, red);
-    if (tid == 0) {
-        status[ST_INCR] = (k >= 2 && den > 0.0) ? sqrt(num / den) : INFINITY;
-        double flags = 0.0;
-        if (lmin < -1e-10 * fmax(lmax, 0.0)) flags += FLAG_NOT_SPD;
-        status[ST_FLAGS] = flags;
-    }
+    if (threadIdx.x == 0) status[ST_INCR] = (k >= 2 && den > 0.0) ? sqrt(num / den) : INFINITY;
+}
+
+// After beta_k: track max(|alpha|, beta) and record the first breakdown
+// beta_k <= 1e-14 max(|alpha|, beta) (the Krylov space is invariant).
+__global__ void finish_iter_kernel(const double *__restrict__ alpha, const double *__restrict__ beta, int k,
+                                   double *__restrict__ status) {
+    if (threadIdx.x != 0) return;
+    const double a = fabs(alpha[k - 1]), b = beta[k - 1];
+    const double sc = fmax(status[ST_TSCALE], fmax(a, b));
+    status[ST_TSCALE] = sc;
+    if (status[ST_BREAK] == 0.0 && !(b > 1e-14 * sc)) status[ST_BREAK] = (double)k;
+}
+
+// v_{k+1} = w / beta_k, or zeros once a breakdown has been recorded.
+__global__ void next_basis_kernel(double *__restrict__ dst, const double *__restrict__ src,
+                                  const double *__restrict__ beta, const double *__restrict__ status, int64_t n) {
+    const bool broken = status[ST_BREAK] != 0.0;
+    const double inv = broken ? 0.0 : 1.0 / (*beta);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = broken ? 0.0 : src[i] * inv;
 }
 
 struct LanczosWork {
@@ -340,7 +424,7 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
     HIP_TRY(s, s->lz_w.ensure((size_t)ld * sizeof(double)));
     HIP_TRY(s, s->lz_scal.ensure(sizeof(double) * (ST_SIZE + 6 * (size_t)(kMaxK + 1))));
     HIP_TRY(s, s->lz_red.ensure(sizeof(double) * (size_t)kRedBlocks * (kMaxK + 1)));
-    HIP_TRY(s, s->lz_q.ensure(sizeof(double) * (size_t)kmax * kmax));
+    HIP_TRY(s, s->lz_q.ensure(sizeof(double) * 2 * (size_t)kmax * kmax));
     if (!s->host_scal) HIP_TRY(s, hipHostMalloc((void **)&s->host_scal, sizeof(double) * 8, hipHostMallocDefault));
     LanczosWork L;
     L.V = s->lz_basis.as<double>();
@@ -360,7 +444,8 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
     rpy_status r = ensure_vec_buffers(s, ang_mode);
     if (r != RPY_OK) return r;
 
-    // beta0 = |W|, v1 = W / beta0
+    // beta0 = |W|, v1 = W / beta0; the status block starts cleared
+    HIP_TRY(s, launch_fill_zero<double>(L.status, ST_SIZE, st));
     hipLaunchKernelGGL((sumsq_partial<Tio>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, w_in, n, L.red);
     hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, L.red, kRedBlocks, L.status + ST_BETA0, 1);
     HIP_TRY(s, hipGetLastError());
@@ -378,9 +463,16 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
     hipLaunchKernelGGL((init_basis<Tio>), dim3(grid_for(n)), dim3(256), 0, st, L.V, w_in, L.status + ST_BETA0, n);
     HIP_TRY(s, hipGetLastError());
 
+    // The increment test needs s_{k-1} and s_k, both produced by one launch
+    // of the eigensolver; it is evaluated at iterations predicted from the
+    // observed convergence rate (and always at max_iter), and the host only
+    // waits for the device at those iterations.  RPY_LANCZOS_CHECK=every
+    // evaluates it at every iteration.
+    const char *check_env = std::getenv("RPY_LANCZOS_CHECK");
+    const bool check_every = check_env && std::string(check_env) == "every";
     const int g = grid_for(n);
-    int k = 0;
-    double incr = INFINITY, tscale = 0.0;
+    int k = 0, kf = 0, next_check = 2, prev_k = -1;
+    double incr = INFINITY, prev_incr = INFINITY;
     bool converged = false, not_spd = false;
     for (k = 1; k <= kmax; ++k) {
         const double *vk = L.V + (size_t)(k - 1) * ld;
@@ -408,40 +500,53 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
             hipLaunchKernelGGL(gemv_t_final, dim3(k), dim3(kRedThreads), 0, st, L.red, kRedBlocks, k, L.h);
             hipLaunchKernelGGL(gemv_n_sub, dim3(g), dim3(256), 0, st, L.V, ld, k, L.h, L.w, n);
         }
-        // beta_k = |w|
+        // beta_k = |w|, breakdown bookkeeping, v_{k+1}
         hipLaunchKernelGGL(dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, L.w, L.w, n, L.red);
         hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, L.red, kRedBlocks, L.beta + (k - 1), 1);
-        // T_k eigensolve, s_k, increment
-        hipLaunchKernelGGL(tridiag_sqrt_kernel, dim3(1), dim3(kEigThreads), 0, st, L.alpha, L.beta, k, L.s_prev, L.s,
-                           L.Q, L.status);
+        hipLaunchKernelGGL(finish_iter_kernel, dim3(1), dim3(64), 0, st, L.alpha, L.beta, k, L.status);
         HIP_TRY(s, hipGetLastError());
-        HIP_TRY(s, hipMemcpyAsync(s->host_scal, L.status, sizeof(double) * ST_SIZE, hipMemcpyDeviceToHost, st));
-        HIP_TRY(s, hipMemcpyAsync(s->host_scal + ST_BETAK, L.beta + (k - 1), sizeof(double), hipMemcpyDeviceToHost, st));
-        HIP_TRY(s, hipMemcpyAsync(s->host_scal + ST_ALPHAK, L.alpha + (k - 1), sizeof(double), hipMemcpyDeviceToHost, st));
-        HIP_TRY(s, hipStreamSynchronize(st));
-        incr = s->host_scal[ST_INCR];
-        const double flags = s->host_scal[ST_FLAGS];
-        const double betak = s->host_scal[ST_BETAK];
-        tscale = std::max({tscale, std::fabs(s->host_scal[ST_ALPHAK]), betak});
-        if (((int)flags) & FLAG_NOT_SPD) {
-            not_spd = true;
-            break;
+        const bool last = (k == kmax);
+        if (k >= next_check || last || check_every) {
+            hipLaunchKernelGGL(tridiag_sqrt_kernel, dim3(2), dim3(kEigThreads), 0, st, L.alpha, L.beta, k, L.s_prev,
+                               L.s, L.Q, (int64_t)kmax * kmax, L.status);
+            hipLaunchKernelGGL(increment_kernel, dim3(1), dim3(kRedThreads), 0, st, L.s_prev, L.s, k, L.status);
+            HIP_TRY(s, hipGetLastError());
+            HIP_TRY(s, hipMemcpyAsync(s->host_scal, L.status, sizeof(double) * ST_SIZE, hipMemcpyDeviceToHost, st));
+            HIP_TRY(s, hipStreamSynchronize(st));
+            incr = s->host_scal[ST_INCR];
+            const int kb = (int)s->host_scal[ST_BREAK];
+            kf = k;
+            if (kb > 0) {
+                // invariant Krylov space at kb: T_k = diag(T_kb, 0), so s_k = [s_kb; 0]
+                kf = kb;
+                converged = true;
+                break;
+            }
+            if (((int)s->host_scal[ST_FLAGS]) & FLAG_NOT_SPD) {
+                not_spd = true;
+                break;
+            }
+            if (k >= 2 && incr < tol) {
+                converged = true;
+                break;
+            }
+            if (last) break;
+            // next evaluation: a little before the iteration where the observed
+            // geometric decrease of the increment would cross tol
+            int step = std::max(1, k / 4);
+            if (prev_k > 0 && std::isfinite(incr) && incr > 0.0 && incr < prev_incr) {
+                const double rate = std::log(incr / prev_incr) / (double)(k - prev_k);
+                const double remaining = std::log(tol / incr) / rate;
+                step = (int)std::floor(0.8 * remaining);
+                step = std::max(1, std::min(step, std::max(1, k / 2)));
+            }
+            prev_k = k;
+            prev_incr = incr;
+            next_check = k + step;
         }
-        if (k >= 2 && incr < tol) {
-            converged = true;
-            break;
-        }
-        // breakdown: the Krylov space is (numerically) invariant, y_k is exact
-        if (!(betak > 1e-14 * tscale) || k == n) {
-            converged = true;
-            break;
-        }
-        if (k == kmax) break;
-        // scale for the next basis vector; remember s_k
-        hipLaunchKernelGGL(scale_div, dim3(g), dim3(256), 0, st, L.V + (size_t)k * ld, L.w, L.beta + (k - 1), n);
-        HIP_TRY(s, hipMemcpyAsync(L.s_prev, L.s, sizeof(double) * k, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(next_basis_kernel, dim3(g), dim3(256), 0, st, L.V + (size_t)k * ld, L.w, L.beta + (k - 1),
+                           L.status, n);
     }
-    const int kf = std::min(k, kmax);
     hipLaunchKernelGGL((combine_out<Tio>), dim3(g), dim3(256), 0, st, L.V, ld, kf, L.s, L.status, prefactor, n,
                        3 * np, lin, ang);
     HIP_TRY(s, hipGetLastError());

@@ -62,6 +62,29 @@ def test_lanczos_matched_iterations(dtype, angular, n):
     assert e2 <= 1e-5
 
 
+@pytest.mark.parametrize("angular", [False, True])
+def test_lanczos_stopping_iteration_against_oracle(monkeypatch, angular):
+    """Evaluating the increment test at every iteration stops exactly where
+    the oracle's Lanczos stops; the default (rate-predicted) evaluation stops
+    there or a few iterations later, never earlier."""
+    say(f"case lanczos stopping rule angular={angular}")
+    s = workloads.uniform_cube(400, 0.2, 41, w=True, angular_w=angular)
+    m = mobility.grand_mobility(s.pos, s.radius, s.viscosity, angular)
+    y_ref, info = lanczos.lanczos_sqrt(lambda v: m @ v, s.w, tol=1e-6)
+    sol = _solver(angular)
+    sol.setPositions(to_dev(s.pos, torch.float64))
+    monkeypatch.setenv("RPY_LANCZOS_CHECK", "every")
+    lin, ang = sol.sqrtMdotW(to_dev(s.w, torch.float64), tol=1e-6)
+    say(f"  oracle stops at {info.iters}, every-iteration check at {sol.last_iterations}")
+    assert sol.last_iterations == info.iters
+    y = _flat(lin, ang)
+    assert np.abs(y - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
+    monkeypatch.delenv("RPY_LANCZOS_CHECK")
+    sol.sqrtMdotW(to_dev(s.w, torch.float64), tol=1e-6)
+    say(f"  rate-predicted check stops at {sol.last_iterations}")
+    assert info.iters <= sol.last_iterations <= info.iters + max(3, info.iters // 5)
+
+
 def test_lanczos_zero_noise_and_not_converged():
     import paper_2510_02135_amd as rpy
     say("case lanczos edge cases")
