@@ -50,6 +50,7 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     p.add_argument("--no-breakdown", action="store_true", help="skip the per-precision breakdown and oracle check")
+    p.add_argument("--no-batch", action="store_true", help="skip the batched-systems measurement")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -84,6 +85,64 @@ def hbm_traffic(kernel: str, n: int):
     if h.hexdigest() != d.get("kernel_source_sha256"):
         return None
     return d.get("traffic_bytes_per_dispatch")
+
+
+def bench_batched(rpy, workloads, dev, stream, timed):
+    """512 independent systems (N log-uniform in [64, 8192], phi in [0.05, 0.3],
+    seed 1004), float32: Mdot and sqrtMdotW (tol 1e-6) for all systems in one
+    batched call vs one single-system solver call per system."""
+    import numpy as np
+    import torch
+    syss = workloads.c4_systems()
+    ns = np.array([s.n for s in syss])
+    off = np.concatenate([[0], np.cumsum(ns)])
+    f32 = torch.float32
+    X = torch.tensor(np.concatenate([s.pos for s in syss]), dtype=f32, device=dev)
+    F = torch.tensor(np.concatenate([s.forces for s in syss]), dtype=f32, device=dev)
+    W = torch.tensor(np.concatenate([s.w for s in syss]), dtype=f32, device=dev)
+    b = rpy.Batch(off, workloads.VISCOSITY, workloads.RADIUS, f32)
+    b.setPositions(X)
+    b.Mdot(F)
+    t_mdot = timed(lambda: b.Mdot(F), 5, stream)
+    b.sqrtMdotW(W, tol=1e-6)
+    t0 = time.perf_counter()
+    b.sqrtMdotW(W, tol=1e-6)
+    torch.cuda.synchronize()
+    t_sqrt = 1e3 * (time.perf_counter() - t0)
+    iters = np.array(b.last_iterations)
+    # one solver call per system (each system's arrays already on the device)
+    sols = []
+    for k, s in enumerate(syss):
+        so = rpy.Solver()
+        so.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius)
+        so.setPositions(X[off[k]:off[k + 1]])
+        sols.append(so)
+    Fs = [F[off[k]:off[k + 1]] for k in range(len(syss))]
+    Ws = [W[3 * off[k]:3 * off[k + 1]] for k in range(len(syss))]
+    def per_system_mdot():
+        for so, f in zip(sols, Fs):
+            so.Mdot(f)
+    per_system_mdot()
+    t_mdot_ps = timed(per_system_mdot, 3, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_ps = []
+    for so, w in zip(sols, Ws):
+        so.sqrtMdotW(w, tol=1e-6)
+        it_ps.append(so.last_iterations)
+    torch.cuda.synchronize()
+    t_sqrt_ps = 1e3 * (time.perf_counter() - t0)
+    for so in sols:
+        so.close()
+    b.close()
+    pairs = float((ns.astype(np.float64) ** 2).sum())
+    return {"systems": len(syss), "total_particles": int(off[-1]), "sum_n2": pairs,
+            "mdot_ms": round(t_mdot, 4), "mdot_pairs_per_s": pairs / (t_mdot * 1e-3),
+            "mdot_per_system_launches_ms": round(t_mdot_ps, 3),
+            "sqrt_ms": round(t_sqrt, 3), "sqrt_per_system_launches_ms": round(t_sqrt_ps, 3),
+            "lanczos_iterations": {"min": int(iters.min()), "median": float(np.median(iters)),
+                                   "max": int(iters.max())},
+            "per_system_lanczos_iterations_median": float(np.median(it_ps))}
 
 
 def timed(fn, reps, stream):
@@ -133,6 +192,8 @@ def main():
     sol = rpy.Solver("open", "open", "open")
     sol.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius, includeAngular=True)
     sol.setPositions(X)
+    print("bench: autotuning the pair kernel tiles", file=sys.stderr, flush=True)
+    tiles = sol.autotune()
 
     iters = []
 
@@ -190,6 +251,7 @@ def main():
             so = rpy.Solver()
             so.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius, includeAngular=ang)
             so.setPositions(Xd)
+            so.autotune()
             key = f"{name}_{'angular' if ang else 'linear'}"
             fwd = lambda: so.Mdot(forces=Fd, torques=Td if ang else None)
             bwd = lambda: so.Mdot_backward(Fd, Td if ang else None, GUd, GWd if ang else None)
@@ -204,6 +266,12 @@ def main():
             results[key] = (lin.double().cpu().numpy(), None if angv is None else angv.double().cpu().numpy(),
                             gp.double().cpu().numpy(), gf.double().cpu().numpy())
             so.close()
+
+    # ---- batched systems: one persistent launch vs one launch per system ----
+    batched = None
+    if not args.no_batch:
+        print("bench: batched systems", file=sys.stderr, flush=True)
+        batched = bench_batched(rpy, workloads, dev, stream, timed)
 
     # ---- accuracy against the float64 oracle on sampled particles --------
     print("bench: oracle check on sampled rows", file=sys.stderr, flush=True)
@@ -265,6 +333,8 @@ def main():
         "cpu_baseline": cpu,
         "breakdown": breakdown,
         "accuracy_vs_fp64_oracle": acc,
+        "batched": batched,
+        "tiles": {"linear": tiles[0], "angular": tiles[1]},
         "adjoint_kernel_avg_ms": round(adj_ms / max(adj_launches, 1), 4),
     }
     sol.close()

@@ -159,6 +159,80 @@ rpy_status rpy_mdot_backward(rpy_solver *s, const void *forces, const void *torq
                              const void *grad_lin, const void *grad_ang, void *grad_pos,
                              void *grad_forces, void *grad_torques, void *hip_stream);
 
+/*
+ * Batched solver: many independent open-boundary systems of uneven size
+ * (an addition beside the paper's method).  System s owns particles
+ * offsets[s] .. offsets[s+1]-1 of every concatenated per-particle array
+ * (positions, forces, outputs: total x 3 row-major) and entries
+ * 3*offsets[s] .. 3*offsets[s+1]-1 of noise vectors.  Systems never
+ * interact.  Translational blocks only (M_uF).  All systems share one
+ * dtype; viscosity and radius are per system.
+ */
+typedef struct rpy_batch rpy_batch;
+
+/*
+ * offsets (host, n_systems + 1 entries, offsets[0] = 0, strictly
+ * increasing), viscosity and radius (host, n_systems entries each, > 0).
+ * The arrays are copied.  Allocates the device task list; the caller owns
+ * *out and frees it with rpy_batch_destroy.
+ */
+rpy_status rpy_batch_create(int32_t n_systems, const int64_t *offsets, const double *viscosity,
+                            const double *radius, rpy_dtype dtype, rpy_batch **out);
+
+/* Store the positions of every system (device, total x 3); checks for
+ * NaN/Inf and therefore synchronises hip_stream. */
+rpy_status rpy_batch_set_positions(rpy_batch *b, const void *pos, void *hip_stream);
+
+/*
+ * lin_out = M_s F for every system s (device, total x 3), all systems in
+ * one persistent kernel launch.  Asynchronous.
+ */
+rpy_status rpy_batch_mdot(rpy_batch *b, const void *forces, void *lin_out, void *hip_stream);
+
+/*
+ * lin_out = prefactor * M_s^{1/2} w_s for every system (device w of
+ * 3 x total entries, lin_out total x 3) by Lanczos (Sec. 3.3) with the
+ * stopping rule of rpy_sqrt_mdot_w applied to each system separately.  All
+ * systems advance together; one iteration (persistent pair kernel for all
+ * systems, segmented float64 vector operations) is one replay of a
+ * captured HIP graph, and a second graph runs the per-system eigensolves
+ * and convergence tests every `check_every` iterations (>= 1).  iters_out
+ * (host, n_systems entries, may be NULL) receives each system's iteration
+ * count.  Synchronises hip_stream.  Returns RPY_ERR_NOT_CONVERGED if any
+ * system reached max_iter (all results written), RPY_ERR_NOT_SPD if any
+ * system's matrix was found indefinite.
+ */
+rpy_status rpy_batch_sqrt_mdot_w(rpy_batch *b, const void *w, double prefactor, double tol, int max_iter,
+                                 int check_every, void *lin_out, int *iters_out, void *hip_stream);
+
+/* Message describing the last failure of `b`; owned by `b`. */
+const char *rpy_batch_last_error(const rpy_batch *b);
+
+/* Release the batch, its graphs and device buffers.  NULL is ignored. */
+void rpy_batch_destroy(rpy_batch *b);
+
+/*
+ * Tile configuration of the pair kernel, separately for products without
+ * (angular = 0) and with (angular = 1) the angular blocks:
+ * targets_per_lane in {1, 2, 4}; source_splits = number of source ranges
+ * the grid is split into (0 = chosen from N; clamped to ceil(N/256)).
+ * Results do not depend on the configuration beyond float rounding order.
+ */
+rpy_status rpy_set_tile_config(rpy_solver *s, int angular, int targets_per_lane, int source_splits);
+rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_per_lane, int *source_splits);
+
+/*
+ * Autotuner (an addition beside the paper's method): for the stored
+ * positions' N and dtype, times every candidate (targets per lane x source
+ * splits) of the pair kernel with HIP events on hip_stream, for the
+ * translational product and, with include_angular, the angular one, and
+ * keeps the fastest as the solver's tile configuration.  With cache_path
+ * != NULL the choice is looked up in / added to a text file of lines
+ *   <arch>|<f32|f64>|<lin|ang>|<round(log2 N)> <targets_per_lane> <splits> <ms>
+ * (a cached entry is used without timing).  Synchronises hip_stream.
+ */
+rpy_status rpy_autotune(rpy_solver *s, const char *cache_path, void *hip_stream);
+
 /* Kernel classes reported by rpy_kernel_time. */
 typedef enum { RPY_KERNEL_PAIR = 0, RPY_KERNEL_ADJOINT = 1 } rpy_kernel;
 

@@ -77,6 +77,16 @@ def load() -> ctypes.CDLL:
         "rpy_sqrt_mdot_w": ([vp, vp, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_div_m": ([vp, vp, vp, vp], i),
         "rpy_mdot_backward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i),
+        "rpy_batch_create": ([ctypes.c_int32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d), i,
+                              ctypes.POINTER(vp)], i),
+        "rpy_batch_set_positions": ([vp, vp, vp], i),
+        "rpy_batch_mdot": ([vp, vp, vp, vp], i),
+        "rpy_batch_sqrt_mdot_w": ([vp, vp, d, d, i, i, vp, ctypes.POINTER(i), vp], i),
+        "rpy_batch_last_error": ([vp], ctypes.c_char_p),
+        "rpy_batch_destroy": ([vp], None),
+        "rpy_set_tile_config": ([vp, i, i, i], i),
+        "rpy_get_tile_config": ([vp, i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
+        "rpy_autotune": ([vp, ctypes.c_char_p, vp], i),
         "rpy_enable_timing": ([vp, i], i),
         "rpy_kernel_time": ([vp, i, ctypes.POINTER(d), ctypes.POINTER(i64), ctypes.POINTER(d)], i),
         "rpy_last_error": ([vp], ctypes.c_char_p),
@@ -177,6 +187,74 @@ def rpy_mdot_backward(h, forces, torques, grad_lin, grad_ang, grad_pos, grad_for
         _ptr(grad_lin, dtype, 3 * n, "grad_lin"), _ptr(grad_ang, dtype, 3 * n, "grad_ang"),
         _ptr(grad_pos, dtype, 3 * n, "grad_pos"), _ptr(grad_forces, dtype, 3 * n, "grad_forces"),
         _ptr(grad_torques, dtype, 3 * n, "grad_torques"), _stream(ref)))
+
+
+def _bcheck(h, status: int):
+    if status != 0:
+        raise RpyError(status, load().rpy_batch_last_error(h).decode() if h else "")
+
+
+def rpy_batch_create(offsets, viscosity, radius, dtype: torch.dtype):
+    """Batch of independent systems; offsets has n_systems + 1 entries."""
+    import numpy as np
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    eta = np.ascontiguousarray(viscosity, dtype=np.float64)
+    rad = np.ascontiguousarray(radius, dtype=np.float64)
+    ns = off.shape[0] - 1
+    if ns < 1 or eta.shape[0] != ns or rad.shape[0] != ns:
+        raise ValueError("offsets must have n_systems + 1 entries and viscosity/radius n_systems")
+    if dtype not in DTYPE:
+        raise ValueError(f"DTYPE_MISMATCH: dtype must be float32 or float64, got {dtype}")
+    out = ctypes.c_void_p()
+    st = load().rpy_batch_create(ns, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                 eta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                 rad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), DTYPE[dtype],
+                                 ctypes.byref(out))
+    if st != 0:
+        raise RpyError(st, "rpy_batch_create")
+    return out
+
+
+def rpy_batch_set_positions(h, pos, dtype, total):
+    _bcheck(h, load().rpy_batch_set_positions(h, _ptr(pos, dtype, 3 * total, "positions"), _stream(pos)))
+
+
+def rpy_batch_mdot(h, forces, lin_out, dtype, total):
+    _bcheck(h, load().rpy_batch_mdot(h, _ptr(forces, dtype, 3 * total, "forces"),
+                                     _ptr(lin_out, dtype, 3 * total, "lin_out"), _stream(lin_out)))
+
+
+def rpy_batch_sqrt_mdot_w(h, w, prefactor, tol, max_iter, check_every, lin_out, dtype, total, n_systems):
+    iters = (ctypes.c_int * n_systems)()
+    st = load().rpy_batch_sqrt_mdot_w(h, _ptr(w, dtype, 3 * total, "W"), float(prefactor), float(tol),
+                                      int(max_iter), int(check_every), _ptr(lin_out, dtype, 3 * total, "lin_out"),
+                                      iters, _stream(lin_out))
+    it = list(iters)
+    if st == Status.NOT_CONVERGED:
+        raise NotConvergedError(st, load().rpy_batch_last_error(h).decode(), lin_out, it, float("nan"))
+    _bcheck(h, st)
+    return it
+
+
+def rpy_batch_destroy(h):
+    if h:
+        load().rpy_batch_destroy(h)
+
+
+def rpy_set_tile_config(h, angular: bool, targets_per_lane: int, source_splits: int):
+    _check(h, load().rpy_set_tile_config(h, int(bool(angular)), int(targets_per_lane), int(source_splits)))
+
+
+def rpy_get_tile_config(h, angular: bool):
+    tm = ctypes.c_int(0)
+    sp = ctypes.c_int(0)
+    _check(h, load().rpy_get_tile_config(h, int(bool(angular)), ctypes.byref(tm), ctypes.byref(sp)))
+    return tm.value, sp.value
+
+
+def rpy_autotune(h, cache_path: str | None = None):
+    path = None if cache_path is None else os.fspath(cache_path).encode()
+    _check(h, load().rpy_autotune(h, path, _stream()))
 
 
 def rpy_enable_timing(h, enable: bool = True):

@@ -21,6 +21,7 @@
 // Same decomposition as the forward pair kernel: target blocks x source
 // splits, LDS source tiles (position, F, g_U [, T, g_W]), fp32 in-tile sums
 // folded into Neumaier pairs per tile, fp64 plain sums.
+#include "rpy_device.hpp"
 #include "rpy_internal.hpp"
 #include "rpy_solver_ops.hpp"
 
@@ -32,30 +33,6 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kTile = 256;
-
-__device__ __forceinline__ float rsq_a(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rsq_a(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double h = x * y;
-    double e = fma(-h, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    h = x * y;
-    e = fma(-h, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    return y;
-}
-
-__device__ __forceinline__ void neumaier_a(float &s, float &c, float x) {
-    const float t = s + x;
-    const float lost = (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
-    c += lost;
-    s = t;
-}
-
-template <typename Real>
-struct Vec3 {
-    Real x, y, z;
-};
 
 template <typename Real>
 __device__ __forceinline__ Real dot3(Real ax, Real ay, Real az, Real bx, Real by, Real bz) {
@@ -79,7 +56,7 @@ __device__ __forceinline__ void adj_interact(const Tgt<Real, ANG> &k, const vec4
                                              const PairConst<Real> &c, Real *acc) {
     const Real dx = k.x - sp.x, dy = k.y - sp.y, dz = k.z - sp.z;
     const Real r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const Real ri = rsq_a(r2);
+    const Real ri = rsq(r2);
     const Real ri2 = ri * ri;
     const Real ri3 = ri * ri2;
     const Real ri5 = ri3 * ri2;
@@ -230,7 +207,7 @@ adjoint_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__restr
         if constexpr (COMP) {
 #pragma unroll
             for (int q = 0; q < NC; ++q) {
-                neumaier_a(sum[q], cmp[q], acc[q]);
+                neumaier(sum[q], cmp[q], acc[q]);
                 acc[q] = Real(0);
             }
         }
@@ -268,7 +245,7 @@ __global__ void reduce3_kernel(const Real *__restrict__ part, int n_split, int n
         if constexpr (COMP) {
             float s = 0.f, cp = 0.f, extra = 0.f;
             for (int q = 0; q < n_split; ++q) {
-                neumaier_a(s, cp, (float)part[q * stride + (size_t)c * nn + i]);
+                neumaier(s, cp, (float)part[q * stride + (size_t)c * nn + i]);
                 extra += (float)part[q * stride + (size_t)(NC + c) * nn + i];
             }
             v = (double)s + ((double)cp + (double)extra);
@@ -299,9 +276,8 @@ rpy_status backward_typed(rpy_solver *s, const Real *F, const Real *T, const Rea
     }
     const int nc = (ang ? 9 : 6) * (std::is_same<Real, float>::value ? 2 : 1);
     const int64_t tblocks = (n + kBlock - 1) / kBlock;
-    int splits = s->cfg.n_split > 0 ? s->cfg.n_split
-                                    : (int)std::max<int64_t>(1, std::min<int64_t>((2048 + tblocks - 1) / tblocks,
-                                                                                  (n + kTile - 1) / kTile));
+    const int splits = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + tblocks - 1) / tblocks,
+                                                                   (n + kTile - 1) / kTile));
     HIP_TRY(s, s->part.ensure((size_t)splits * nc * n * sizeof(Real)));
     int64_t split_len = (n + splits - 1) / splits;
     split_len = (split_len + kTile - 1) / kTile * kTile;

@@ -1,0 +1,201 @@
+// Tile autotuner of the pair kernel and the tile-configuration accessors.
+//
+// For the solver's current N and dtype it times every candidate
+// (targets per lane in {1, 2, 4}) x (source splits around the default
+// choice) with HIP events on the caller's stream and keeps the fastest, for
+// translational-only products and, with include_angular, for angular ones.
+// The forces used for timing are zeros: the pair kernel's work does not
+// depend on the values (only on positions, through the overlap branch).
+// Choices can be cached in a text file, one line per
+// (arch, dtype, mode, log2 N bucket).
+#include "rpy_internal.hpp"
+#include "rpy_solver_ops.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+using namespace rpy;
+
+namespace {
+
+struct Entry {
+    int tm = 2, split = 0;
+    double ms = 0.0;
+};
+
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string a = p.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string cache_key(const rpy_solver *s, bool ang) {
+    const int bucket = (int)std::lround(std::log2((double)std::max<int64_t>(1, s->n)));
+    return arch_name() + "|" + (s->dtype == RPY_F64 ? "f64" : "f32") + "|" + (ang ? "ang" : "lin") + "|" +
+           std::to_string(bucket);
+}
+
+std::map<std::string, Entry> read_cache(const char *path) {
+    std::map<std::string, Entry> m;
+    if (!path) return m;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream is(line);
+        std::string key;
+        Entry e;
+        if (is >> key >> e.tm >> e.split >> e.ms) m[key] = e;
+    }
+    return m;
+}
+
+bool write_cache(const char *path, const std::map<std::string, Entry> &m) {
+    if (!path) return true;
+    const std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        if (!f) return false;
+        for (const auto &kv : m) f << kv.first << " " << kv.second.tm << " " << kv.second.split << " " << kv.second.ms << "\n";
+        if (!f) return false;
+    }
+    return std::rename(tmp.c_str(), path) == 0;
+}
+
+// Median time (ms) of `reps` launches of the pair kernel with configuration c.
+template <typename Real>
+rpy_status time_config(rpy_solver *s, bool ang, const TileConfig &c, int reps, hipStream_t st, hipEvent_t a,
+                       hipEvent_t b, double *ms_out) {
+    const int64_t n = s->n;
+    const PairConst<Real> pc = make_pair_const<Real>(s->radius);
+    const auto *pos = s->pos.as<vec4_t<Real>>();
+    const auto *f = s->f.as<vec4_t<Real>>();
+    const auto *t = s->t.as<vec4_t<Real>>();
+    std::vector<float> times;
+    for (int r = 0; r < reps + 1; ++r) {
+        HIP_TRY(s, hipEventRecord(a, st));
+        if (ang)
+            HIP_TRY(s, (launch_pair<Real, true>(pos, f, t, n, pc, c, c.n_split, s->part.as<Real>(), st)));
+        else
+            HIP_TRY(s, (launch_pair<Real, false>(pos, f, nullptr, n, pc, c, c.n_split, s->part.as<Real>(), st)));
+        HIP_TRY(s, hipEventRecord(b, st));
+        HIP_TRY(s, hipEventSynchronize(b));
+        float ms = 0.f;
+        HIP_TRY(s, hipEventElapsedTime(&ms, a, b));
+        if (r > 0) times.push_back(ms);   // the first launch is a warm-up
+    }
+    std::sort(times.begin(), times.end());
+    *ms_out = times[times.size() / 2];
+    return RPY_OK;
+}
+
+template <typename Real>
+rpy_status tune_mode(rpy_solver *s, bool ang, hipStream_t st, Entry *best) {
+    const int64_t n = s->n;
+    const int smax = max_splits(n);
+    const int s0 = choose_splits(n, 2, s->dtype == RPY_F64, ang);
+    std::vector<int> splits;
+    for (int f : {-4, -2, 1, 2, 4}) {
+        const int v = f < 0 ? std::max(1, s0 / -f) : std::min(smax, s0 * f);
+        if (std::find(splits.begin(), splits.end(), v) == splits.end()) splits.push_back(v);
+    }
+    const int nc = (ang ? 6 : 3) * (std::is_same<Real, float>::value ? 2 : 1);
+    HIP_TRY(s, s->part.ensure((size_t)(*std::max_element(splits.begin(), splits.end())) * nc * n * sizeof(Real)));
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(s, hipEventCreate(&a));
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(s, RPY_ERR_HIP, "hipEventCreate failed");
+    }
+    best->ms = 1e300;
+    rpy_status r = RPY_OK;
+    for (int tm : {1, 2, 4}) {
+        for (int sp : splits) {
+            TileConfig c;
+            c.tm = tm;
+            c.n_split = sp;
+            double ms = 0.0;
+            r = time_config<Real>(s, ang, c, 3, st, a, b, &ms);
+            if (r != RPY_OK) break;
+            if (ms < best->ms) {
+                best->ms = ms;
+                best->tm = tm;
+                best->split = sp;
+            }
+        }
+        if (r != RPY_OK) break;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return r;
+}
+
+}  // namespace
+
+extern "C" {
+
+rpy_status rpy_set_tile_config(rpy_solver *s, int angular, int targets_per_lane, int source_splits) {
+    if (!s) return RPY_ERR_INVALID_ARG;
+    if (targets_per_lane != 1 && targets_per_lane != 2 && targets_per_lane != 4)
+        return fail(s, RPY_ERR_INVALID_ARG, "targets per lane must be 1, 2 or 4");
+    if (source_splits < 0) return fail(s, RPY_ERR_INVALID_ARG, "source splits must be >= 0");
+    TileConfig &c = s->cfg[angular ? 1 : 0];
+    c.tm = targets_per_lane;
+    c.n_split = source_splits;
+    return RPY_OK;
+}
+
+rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_per_lane, int *source_splits) {
+    if (!s) return RPY_ERR_INVALID_ARG;
+    const TileConfig &c = s->cfg[angular ? 1 : 0];
+    if (targets_per_lane) *targets_per_lane = c.tm;
+    if (source_splits) *source_splits = c.n_split;
+    return RPY_OK;
+}
+
+rpy_status rpy_autotune(rpy_solver *s, const char *cache_path, void *hip_stream) {
+    rpy_status r = check_ready(s);
+    if (r != RPY_OK) return r;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    std::map<std::string, Entry> cache = read_cache(cache_path);
+    bool dirty = false;
+    for (int mode = 0; mode < (s->angular ? 2 : 1); ++mode) {
+        const bool ang = mode == 1;
+        const std::string key = cache_key(s, ang);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            s->cfg[mode].tm = it->second.tm;
+            s->cfg[mode].n_split = it->second.split;
+            continue;
+        }
+        r = ensure_vec_buffers(s, true);
+        if (r != RPY_OK) return r;
+        if (s->dtype == RPY_F64) {
+            HIP_TRY(s, (launch_stage_vec<double, double>(nullptr, s->n, s->f.as<double4>(), st)));
+            HIP_TRY(s, (launch_stage_vec<double, double>(nullptr, s->n, s->t.as<double4>(), st)));
+        } else {
+            HIP_TRY(s, (launch_stage_vec<float, float>(nullptr, s->n, s->f.as<float4>(), st)));
+            HIP_TRY(s, (launch_stage_vec<float, float>(nullptr, s->n, s->t.as<float4>(), st)));
+        }
+        Entry best;
+        r = s->dtype == RPY_F64 ? tune_mode<double>(s, ang, st, &best) : tune_mode<float>(s, ang, st, &best);
+        if (r != RPY_OK) return r;
+        s->cfg[mode].tm = best.tm;
+        s->cfg[mode].n_split = best.split;
+        cache[key] = best;
+        dirty = true;
+    }
+    if (dirty && !write_cache(cache_path, cache))
+        return fail(s, RPY_ERR_INVALID_ARG, std::string("cannot write the autotune cache ") + cache_path);
+    return RPY_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,849 @@
+// Batched solver: many independent open-boundary systems of uneven N.
+//
+// Mdot for every system runs in one persistent kernel: work items are
+// (system, 64-target tile) pairs, ordered longest-system first and claimed
+// one wavefront at a time from an atomic counter; a wavefront keeps its 64
+// targets in registers and streams the system's sources with wave-uniform
+// (scalar) loads, so systems of a few dozen particles and of thousands share
+// the machine without per-system launches.  float32 mode folds per-256-source
+// sums into Neumaier pairs like the single-system kernel.
+//
+// sqrtMdotW runs the Lanczos iteration of Sec. 3.3 for all systems in lock
+// step on one global iteration counter kept in device memory, so the kernel
+// sequence of one iteration is captured once into a HIP graph and replayed;
+// float64 vector operations are segmented (every block of the segmented
+// kernels lies inside one system) with fixed-order two-stage reductions, and
+// converged systems drop out of all work.  A second graph runs, every
+// `check_every` iterations, one eigensolver workgroup pair per system
+// (s_{k-1} and s_k), the per-system increment test of the single-system
+// solver, and writes the result of each system as it converges.
+#include "rpy_device.hpp"
+#include "rpy_internal.hpp"
+#include "rpy_solver_ops.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+namespace rpy {
+namespace {
+
+constexpr int kBatchBlock = 256;   // 4 wavefronts per workgroup of the pair kernel
+constexpr int kSrcChunk = 256;     // sources per compensated fold (float32)
+constexpr int kSegChunk = 2048;    // vector elements per segmented block
+constexpr int kSegThreads = 256;
+
+// per-system status (double): beta0, increment, not-SPD flag, running
+// max(|alpha|, beta), first breakdown iteration, iterations at stop
+// (0 while active), result code (0 ok, 1 not converged, 2 not SPD), spare
+enum { BS_BETA0 = 0, BS_INCR, BS_NSPD, BS_TSCALE, BS_BREAK, BS_DONE, BS_CODE, BS_SIZE = 8 };
+
+// ---------------------------------------------------------------------------
+// persistent batched pair kernel
+// ---------------------------------------------------------------------------
+template <typename Real, typename Tout>
+__global__ void __launch_bounds__(kBatchBlock)
+batch_pair_kernel(const vec4_t<Real> *__restrict__ rec, const int64_t *__restrict__ off,
+                  const int2 *__restrict__ tasks, int ntasks, unsigned *__restrict__ counter,
+                  const PairConst<Real> *__restrict__ pcs, const double *__restrict__ kfac,
+                  const int *__restrict__ active, Tout *__restrict__ out) {
+    using R4 = vec4_t<Real>;
+    constexpr bool COMP = std::is_same<Real, float>::value;
+    const int lane = threadIdx.x & 63;
+    const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+    while (true) {
+        unsigned t = 0;
+        if (lane == 0) t = atomicAdd(counter, 1u);
+        t = __builtin_amdgcn_readfirstlane(__shfl(t, 0, 64));
+        if (t >= (unsigned)ntasks) break;
+        const int2 task = tasks[t];
+        const int s = task.x;
+        if (active && active[s] == 0) continue;
+        const int64_t o = off[s];
+        const int ns = (int)(off[s + 1] - o);
+        const int i = task.y * 64 + lane;
+        const R4 *src = rec + 2 * o;
+        const R4 p = src[2 * min(i, ns - 1)];
+        const PairConst<Real> c = pcs[s];
+        Real acc[3] = {Real(0), Real(0), Real(0)};
+        Real sum[3] = {Real(0), Real(0), Real(0)}, cmp[3] = {Real(0), Real(0), Real(0)};
+        for (int j0 = 0; j0 < ns; j0 += kSrcChunk) {
+            const int cnt = min(kSrcChunk, ns - j0);
+#pragma unroll 4
+            for (int q = 0; q < cnt; ++q) {
+                const R4 sp = src[2 * (j0 + q)];
+                const R4 sf = src[2 * (j0 + q) + 1];
+                interact<Real, false>(p.x, p.y, p.z, sp, sf, zero4, c, acc, nullptr);
+            }
+            if constexpr (COMP) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    neumaier(sum[d], cmp[d], acc[d]);
+                    acc[d] = Real(0);
+                }
+            }
+        }
+        if (i < ns) {
+            const double kk = kfac[s];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double v = COMP ? ((double)sum[d] + (double)cmp[d]) : (double)acc[d];
+                out[3 * (o + i) + d] = (Tout)(kk * v);
+            }
+        }
+    }
+}
+
+// positions (AoS total x 3) -> pos slots of the records, counting non-finite entries
+template <typename Real>
+__global__ void batch_stage_pos(const Real *__restrict__ in, int64_t ntot, vec4_t<Real> *__restrict__ rec,
+                                unsigned *__restrict__ nonfinite) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntot) return;
+    const Real x = in[3 * i], y = in[3 * i + 1], z = in[3 * i + 2];
+    if (!(isfinite((double)x) && isfinite((double)y) && isfinite((double)z))) atomicAdd(nonfinite, 1u);
+    vec4_t<Real> v;
+    v.x = x;
+    v.y = y;
+    v.z = z;
+    v.w = Real(0);
+    rec[2 * i] = v;
+}
+
+// AoS total x 3 vector (caller dtype, or the float64 Lanczos column at
+// V + (k-1) ld when kdev is given) -> force slots of the records
+template <typename Tin, typename Real>
+__global__ void batch_stage_vec(const Tin *__restrict__ in, const int *__restrict__ kdev, int64_t ld, int64_t ntot,
+                                vec4_t<Real> *__restrict__ rec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntot) return;
+    const Tin *v = kdev ? in + (size_t)(kdev[0] - 1) * ld : in;
+    vec4_t<Real> r;
+    r.x = (Real)v[3 * i];
+    r.y = (Real)v[3 * i + 1];
+    r.z = (Real)v[3 * i + 2];
+    r.w = Real(0);
+    rec[2 * i + 1] = r;
+}
+
+// ---------------------------------------------------------------------------
+// segmented float64 vector kernels (block b covers [blk_lo[b], blk_hi[b]) of system blk_sys[b])
+// ---------------------------------------------------------------------------
+struct SegMap {
+    const int *sys;
+    const int64_t *lo, *hi;
+};
+
+__device__ __forceinline__ bool seg_skip(const SegMap &m, const int *active, int &s, int64_t &lo, int64_t &hi) {
+    s = m.sys[blockIdx.x];
+    lo = m.lo[blockIdx.x];
+    hi = m.hi[blockIdx.x];
+    return active[s] == 0;
+}
+
+// partial[b] = sum of w*w (or of in*in for the caller's W) over block b
+template <typename Tin>
+__global__ void seg_sumsq(const Tin *__restrict__ v, SegMap m, double *__restrict__ partial) {
+    __shared__ double sh[kSegThreads];
+    const int64_t lo = m.lo[blockIdx.x], hi = m.hi[blockIdx.x];
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const double x = (double)v[i];
+        acc = fma(x, x, acc);
+    }
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// out[s * ostride + (kdev ? kdev[0] - 1 : 0)] = sum (or sqrt of the sum) of the partials of system s
+__global__ void seg_sys_reduce(const double *__restrict__ partial, const int *__restrict__ b0,
+                               const int *__restrict__ b1, int nsys, const int *__restrict__ active,
+                               const int *__restrict__ kdev, double *__restrict__ out, int64_t ostride,
+                               int take_sqrt) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys || (active && active[s] == 0)) return;
+    double acc = 0.0;
+    for (int b = b0[s]; b < b1[s]; ++b) acc += partial[b];
+    const int col = kdev ? kdev[0] - 1 : 0;
+    out[(size_t)s * ostride + col] = take_sqrt ? sqrt(acc) : acc;
+}
+
+// v1 = W / beta0 (system-wise)
+template <typename Tin>
+__global__ void seg_init_basis(double *__restrict__ v, const Tin *__restrict__ w, SegMap m,
+                               const double *__restrict__ status, const int *__restrict__ active) {
+    int s;
+    int64_t lo, hi;
+    if (seg_skip(m, active, s, lo, hi)) return;
+    const double inv = 1.0 / status[(size_t)s * BS_SIZE + BS_BETA0];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) v[i] = (double)w[i] * inv;
+}
+
+// w -= beta_{k-1} v_{k-1} (k > 1), then partial[b] = v_k . w over the block
+__global__ void seg_recur_dot(double *__restrict__ w, const double *__restrict__ V, int64_t ld,
+                              const double *__restrict__ beta, int64_t lstride, SegMap m,
+                              const int *__restrict__ active, const int *__restrict__ kdev,
+                              double *__restrict__ partial) {
+    __shared__ double sh[kSegThreads];
+    int s;
+    int64_t lo, hi;
+    if (seg_skip(m, active, s, lo, hi)) return;
+    const int k = kdev[0];
+    const double *vk = V + (size_t)(k - 1) * ld;
+    const double *vp = k > 1 ? V + (size_t)(k - 2) * ld : nullptr;
+    const double bp = k > 1 ? beta[(size_t)s * lstride + k - 2] : 0.0;
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        double x = w[i];
+        if (vp) x = fma(-bp, vp[i], x);
+        w[i] = x;
+        acc = fma(vk[i], x, acc);
+    }
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// w -= alpha_k v_k
+__global__ void seg_sub_alpha(double *__restrict__ w, const double *__restrict__ V, int64_t ld,
+                              const double *__restrict__ alpha, int64_t lstride, SegMap m,
+                              const int *__restrict__ active, const int *__restrict__ kdev) {
+    int s;
+    int64_t lo, hi;
+    if (seg_skip(m, active, s, lo, hi)) return;
+    const int k = kdev[0];
+    const double *vk = V + (size_t)(k - 1) * ld;
+    const double a = alpha[(size_t)s * lstride + k - 1];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) w[i] = fma(-a, vk[i], w[i]);
+}
+
+// partial[b * kcap + j] = V[j][block] . w[block], j < k (eight columns per barrier)
+__global__ void __launch_bounds__(kSegThreads)
+seg_gemv_t_partial(const double *__restrict__ V, int64_t ld, const double *__restrict__ w, SegMap m,
+                   const int *__restrict__ active, const int *__restrict__ kdev, int kcap,
+                   double *__restrict__ partial) {
+    constexpr int kCols = 8;
+    constexpr int kWaves = kSegThreads / 64;
+    __shared__ double sh[kCols][kWaves];
+    int s;
+    int64_t lo, hi;
+    if (seg_skip(m, active, s, lo, hi)) return;
+    const int k = kdev[0];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int j0 = 0; j0 < k; j0 += kCols) {
+        const int nc = min(kCols, k - j0);
+        double acc[kCols];
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) acc[c] = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+            const double wi = w[i];
+#pragma unroll
+            for (int c = 0; c < kCols; ++c)
+                if (c < nc) acc[c] = fma(V[(size_t)(j0 + c) * ld + i], wi, acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) {
+            const double v = wave_sum(acc[c]);
+            if (lane == 0) sh[c][wv] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < nc) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) t += sh[threadIdx.x][q];
+            partial[(size_t)blockIdx.x * kcap + j0 + threadIdx.x] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// h[s * lstride + j] = sum over the blocks of system s of partial[b * kcap + j]
+__global__ void seg_gemv_t_final(const double *__restrict__ partial, const int *__restrict__ b0,
+                                 const int *__restrict__ b1, const int *__restrict__ active,
+                                 const int *__restrict__ kdev, int kcap, double *__restrict__ h, int64_t lstride) {
+    const int s = blockIdx.x;
+    if (active[s] == 0) return;
+    const int k = kdev[0];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        double acc = 0.0;
+        for (int b = b0[s]; b < b1[s]; ++b) acc += partial[(size_t)b * kcap + j];
+        h[(size_t)s * lstride + j] = acc;
+    }
+}
+
+// w -= V_k h_s over the block
+__global__ void seg_gemv_n_sub(const double *__restrict__ V, int64_t ld, const double *__restrict__ h,
+                               int64_t lstride, double *__restrict__ w, SegMap m, const int *__restrict__ active,
+                               const int *__restrict__ kdev) {
+    __shared__ double hs[kMaxK];
+    int s;
+    int64_t lo, hi;
+    if (seg_skip(m, active, s, lo, hi)) return;
+    const int k = kdev[0];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) hs[j] = h[(size_t)s * lstride + j];
+    __syncthreads();
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        double acc = 0.0;
+        for (int j = 0; j < k; ++j) acc = fma(V[(size_t)j * ld + i], hs[j], acc);
+        w[i] -= acc;
+    }
+}
+
+// partial[b] = w . w over the block
+__global__ void seg_norm_partial(const double *__restrict__ w, SegMap m, const int *__restrict__ active,
+                                 double *__restrict__ partial) {
+    __shared__ double sh[kSegThreads];
+    int s;
+    int64_t lo, hi;
+    if (seg_skip(m, active, s, lo, hi)) return;
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) acc = fma(w[i], w[i], acc);
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// running max(|alpha|, beta) and first breakdown per system; reaching the
+// system's dimension 3N_s (the whole space) counts as a breakdown too
+__global__ void seg_finish_iter(const double *__restrict__ alpha, const double *__restrict__ beta, int64_t lstride,
+                                int nsys, const int *__restrict__ active, const int *__restrict__ kdev,
+                                const int *__restrict__ dim_sys, double *__restrict__ status) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys || active[s] == 0) return;
+    const int k = kdev[0];
+    double *st = status + (size_t)s * BS_SIZE;
+    const double a = fabs(alpha[(size_t)s * lstride + k - 1]), b = beta[(size_t)s * lstride + k - 1];
+    const double sc = fmax(st[BS_TSCALE], fmax(a, b));
+    st[BS_TSCALE] = sc;
+    if (st[BS_BREAK] == 0.0 && (!(b > 1e-14 * sc) || k >= dim_sys[s])) st[BS_BREAK] = (double)k;
+}
+
+// V[k] = w / beta_k, or zeros after a breakdown
+__global__ void seg_next_basis(double *__restrict__ V, int64_t ld, const double *__restrict__ w,
+                               const double *__restrict__ beta, int64_t lstride, const double *__restrict__ status,
+                               SegMap m, const int *__restrict__ active, const int *__restrict__ kdev) {
+    int s;
+    int64_t lo, hi;
+    if (seg_skip(m, active, s, lo, hi)) return;
+    const int k = kdev[0];
+    const bool broken = status[(size_t)s * BS_SIZE + BS_BREAK] != 0.0;
+    const double inv = broken ? 0.0 : 1.0 / beta[(size_t)s * lstride + k - 1];
+    double *dst = V + (size_t)k * ld;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) dst[i] = broken ? 0.0 : w[i] * inv;
+}
+
+__global__ void advance_k(int *kdev) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) kdev[0] += 1;
+}
+
+// eigensolves of T_{kc-1} (workgroup 0) and T_kc (workgroup 1) of every
+// active system, kc = kdev[0] - 1 (the last completed iteration)
+__global__ void __launch_bounds__(kEigThreads)
+batch_tridiag(const double *__restrict__ alpha, const double *__restrict__ beta, int64_t lstride,
+              double *__restrict__ s_prev, double *__restrict__ s_cur, double *__restrict__ Q, int64_t qstride,
+              double *__restrict__ status, const int *__restrict__ active, const int *__restrict__ kdev) {
+    const int s = blockIdx.y;
+    if (active[s] == 0) return;
+    const int kc = kdev[0] - 1;
+    const int kk = kc - 1 + (int)blockIdx.x;
+    if (kk <= 0) return;
+    tridiag_sqrt_block(alpha + (size_t)s * lstride, beta + (size_t)s * lstride, kk,
+                       (blockIdx.x == 0 ? s_prev : s_cur) + (size_t)s * lstride,
+                       Q + ((size_t)s * 2 + blockIdx.x) * qstride,
+                       blockIdx.x == 1 ? status + (size_t)s * BS_SIZE + BS_NSPD : nullptr);
+}
+
+__global__ void batch_increment(const double *__restrict__ s_prev, const double *__restrict__ s_cur, int64_t lstride,
+                                double *__restrict__ status, const int *__restrict__ active,
+                                const int *__restrict__ kdev) {
+    __shared__ double red[kSegThreads];
+    const int s = blockIdx.x;
+    if (active[s] == 0) return;
+    const int k = kdev[0] - 1;
+    const double *a = s_prev + (size_t)s * lstride, *b = s_cur + (size_t)s * lstride;
+    double num = 0.0, den = 0.0;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        const double prev = (i < k - 1) ? a[i] : 0.0;
+        const double dl = b[i] - prev;
+        num = fma(dl, dl, num);
+        den = fma(b[i], b[i], den);
+    }
+    num = block_sum(num, red);
+    den = block_sum(den, red);
+    if (threadIdx.x == 0) status[(size_t)s * BS_SIZE + BS_INCR] = (k >= 2 && den > 0.0) ? sqrt(num / den) : INFINITY;
+}
+
+// Stopping decisions of every active system after iteration kc; systems
+// that stop are marked in `fresh` for the combine kernel.  kdev[1] receives
+// the number of systems still active.
+__global__ void batch_converge(double *__restrict__ status, int *__restrict__ active, int *__restrict__ fresh,
+                               int kcap, int nsys, double tol, int *__restrict__ kdev) {
+    __shared__ int cnt[kSegThreads];
+    const int kc = kdev[0] - 1;
+    int mine = 0;
+    for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
+        if (active[s] == 0) continue;
+        double *st = status + (size_t)s * BS_SIZE;
+        const int kb = (int)st[BS_BREAK];
+        int done = 0;
+        double code = 0.0;
+        if (kb > 0) {
+            done = kb;                   // invariant Krylov space: s_kc = [s_kb; 0]
+        } else if (st[BS_NSPD] != 0.0) {
+            done = kc;
+            code = 2.0;
+        } else if (kc >= 2 && st[BS_INCR] < tol) {
+            done = kc;
+        } else if (kc >= kcap) {
+            done = kc;                   // max_iter reached
+            code = 1.0;
+        }
+        if (done > 0) {
+            st[BS_DONE] = (double)done;
+            st[BS_CODE] = code;
+            active[s] = 0;
+            fresh[s] = 1;
+        } else {
+            ++mine;
+        }
+    }
+    cnt[threadIdx.x] = mine;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) cnt[threadIdx.x] += cnt[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) kdev[1] = cnt[0];
+}
+
+// y_s = prefactor beta0_s V_{k_s} s_s for every system that just stopped
+template <typename Tout>
+__global__ void batch_combine(const double *__restrict__ V, int64_t ld, const double *__restrict__ s_cur,
+                              int64_t lstride, const double *__restrict__ status, const int *__restrict__ fresh,
+                              const double *__restrict__ prefactor, SegMap m, Tout *__restrict__ out) {
+    __shared__ double hs[kMaxK];
+    const int s = m.sys[blockIdx.x];
+    if (fresh[s] == 0) return;
+    const int64_t lo = m.lo[blockIdx.x], hi = m.hi[blockIdx.x];
+    const double *st = status + (size_t)s * BS_SIZE;
+    const int kf = (int)st[BS_DONE];
+    for (int j = threadIdx.x; j < kf; j += blockDim.x) hs[j] = s_cur[(size_t)s * lstride + j];
+    __syncthreads();
+    const double scale = prefactor[0] * st[BS_BETA0];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        double acc = 0.0;
+        for (int j = 0; j < kf; ++j) acc = fma(V[(size_t)j * ld + i], hs[j], acc);
+        out[i] = (Tout)(scale * acc);
+    }
+}
+
+__global__ void clear_ints(int *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// initial activity: systems with W = 0 produce zeros and never run
+__global__ void batch_init_status(double *__restrict__ status, int *__restrict__ active, int *__restrict__ fresh,
+                                  int nsys, int *__restrict__ kdev, int *__restrict__ nonfinite) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s == 0) kdev[0] = 1;
+    if (s >= nsys) return;
+    double *st = status + (size_t)s * BS_SIZE;
+    const double b0 = st[BS_BETA0];
+    if (!isfinite(b0)) atomicAdd(nonfinite, 1);
+    active[s] = (b0 > 0.0 && isfinite(b0)) ? 1 : 0;
+    fresh[s] = 0;
+    for (int q = 1; q < BS_SIZE; ++q) st[q] = 0.0;
+}
+
+template <typename T>
+__global__ void seg_zero_inactive(T *__restrict__ out, SegMap m, const int *__restrict__ active,
+                                  const double *__restrict__ status) {
+    const int s = m.sys[blockIdx.x];
+    if (active[s] != 0 || status[(size_t)s * BS_SIZE + BS_BETA0] != 0.0) return;
+    for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < m.hi[blockIdx.x]; i += blockDim.x) out[i] = T(0);
+}
+
+}  // namespace
+}  // namespace rpy
+
+using namespace rpy;
+
+struct rpy_batch {
+    int nsys = 0;
+    int64_t ntot = 0;
+    rpy_dtype dtype = RPY_F32;
+    std::vector<int64_t> off;
+    std::vector<double> eta, radius;
+    bool have_pos = false;
+    int ntasks = 0, nblk = 0;
+    int max_sys_n = 0;
+    DevBuf d_off, d_kfac, d_pc, d_tasks, d_counter, d_rec, d_flag;
+    DevBuf d_blk_sys, d_blk_lo, d_blk_hi, d_sys_b0, d_sys_b1, d_kmax;
+    DevBuf V, w, lanc, red, Q, status, ints, pref;
+    unsigned *host_u = nullptr;
+    int *host_i = nullptr;
+    std::string err;
+};
+
+namespace {
+
+rpy_status bfail(rpy_batch *b, rpy_status code, const std::string &msg) {
+    if (b) b->err = msg;
+    return code;
+}
+
+rpy_status bhip(rpy_batch *b, hipError_t e, const char *what) {
+    if (b) b->err = std::string("HIP error '") + hipGetErrorString(e) + "' in " + what;
+    return e == hipErrorOutOfMemory ? RPY_ERR_OUT_OF_MEMORY : RPY_ERR_HIP;
+}
+
+#define BHIP(b, expr)                                        \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return bhip((b), e_, #expr);   \
+    } while (0)
+
+SegMap seg_map(const rpy_batch *b) {
+    return SegMap{b->d_blk_sys.as<int>(), b->d_blk_lo.as<int64_t>(), b->d_blk_hi.as<int64_t>()};
+}
+
+unsigned persistent_blocks(int ntasks) {
+    const int waves = std::max(1, ntasks);
+    return (unsigned)std::min((waves + 3) / 4, 256 * 8);
+}
+
+template <typename Real>
+rpy_status batch_mdot_typed(rpy_batch *b, const Real *F, Real *out, hipStream_t st) {
+    hipLaunchKernelGGL((batch_stage_vec<Real, Real>), dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0, st, F,
+                       (const int *)nullptr, (int64_t)0, b->ntot, b->d_rec.as<vec4_t<Real>>());
+    BHIP(b, launch_fill_zero<unsigned>(b->d_counter.as<unsigned>(), 1, st));
+    hipLaunchKernelGGL((batch_pair_kernel<Real, Real>), dim3(persistent_blocks(b->ntasks)), dim3(kBatchBlock), 0, st,
+                       b->d_rec.as<vec4_t<Real>>(), b->d_off.as<int64_t>(), b->d_tasks.as<int2>(), b->ntasks,
+                       b->d_counter.as<unsigned>(), b->d_pc.as<PairConst<Real>>(), b->d_kfac.as<double>(),
+                       (const int *)nullptr, out);
+    BHIP(b, hipGetLastError());
+    return RPY_OK;
+}
+
+// Enqueue one Lanczos iteration for all active systems (captured into a graph).
+template <typename Real>
+void enqueue_iteration(rpy_batch *b, int kcap, hipStream_t st) {
+    const int64_t n = 3 * b->ntot;
+    const int64_t ld = (n + 63) / 64 * 64;
+    const int64_t L = kcap + 1;
+    double *lan = b->lanc.as<double>();
+    double *alpha = lan, *beta = lan + b->nsys * L, *h = lan + 2 * b->nsys * L;
+    int *ints = b->ints.as<int>();
+    int *kdev = ints, *active = ints + 2;
+    const SegMap m = seg_map(b);
+    const dim3 gb((unsigned)b->nblk), tb(kSegThreads);
+    const dim3 gs((unsigned)((b->nsys + 255) / 256));
+    double *V = b->V.as<double>(), *w = b->w.as<double>(), *red = b->red.as<double>();
+    // w = M v_k (only active systems' tasks do work)
+    hipLaunchKernelGGL((batch_stage_vec<double, Real>), dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0, st, V,
+                       kdev, ld, b->ntot, b->d_rec.as<vec4_t<Real>>());
+    hipLaunchKernelGGL(clear_ints, dim3(1), dim3(64), 0, st, (int *)b->d_counter.p, 1);
+    hipLaunchKernelGGL((batch_pair_kernel<Real, double>), dim3(persistent_blocks(b->ntasks)), dim3(kBatchBlock), 0, st,
+                       b->d_rec.as<vec4_t<Real>>(), b->d_off.as<int64_t>(), b->d_tasks.as<int2>(), b->ntasks,
+                       b->d_counter.as<unsigned>(), b->d_pc.as<PairConst<Real>>(), b->d_kfac.as<double>(), active, w);
+    // recurrence
+    hipLaunchKernelGGL(seg_recur_dot, gb, tb, 0, st, w, V, ld, beta, L, m, active, kdev, red);
+    hipLaunchKernelGGL(seg_sys_reduce, gs, dim3(256), 0, st, red, b->d_sys_b0.as<int>(), b->d_sys_b1.as<int>(),
+                       b->nsys, active, kdev, alpha, L, 0);
+    hipLaunchKernelGGL(seg_sub_alpha, gb, tb, 0, st, w, V, ld, alpha, L, m, active, kdev);
+    for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL(seg_gemv_t_partial, gb, tb, 0, st, V, ld, w, m, active, kdev, kcap, red);
+        hipLaunchKernelGGL(seg_gemv_t_final, dim3((unsigned)b->nsys), dim3(256), 0, st, red, b->d_sys_b0.as<int>(),
+                           b->d_sys_b1.as<int>(), active, kdev, kcap, h, L);
+        hipLaunchKernelGGL(seg_gemv_n_sub, gb, tb, 0, st, V, ld, h, L, w, m, active, kdev);
+    }
+    hipLaunchKernelGGL(seg_norm_partial, gb, tb, 0, st, w, m, active, red);
+    hipLaunchKernelGGL(seg_sys_reduce, gs, dim3(256), 0, st, red, b->d_sys_b0.as<int>(), b->d_sys_b1.as<int>(),
+                       b->nsys, active, kdev, beta, L, 1);
+    hipLaunchKernelGGL(seg_finish_iter, gs, dim3(256), 0, st, alpha, beta, L, b->nsys, active, kdev,
+                       b->d_kmax.as<int>(), b->status.as<double>());
+    hipLaunchKernelGGL(seg_next_basis, gb, tb, 0, st, V, ld, w, beta, L, b->status.as<double>(), m, active, kdev);
+    hipLaunchKernelGGL(advance_k, dim3(1), dim3(64), 0, st, kdev);
+}
+
+// Enqueue the per-system check: eigensolves, increments, stopping, output of stopped systems.
+template <typename Tout>
+void enqueue_check(rpy_batch *b, int kcap, double tol, Tout *out, hipStream_t st) {
+    const int64_t n = 3 * b->ntot;
+    const int64_t ld = (n + 63) / 64 * 64;
+    const int64_t L = kcap + 1;
+    double *lan = b->lanc.as<double>();
+    double *alpha = lan, *beta = lan + b->nsys * L;
+    double *s_prev = lan + 3 * b->nsys * L, *s_cur = lan + 4 * b->nsys * L;
+    int *ints = b->ints.as<int>();
+    int *kdev = ints, *active = ints + 2, *fresh = ints + 2 + b->nsys;
+    const SegMap m = seg_map(b);
+    hipLaunchKernelGGL(batch_tridiag, dim3(2, (unsigned)b->nsys), dim3(kEigThreads), 0, st, alpha, beta, L, s_prev,
+                       s_cur, b->Q.as<double>(), (int64_t)kcap * kcap, b->status.as<double>(), active, kdev);
+    hipLaunchKernelGGL(batch_increment, dim3((unsigned)b->nsys), dim3(kSegThreads), 0, st, s_prev, s_cur, L,
+                       b->status.as<double>(), active, kdev);
+    hipLaunchKernelGGL(batch_converge, dim3(1), dim3(kSegThreads), 0, st, b->status.as<double>(), active, fresh, kcap,
+                       b->nsys, tol, kdev);
+    hipLaunchKernelGGL((batch_combine<Tout>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, b->V.as<double>(), ld,
+                       s_cur, L, b->status.as<double>(), fresh, b->pref.as<double>(), m, out);
+    hipLaunchKernelGGL(clear_ints, dim3((unsigned)((b->nsys + 255) / 256)), dim3(256), 0, st, fresh, b->nsys);
+}
+
+template <typename Real>
+rpy_status batch_sqrt_typed(rpy_batch *b, const Real *w_in, double prefactor, double tol, int max_iter,
+                            int check_every, Real *out, int *iters_out, hipStream_t st) {
+    const int64_t n = 3 * b->ntot;
+    const int64_t ld = (n + 63) / 64 * 64;
+    const int kcap = std::min({max_iter, kMaxK, 3 * b->max_sys_n});
+    const int64_t L = kcap + 1;
+    BHIP(b, b->V.ensure((size_t)(kcap + 1) * ld * sizeof(double)));
+    BHIP(b, b->w.ensure((size_t)ld * sizeof(double)));
+    BHIP(b, b->lanc.ensure((size_t)5 * b->nsys * L * sizeof(double)));
+    BHIP(b, b->red.ensure((size_t)b->nblk * std::max(kcap, 1) * sizeof(double)));
+    BHIP(b, b->Q.ensure((size_t)b->nsys * 2 * kcap * kcap * sizeof(double)));
+    BHIP(b, b->status.ensure((size_t)b->nsys * BS_SIZE * sizeof(double)));
+    BHIP(b, b->ints.ensure((size_t)(3 + 2 * b->nsys) * sizeof(int)));
+    BHIP(b, b->pref.ensure(sizeof(double)));
+    int *ints = b->ints.as<int>();
+    int *kdev = ints, *active = ints + 2, *fresh = ints + 2 + b->nsys, *nonfin = ints + 2 + 2 * b->nsys;
+    const SegMap m = seg_map(b);
+    // per-system dimension 3 N_s (the Krylov space cannot grow beyond it)
+    {
+        std::vector<int> dims(b->nsys);
+        for (int s = 0; s < b->nsys; ++s) dims[s] = (int)(3 * (b->off[s + 1] - b->off[s]));
+        BHIP(b, b->d_kmax.ensure(sizeof(int) * b->nsys));
+        BHIP(b, hipMemcpy(b->d_kmax.p, dims.data(), sizeof(int) * b->nsys, hipMemcpyHostToDevice));
+    }
+    BHIP(b, hipMemcpy(b->pref.p, &prefactor, sizeof(double), hipMemcpyHostToDevice));
+    // beta0 per system, activity, v1
+    hipLaunchKernelGGL(clear_ints, dim3(1), dim3(64), 0, st, nonfin, 1);
+    hipLaunchKernelGGL((seg_sumsq<Real>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, w_in, m, b->red.as<double>());
+    hipLaunchKernelGGL(seg_sys_reduce, dim3((unsigned)((b->nsys + 255) / 256)), dim3(256), 0, st, b->red.as<double>(),
+                       b->d_sys_b0.as<int>(), b->d_sys_b1.as<int>(), b->nsys, (const int *)nullptr,
+                       (const int *)nullptr, b->status.as<double>(), (int64_t)BS_SIZE, 1);
+    hipLaunchKernelGGL(batch_init_status, dim3((unsigned)((b->nsys + 255) / 256)), dim3(256), 0, st,
+                       b->status.as<double>(), active, fresh, b->nsys, kdev, nonfin);
+    hipLaunchKernelGGL((seg_zero_inactive<Real>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, out, m, active,
+                       b->status.as<double>());
+    hipLaunchKernelGGL((seg_init_basis<Real>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, b->V.as<double>(),
+                       w_in, m, b->status.as<double>(), active);
+    BHIP(b, hipGetLastError());
+    BHIP(b, hipMemcpyAsync(b->host_i, nonfin, sizeof(int), hipMemcpyDeviceToHost, st));
+    BHIP(b, hipStreamSynchronize(st));
+    if (b->host_i[0] != 0) return bfail(b, RPY_ERR_NONFINITE, "the noise vector W is not finite");
+
+    // capture one iteration and one check as graphs
+    hipStream_t cap = nullptr;
+    BHIP(b, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t g_iter = nullptr, g_check = nullptr;
+    hipGraphExec_t x_iter = nullptr, x_check = nullptr;
+    auto cleanup = [&]() {
+        if (x_iter) (void)hipGraphExecDestroy(x_iter);
+        if (x_check) (void)hipGraphExecDestroy(x_check);
+        if (g_iter) (void)hipGraphDestroy(g_iter);
+        if (g_check) (void)hipGraphDestroy(g_check);
+        (void)hipStreamDestroy(cap);
+    };
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        enqueue_iteration<Real>(b, kcap, cap);
+        e = hipStreamEndCapture(cap, &g_iter);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&x_iter, g_iter, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        enqueue_check<Real>(b, kcap, tol, out, cap);
+        e = hipStreamEndCapture(cap, &g_check);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&x_check, g_check, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        cleanup();
+        return bhip(b, e, "graph capture of the batched Lanczos iteration");
+    }
+    int n_active = 1;
+    for (int k = 1; k <= kcap && n_active > 0; ++k) {
+        e = hipGraphLaunch(x_iter, st);
+        if (e == hipSuccess && ((k >= 2 && k % check_every == 0) || k == kcap)) {
+            e = hipGraphLaunch(x_check, st);
+            if (e == hipSuccess) e = hipMemcpyAsync(b->host_i, kdev + 1, sizeof(int), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e == hipSuccess) n_active = b->host_i[0];
+        }
+        if (e != hipSuccess) {
+            cleanup();
+            return bhip(b, e, "batched Lanczos iteration");
+        }
+    }
+    cleanup();
+    // per-system iteration counts and codes
+    std::vector<double> stat((size_t)b->nsys * BS_SIZE);
+    BHIP(b, hipMemcpyAsync(stat.data(), b->status.p, stat.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    BHIP(b, hipStreamSynchronize(st));
+    bool nconv = false, nspd = false;
+    for (int s = 0; s < b->nsys; ++s) {
+        if (iters_out) iters_out[s] = (int)stat[(size_t)s * BS_SIZE + BS_DONE];
+        const double c = stat[(size_t)s * BS_SIZE + BS_CODE];
+        if (c == 1.0) nconv = true;
+        if (c == 2.0) nspd = true;
+    }
+    if (nspd) return bfail(b, RPY_ERR_NOT_SPD, "a system's mobility matrix is not positive definite");
+    if (nconv) return bfail(b, RPY_ERR_NOT_CONVERGED, "some systems did not converge within max_iter");
+    return RPY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rpy_status rpy_batch_create(int32_t n_systems, const int64_t *offsets, const double *viscosity, const double *radius,
+                            rpy_dtype dtype, rpy_batch **out) {
+    if (!out) return RPY_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n_systems <= 0 || !offsets || !viscosity || !radius) return RPY_ERR_INVALID_ARG;
+    if (dtype != RPY_F32 && dtype != RPY_F64) return RPY_ERR_DTYPE_MISMATCH;
+    if (offsets[0] != 0) return RPY_ERR_SIZE_MISMATCH;
+    for (int s = 0; s < n_systems; ++s) {
+        if (offsets[s + 1] <= offsets[s]) return RPY_ERR_SIZE_MISMATCH;
+        if (offsets[s + 1] - offsets[s] > (1 << 24)) return RPY_ERR_SIZE_MISMATCH;
+        if (!(viscosity[s] > 0.0) || !std::isfinite(viscosity[s]) || !(radius[s] > 0.0) || !std::isfinite(radius[s]))
+            return RPY_ERR_INVALID_ARG;
+    }
+    if (offsets[n_systems] > (int64_t)(1 << 30)) return RPY_ERR_SIZE_MISMATCH;
+    rpy_batch *b = new (std::nothrow) rpy_batch();
+    if (!b) return RPY_ERR_OUT_OF_MEMORY;
+    b->nsys = n_systems;
+    b->dtype = dtype;
+    b->off.assign(offsets, offsets + n_systems + 1);
+    b->eta.assign(viscosity, viscosity + n_systems);
+    b->radius.assign(radius, radius + n_systems);
+    b->ntot = offsets[n_systems];
+    // task list: (system, 64-target tile), longest systems first
+    std::vector<int> order(n_systems);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (b->off[x + 1] - b->off[x]) > (b->off[y + 1] - b->off[y]);
+    });
+    std::vector<int2> tasks;
+    for (int s : order) {
+        const int64_t ns = b->off[s + 1] - b->off[s];
+        b->max_sys_n = std::max<int>(b->max_sys_n, (int)ns);
+        for (int64_t t = 0; t < (ns + 63) / 64; ++t) tasks.push_back(make_int2(s, (int)t));
+    }
+    b->ntasks = (int)tasks.size();
+    // segmented blocks over the 3N-entry vectors
+    std::vector<int> bsys, b0(n_systems), b1(n_systems);
+    std::vector<int64_t> blo, bhi;
+    for (int s = 0; s < n_systems; ++s) {
+        b0[s] = (int)bsys.size();
+        for (int64_t lo = 3 * b->off[s]; lo < 3 * b->off[s + 1]; lo += kSegChunk) {
+            bsys.push_back(s);
+            blo.push_back(lo);
+            bhi.push_back(std::min<int64_t>(lo + kSegChunk, 3 * b->off[s + 1]));
+        }
+        b1[s] = (int)bsys.size();
+    }
+    b->nblk = (int)bsys.size();
+    std::vector<double> kfac(n_systems);
+    std::vector<PairConst<float>> pcf(n_systems);
+    std::vector<PairConst<double>> pcd(n_systems);
+    for (int s = 0; s < n_systems; ++s) {
+        kfac[s] = 1.0 / (8.0 * M_PI * viscosity[s]);
+        pcf[s] = make_pair_const<float>(radius[s]);
+        pcd[s] = make_pair_const<double>(radius[s]);
+    }
+    auto up = [&](DevBuf &d, const void *src, size_t bytes) -> hipError_t {
+        hipError_t e = d.ensure(bytes);
+        if (e != hipSuccess) return e;
+        return hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice);
+    };
+    hipError_t e = up(b->d_off, b->off.data(), sizeof(int64_t) * (n_systems + 1));
+    if (e == hipSuccess) e = up(b->d_kfac, kfac.data(), sizeof(double) * n_systems);
+    if (e == hipSuccess)
+        e = dtype == RPY_F64 ? up(b->d_pc, pcd.data(), sizeof(PairConst<double>) * n_systems)
+                             : up(b->d_pc, pcf.data(), sizeof(PairConst<float>) * n_systems);
+    if (e == hipSuccess) e = up(b->d_tasks, tasks.data(), sizeof(int2) * tasks.size());
+    if (e == hipSuccess) e = up(b->d_blk_sys, bsys.data(), sizeof(int) * bsys.size());
+    if (e == hipSuccess) e = up(b->d_blk_lo, blo.data(), sizeof(int64_t) * blo.size());
+    if (e == hipSuccess) e = up(b->d_blk_hi, bhi.data(), sizeof(int64_t) * bhi.size());
+    if (e == hipSuccess) e = up(b->d_sys_b0, b0.data(), sizeof(int) * n_systems);
+    if (e == hipSuccess) e = up(b->d_sys_b1, b1.data(), sizeof(int) * n_systems);
+    if (e == hipSuccess) e = b->d_counter.ensure(sizeof(unsigned) * 4);
+    if (e == hipSuccess) e = b->d_flag.ensure(sizeof(unsigned) * 4);
+    const size_t elt = dtype == RPY_F64 ? sizeof(double4) : sizeof(float4);
+    if (e == hipSuccess) e = b->d_rec.ensure(2 * elt * b->ntot);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->host_u, sizeof(unsigned) * 4, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->host_i, sizeof(int) * 4, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        rpy_batch_destroy(b);
+        return e == hipErrorOutOfMemory ? RPY_ERR_OUT_OF_MEMORY : RPY_ERR_HIP;
+    }
+    *out = b;
+    return RPY_OK;
+}
+
+rpy_status rpy_batch_set_positions(rpy_batch *b, const void *pos, void *hip_stream) {
+    if (!b) return RPY_ERR_INVALID_ARG;
+    if (!pos) return bfail(b, RPY_ERR_INVALID_ARG, "positions pointer is NULL");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    b->have_pos = false;
+    BHIP(b, launch_fill_zero<unsigned>(b->d_flag.as<unsigned>(), 1, st));
+    const dim3 g((unsigned)((b->ntot + 255) / 256));
+    if (b->dtype == RPY_F64)
+        hipLaunchKernelGGL((batch_stage_pos<double>), g, dim3(256), 0, st, static_cast<const double *>(pos), b->ntot,
+                           b->d_rec.as<double4>(), b->d_flag.as<unsigned>());
+    else
+        hipLaunchKernelGGL((batch_stage_pos<float>), g, dim3(256), 0, st, static_cast<const float *>(pos), b->ntot,
+                           b->d_rec.as<float4>(), b->d_flag.as<unsigned>());
+    BHIP(b, hipGetLastError());
+    BHIP(b, hipMemcpyAsync(b->host_u, b->d_flag.p, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    BHIP(b, hipStreamSynchronize(st));
+    if (b->host_u[0] != 0) return bfail(b, RPY_ERR_NONFINITE, "particle positions are not finite");
+    b->have_pos = true;
+    b->err.clear();
+    return RPY_OK;
+}
+
+rpy_status rpy_batch_mdot(rpy_batch *b, const void *forces, void *lin_out, void *hip_stream) {
+    if (!b) return RPY_ERR_INVALID_ARG;
+    if (!b->have_pos) return bfail(b, RPY_ERR_NO_POSITIONS, "rpy_batch_set_positions has not been called");
+    if (!forces || !lin_out) return bfail(b, RPY_ERR_INVALID_ARG, "forces and output must not be NULL");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (b->dtype == RPY_F64)
+        return batch_mdot_typed<double>(b, static_cast<const double *>(forces), static_cast<double *>(lin_out), st);
+    return batch_mdot_typed<float>(b, static_cast<const float *>(forces), static_cast<float *>(lin_out), st);
+}
+
+rpy_status rpy_batch_sqrt_mdot_w(rpy_batch *b, const void *w, double prefactor, double tol, int max_iter,
+                                 int check_every, void *lin_out, int *iters_out, void *hip_stream) {
+    if (!b) return RPY_ERR_INVALID_ARG;
+    if (!b->have_pos) return bfail(b, RPY_ERR_NO_POSITIONS, "rpy_batch_set_positions has not been called");
+    if (!w || !lin_out) return bfail(b, RPY_ERR_INVALID_ARG, "W and the output must not be NULL");
+    if (!(tol > 0.0 && tol < 1.0)) return bfail(b, RPY_ERR_INVALID_ARG, "tol must be in (0, 1)");
+    if (max_iter < 1 || max_iter > kMaxK)
+        return bfail(b, RPY_ERR_INVALID_ARG, "max_iter must be in [1, 1024]");
+    if (check_every < 1) return bfail(b, RPY_ERR_INVALID_ARG, "check_every must be >= 1");
+    if (!std::isfinite(prefactor)) return bfail(b, RPY_ERR_INVALID_ARG, "prefactor must be finite");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (b->dtype == RPY_F64)
+        return batch_sqrt_typed<double>(b, static_cast<const double *>(w), prefactor, tol, max_iter, check_every,
+                                        static_cast<double *>(lin_out), iters_out, st);
+    return batch_sqrt_typed<float>(b, static_cast<const float *>(w), prefactor, tol, max_iter, check_every,
+                                   static_cast<float *>(lin_out), iters_out, st);
+}
+
+const char *rpy_batch_last_error(const rpy_batch *b) { return b ? b->err.c_str() : "null batch handle"; }
+
+void rpy_batch_destroy(rpy_batch *b) {
+    if (!b) return;
+    for (DevBuf *d : {&b->d_off, &b->d_kfac, &b->d_pc, &b->d_tasks, &b->d_counter, &b->d_rec, &b->d_flag,
+                      &b->d_blk_sys, &b->d_blk_lo, &b->d_blk_hi, &b->d_sys_b0, &b->d_sys_b1, &b->d_kmax, &b->V,
+                      &b->w, &b->lanc, &b->red, &b->Q, &b->status, &b->ints, &b->pref})
+        d->release();
+    if (b->host_u) (void)hipHostFree(b->host_u);
+    if (b->host_i) (void)hipHostFree(b->host_i);
+    delete b;
+}
+
+}  // extern "C"

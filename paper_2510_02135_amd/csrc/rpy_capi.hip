@@ -3,6 +3,7 @@
 #include "rpy_internal.hpp"
 #include "rpy_solver_ops.hpp"
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -27,8 +28,9 @@ rpy_status hip_fail(rpy_solver *s, hipError_t e, const char *what) {
 double k_factor(const rpy_solver *s) { return 1.0 / (8.0 * M_PI * s->eta); }
 
 int splits_for(const rpy_solver *s, bool ang) {
-    if (s->cfg.n_split > 0) return s->cfg.n_split;
-    return choose_splits(s->n, s->cfg.tm, s->dtype == RPY_F64, ang);
+    const TileConfig &c = s->cfg[ang ? 1 : 0];
+    if (c.n_split > 0) return std::min(c.n_split, max_splits(s->n));
+    return choose_splits(s->n, c.tm, s->dtype == RPY_F64, ang);
 }
 
 // M [F; T] for the stored positions with F, T already staged in s->f / s->t.
@@ -46,9 +48,9 @@ rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *angout, hipStr
     hipEvent_t e0 = timing_begin(s, RPY_KERNEL_PAIR, (double)n * (double)n);
     if (e0) HIP_TRY(s, hipEventRecord(e0, st));
     if (ang)
-        HIP_TRY(s, (launch_pair<Real, true>(pos, f, t, n, pc, s->cfg, splits, s->part.as<Real>(), st)));
+        HIP_TRY(s, (launch_pair<Real, true>(pos, f, t, n, pc, s->cfg[1], splits, s->part.as<Real>(), st)));
     else
-        HIP_TRY(s, (launch_pair<Real, false>(pos, f, nullptr, n, pc, s->cfg, splits, s->part.as<Real>(), st)));
+        HIP_TRY(s, (launch_pair<Real, false>(pos, f, nullptr, n, pc, s->cfg[0], splits, s->part.as<Real>(), st)));
     if (hipEvent_t e1 = timing_end(s, RPY_KERNEL_PAIR)) HIP_TRY(s, hipEventRecord(e1, st));
     if (ang)
         HIP_TRY(s, (launch_reduce<Real, Tout, true>(s->part.as<Real>(), splits, n, k_factor(s), lin, angout, st)));

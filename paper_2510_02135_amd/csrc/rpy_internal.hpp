@@ -65,7 +65,7 @@ inline PairConst<Real> make_pair_const(double a) {
 
 // Tile configuration of the pair kernels.
 struct TileConfig {
-    int tm = 2;          // targets per lane (1 or 2)
+    int tm = 2;          // targets per lane (1, 2 or 4)
     int n_split = 0;     // source splits (0 = choose from N)
 };
 
@@ -103,8 +103,9 @@ hipError_t launch_reduce(const Real *part, int n_split, int64_t n, double k,
 template <typename T>
 hipError_t launch_fill_zero(T *p, int64_t count, hipStream_t st);
 
-// Choice of source splits for n particles.
+// Choice of source splits for n particles; largest useful split count.
 int choose_splits(int64_t n, int tm, bool fp64, bool ang);
+int max_splits(int64_t n);
 int targets_per_block(int tm);
 int source_tile();
 
@@ -119,7 +120,7 @@ struct rpy_solver {
     bool have_pos = false;
     int64_t n = 0;
     rpy_dtype dtype = RPY_F32;
-    rpy::TileConfig cfg;
+    rpy::TileConfig cfg[2];   // pair-kernel tiles for products without / with the angular blocks
     rpy::DevBuf pos, f, t, part, flag;
     // Lanczos workspace (float64): basis, scratch vectors, tridiagonal data
     rpy::DevBuf lz_basis, lz_w, lz_scal, lz_red, lz_q, lz_vec;

@@ -21,6 +21,7 @@
 //         are combined by the reduce kernel.
 //   fp64: plain double sums; 1/sqrt from the hardware estimate refined by
 //         two Newton steps.
+#include "rpy_device.hpp"
 #include "rpy_internal.hpp"
 
 #include <algorithm>
@@ -33,6 +34,8 @@ constexpr int kTile = 256;    // sources per LDS tile (one per thread)
 
 int targets_per_block(int tm) { return kBlock * tm; }
 int source_tile() { return kTile; }
+
+int max_splits(int64_t n) { return (int)std::max<int64_t>(1, (n + kTile - 1) / kTile); }
 
 int choose_splits(int64_t n, int tm, bool fp64, bool ang) {
     (void)fp64;
@@ -64,87 +67,6 @@ void DevBuf::release() {
     if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
-}
-
-// ---------------------------------------------------------------------------
-// device math
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-
-// 1/sqrt(x) in double: hardware estimate, then two Newton steps
-// y <- y + y (1 - x y^2) / 2 (quadratic convergence to full precision).
-__device__ __forceinline__ double rsq(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double h = x * y;
-    double e = fma(-h, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    h = x * y;
-    e = fma(-h, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    return y;
-}
-
-// Neumaier's compensated addition of x into (s, c).
-__device__ __forceinline__ void neumaier(float &s, float &c, float x) {
-    const float t = s + x;
-    const float lost = (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
-    c += lost;
-    s = t;
-}
-
-template <typename Real>
-__device__ __forceinline__ Real sel_pos(Real r2, Real v) { return r2 > Real(0) ? v : Real(0); }
-
-// One source record (position sp, force sf, torque st) acting on target
-// position (xi, yi, zi): adds its contribution to u (and w).
-template <typename Real, bool ANG>
-__device__ __forceinline__ void interact(Real xi, Real yi, Real zi, const vec4_t<Real> &sp,
-                                         const vec4_t<Real> &sf, const vec4_t<Real> &st,
-                                         const PairConst<Real> &c, Real *u, Real *w) {
-    const Real dx = xi - sp.x, dy = yi - sp.y, dz = zi - sp.z;
-    const Real r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const Real ri = rsq(r2);
-    const Real ri2 = ri * ri;
-    const Real ri3 = ri * ri2;
-    const Real ri5 = ri3 * ri2;
-    Real A = fma(c.two_a2_3, ri3, ri);
-    Real B = fma(c.m_two_a2, ri5, ri3);
-    Real G = ri3, D = Real(-0.5) * ri3, E = Real(1.5) * ri5;
-    if (__builtin_expect(r2 < c.four_a2, 0)) {
-        // overlap branch; at r = 0 (self pair) it gives the Stokes drag
-        const Real rs = sel_pos(r2, ri);
-        const Real r = r2 * rs;
-        A = fma(c.nA1, r, c.nA0);
-        B = c.nB * rs;
-        if constexpr (ANG) {
-            G = fma(c.nG1, r, c.nG0);
-            D = fma(fma(c.nD3, r * r, c.nD1), r, c.nD0);
-            E = fma(c.nE_1, rs, c.nE1 * r);
-        }
-    }
-    const Real dF = fma(dx, sf.x, fma(dy, sf.y, dz * sf.z));
-    const Real s = B * dF;
-    u[0] = fma(A, sf.x, fma(s, dx, u[0]));
-    u[1] = fma(A, sf.y, fma(s, dy, u[1]));
-    u[2] = fma(A, sf.z, fma(s, dz, u[2]));
-    if constexpr (ANG) {
-        // U += G (T x d)
-        const Real tx = st.y * dz - st.z * dy;
-        const Real ty = st.z * dx - st.x * dz;
-        const Real tz = st.x * dy - st.y * dx;
-        u[0] = fma(G, tx, u[0]);
-        u[1] = fma(G, ty, u[1]);
-        u[2] = fma(G, tz, u[2]);
-        // W += G (F x d) + D T + E (d.T) d
-        const Real fx = sf.y * dz - sf.z * dy;
-        const Real fy = sf.z * dx - sf.x * dz;
-        const Real fz = sf.x * dy - sf.y * dx;
-        const Real dT = fma(dx, st.x, fma(dy, st.y, dz * st.z));
-        const Real e = E * dT;
-        w[0] = fma(G, fx, fma(D, st.x, fma(e, dx, w[0])));
-        w[1] = fma(G, fy, fma(D, st.y, fma(e, dy, w[1])));
-        w[2] = fma(G, fz, fma(D, st.z, fma(e, dz, w[2])));
-    }
 }
 
 template <typename Real, bool ANG, int TM>
@@ -241,13 +163,16 @@ hipError_t launch_pair(const vec4_t<Real> *pos, const vec4_t<Real> *f, const vec
                        int64_t n, const PairConst<Real> &pc, const TileConfig &cfg, int n_split,
                        Real *part, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    const int tm = cfg.tm == 1 ? 1 : 2;
+    const int tm = (cfg.tm == 1 || cfg.tm == 4) ? cfg.tm : 2;
     const int64_t tpb = targets_per_block(tm);
     int64_t split_len = (n + n_split - 1) / n_split;
     split_len = (split_len + kTile - 1) / kTile * kTile;
     dim3 grid((unsigned)((n + tpb - 1) / tpb), (unsigned)n_split);
     if (tm == 1)
         hipLaunchKernelGGL((pair_kernel<Real, ANG, 1>), grid, dim3(kBlock), 0, st, pos, f, t, (int)n,
+                           (int)split_len, pc, part);
+    else if (tm == 4)
+        hipLaunchKernelGGL((pair_kernel<Real, ANG, 4>), grid, dim3(kBlock), 0, st, pos, f, t, (int)n,
                            (int)split_len, pc, part);
     else
         hipLaunchKernelGGL((pair_kernel<Real, ANG, 2>), grid, dim3(kBlock), 0, st, pos, f, t, (int)n,

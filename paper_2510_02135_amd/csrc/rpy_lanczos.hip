@@ -21,6 +21,7 @@
 //
 // Reductions are two-stage with a fixed block count and fixed order, so the
 // result does not depend on scheduling.
+#include "rpy_device.hpp"
 #include "rpy_internal.hpp"
 #include "rpy_solver_ops.hpp"
 
@@ -35,26 +36,11 @@ namespace {
 
 constexpr int kRedBlocks = 256;    // blocks of the first reduction stage
 constexpr int kRedThreads = 256;
-constexpr int kMaxK = 1024;        // largest tridiagonal the eigensolver takes
-constexpr int kEigThreads = 256;
 
 // status block (double): [0] beta0, [1] relative increment, [2] flags,
 // [3] running max(|alpha|, beta), [4] first breakdown iteration (0 = none)
 enum { ST_BETA0 = 0, ST_INCR = 1, ST_FLAGS = 2, ST_TSCALE = 3, ST_BREAK = 4, ST_SIZE = 8 };
 enum { FLAG_NOT_SPD = 1, FLAG_NONFINITE = 2 };
-
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-    const int t = threadIdx.x;
-    sh[t] = v;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (t < o) sh[t] += sh[t + o];
-        __syncthreads();
-    }
-    const double r = sh[0];
-    __syncthreads();
-    return r;
-}
 
 // partial[b] = sum over the b-th strided slice of a[i] * b[i]
 __global__ void dot_partial(const double *__restrict__ a, const double *__restrict__ b, int64_t n,
@@ -102,12 +88,6 @@ __global__ void sumsq_partial(const Tin *__restrict__ w, int64_t n, double *__re
     }
     const double r = block_sum(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
 }
 
 // partial[b * k + j] = sum over block b's rows of V[j][i] w[i], j < k.
@@ -196,167 +176,16 @@ __global__ void combine_out(const double *__restrict__ V, int64_t ld, int k, con
     }
 }
 
-// One step of a plane rotation pair (c, s) with r = hypot(f, g), without
-// divisions: 1/r from the hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double rhyp(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double h = x * y;
-    double e = fma(-h, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    h = x * y;
-    e = fma(-h, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    return y;
-}
-
-// Eigen-decomposition of the leading kk x kk block of the symmetric
-// tridiagonal T (diagonal alpha, off-diagonal beta) by implicit QL with
-// Wilkinson-type shifts (the textbook tql2 scheme), then
-// s = Q diag(sqrt(max(lambda, 0))) Q^T e_1.  Workgroup b of the launch
-// handles kk = k - 1 + b, so one launch yields s_{k-1} (block 0) and s_k
-// (block 1).  Q lives column-major in global memory (column j = eigenvector
-// j, one coalesced column per rotation step); thread 0 runs the scalar QL
-// recurrences of one sweep and stores its rotations in LDS, then every
-// thread applies them to its rows, carrying the running column in a
-// register so that the loads of a sweep are independent of its stores.
+// s_{k-1} (workgroup 0) and s_k (workgroup 1) of the tridiagonal T_k in one
+// launch; workgroup 1 also records whether T_k is positive definite.
 __global__ void __launch_bounds__(kEigThreads)
 tridiag_sqrt_kernel(const double *__restrict__ alpha, const double *__restrict__ beta, int k,
                     double *__restrict__ s_out0, double *__restrict__ s_out1, double *__restrict__ Qbuf,
                     int64_t qstride, double *__restrict__ status) {
-    __shared__ double d[kMaxK], e[kMaxK];
-    __shared__ double rc[kMaxK], rs[kMaxK];
-    __shared__ int sweep[3];   // lo, m (rotations m-1 .. lo), done flag
-    const int tid = threadIdx.x;
     const int kk = k - 1 + (int)blockIdx.x;
-    double *s_out = blockIdx.x == 0 ? s_out0 : s_out1;
     if (kk <= 0) return;
-    double *Q = Qbuf + (size_t)blockIdx.x * qstride;
-    for (int i = tid; i < kk; i += blockDim.x) {
-        d[i] = alpha[i];
-        e[i] = (i + 1 < kk) ? beta[i] : 0.0;
-    }
-    for (int64_t idx = tid; idx < (int64_t)kk * kk; idx += blockDim.x)
-        Q[idx] = (idx / kk == idx % kk) ? 1.0 : 0.0;
-    __syncthreads();
-
-    int l = 0;
-    int iter = 0;
-    while (true) {
-        if (tid == 0) {
-            int m = l;
-            int done = 0;
-            while (l < kk) {
-                for (m = l; m < kk - 1; ++m) {
-                    const double dd = fabs(d[m]) + fabs(d[m + 1]);
-                    if (fabs(e[m]) <= 2.220446049250313e-16 * dd) break;
-                }
-                if (m != l && iter < 60) break;
-                // eigenvalue l converged (or gave up after 60 sweeps)
-                ++l;
-                iter = 0;
-            }
-            if (l >= kk) {
-                done = 1;
-            } else {
-                ++iter;
-                double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-                double r = sqrt(fma(g, g, 1.0));
-                g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
-                double sn = 1.0, cs = 1.0, p = 0.0;
-                int i;
-                bool underflow = false;
-                double ei = e[m - 1], di = d[m - 1], dip1 = d[m];
-                for (i = m - 1; i >= l; --i) {
-                    // prefetch the next step's (unmodified) entries
-                    const double e_nx = i > l ? e[i - 1] : 0.0;
-                    const double d_nx = i > l ? d[i - 1] : 0.0;
-                    const double f = sn * ei;
-                    const double b = cs * ei;
-                    const double r2 = fma(f, f, g * g);
-                    if (r2 == 0.0) {
-                        d[i + 1] = dip1 - p;
-                        e[m] = 0.0;
-                        underflow = true;
-                        break;
-                    }
-                    const double ri = rhyp(r2);
-                    e[i + 1] = r2 * ri;
-                    sn = f * ri;
-                    cs = g * ri;
-                    g = dip1 - p;
-                    r = (di - g) * sn + 2.0 * cs * b;
-                    p = sn * r;
-                    d[i + 1] = g + p;
-                    g = cs * r - b;
-                    rc[i] = cs;
-                    rs[i] = sn;
-                    dip1 = di;
-                    di = d_nx;
-                    ei = e_nx;
-                }
-                const int lo = underflow ? i + 1 : l;
-                if (!underflow) {
-                    d[l] = dip1 - p;
-                    e[l] = g;
-                    e[m] = 0.0;
-                }
-                sweep[0] = lo;
-                sweep[1] = m;
-            }
-            sweep[2] = done;
-        }
-        __syncthreads();
-        if (sweep[2]) break;
-        const int lo = sweep[0], m = sweep[1];
-        for (int row = tid; row < kk; row += blockDim.x) {
-            double carry = Q[(size_t)m * kk + row];
-            int i = m - 1;
-            for (; i - 3 >= lo; i -= 4) {
-                const double q0 = Q[(size_t)i * kk + row];
-                const double q1 = Q[(size_t)(i - 1) * kk + row];
-                const double q2 = Q[(size_t)(i - 2) * kk + row];
-                const double q3 = Q[(size_t)(i - 3) * kk + row];
-                double nv;
-                nv = fma(rs[i], q0, rc[i] * carry);
-                carry = fma(rc[i], q0, -rs[i] * carry);
-                Q[(size_t)(i + 1) * kk + row] = nv;
-                nv = fma(rs[i - 1], q1, rc[i - 1] * carry);
-                carry = fma(rc[i - 1], q1, -rs[i - 1] * carry);
-                Q[(size_t)i * kk + row] = nv;
-                nv = fma(rs[i - 2], q2, rc[i - 2] * carry);
-                carry = fma(rc[i - 2], q2, -rs[i - 2] * carry);
-                Q[(size_t)(i - 1) * kk + row] = nv;
-                nv = fma(rs[i - 3], q3, rc[i - 3] * carry);
-                carry = fma(rc[i - 3], q3, -rs[i - 3] * carry);
-                Q[(size_t)(i - 2) * kk + row] = nv;
-            }
-            for (; i >= lo; --i) {
-                const double q0 = Q[(size_t)i * kk + row];
-                Q[(size_t)(i + 1) * kk + row] = fma(rs[i], q0, rc[i] * carry);
-                carry = fma(rc[i], q0, -rs[i] * carry);
-            }
-            Q[(size_t)lo * kk + row] = carry;
-        }
-        __syncthreads();
-    }
-
-    // spectrum check (largest block only) and the square root applied to e_1
-    if (blockIdx.x == 1 && tid == 0) {
-        double lmax = -1e308, lmin = 1e308;
-        for (int j = 0; j < kk; ++j) {
-            lmax = fmax(lmax, d[j]);
-            lmin = fmin(lmin, d[j]);
-        }
-        status[ST_FLAGS] = (lmin < -1e-10 * fmax(lmax, 0.0)) ? (double)FLAG_NOT_SPD : 0.0;
-    }
-    // u_j = sqrt(max(lambda_j, 0)) * Q[0][j]  (row 0 of column j)
-    for (int j = tid; j < kk; j += blockDim.x) rc[j] = sqrt(fmax(d[j], 0.0)) * Q[(size_t)j * kk];
-    __syncthreads();
-    for (int row = tid; row < kk; row += blockDim.x) {
-        double acc = 0.0;
-        for (int j = 0; j < kk; ++j) acc = fma(Q[(size_t)j * kk + row], rc[j], acc);
-        s_out[row] = acc;
-    }
+    tridiag_sqrt_block(alpha, beta, kk, blockIdx.x == 0 ? s_out0 : s_out1, Qbuf + (size_t)blockIdx.x * qstride,
+                       blockIdx.x == 1 ? status + ST_FLAGS : nullptr);
 }
 
 // status[ST_INCR] = |s1 - [s0; 0]| / |s1| for s0 of length k-1, s1 of length k.
@@ -531,14 +360,16 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
                 break;
             }
             if (last) break;
-            // next evaluation: a little before the iteration where the observed
-            // geometric decrease of the increment would cross tol
-            int step = std::max(1, k / 4);
+            // next evaluation: half way to the iteration where the observed
+            // geometric decrease of the increment would cross tol (an
+            // evaluation costs less than an iteration, and convergence tends
+            // to accelerate, so the schedule errs early)
+            int step = std::max(1, k / 8);
             if (prev_k > 0 && std::isfinite(incr) && incr > 0.0 && incr < prev_incr) {
                 const double rate = std::log(incr / prev_incr) / (double)(k - prev_k);
                 const double remaining = std::log(tol / incr) / rate;
-                step = (int)std::floor(0.8 * remaining);
-                step = std::max(1, std::min(step, std::max(1, k / 2)));
+                step = (int)std::floor(0.5 * remaining);
+                step = std::max(1, std::min(step, std::max(1, k / 4)));
             }
             prev_k = k;
             prev_incr = incr;

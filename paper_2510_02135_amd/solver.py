@@ -114,9 +114,69 @@ class Solver:
         _lib.rpy_mdot_backward(self._h, f, t, gl, ga, gp, gf, gt, self._dtype, self._n)
         return gp, gf, gt
 
+    # -- tile configuration of the pair kernel ------------------------------
+    def autotune(self, cache_path: str | None = None):
+        """Time the pair-kernel tile candidates at the current N and keep the fastest."""
+        _lib.rpy_autotune(self._h, cache_path)
+        return self.tileConfig(False), (self.tileConfig(True) if self._angular else None)
+
+    def tileConfig(self, angular: bool = False):
+        """(targets per lane, source splits; 0 = automatic)."""
+        return _lib.rpy_get_tile_config(self._h, angular)
+
+    def setTileConfig(self, angular: bool, targets_per_lane: int, source_splits: int = 0):
+        _lib.rpy_set_tile_config(self._h, angular, targets_per_lane, source_splits)
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.rpy_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent open-boundary systems solved together.
+
+    System s owns rows offsets[s]:offsets[s+1] of the concatenated (total, 3)
+    positions / forces / outputs.  Translational blocks only.
+    """
+
+    def __init__(self, offsets, viscosity, radius, dtype=torch.float32, device=None):
+        import numpy as np
+        self.offsets = np.asarray(offsets, dtype=np.int64)
+        self.n_systems = int(self.offsets.shape[0] - 1)
+        self.total = int(self.offsets[-1])
+        vis = np.broadcast_to(np.asarray(viscosity, dtype=np.float64), (self.n_systems,))
+        rad = np.broadcast_to(np.asarray(radius, dtype=np.float64), (self.n_systems,))
+        self._dtype = dtype
+        self._device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self._h = _lib.rpy_batch_create(self.offsets, vis, rad, dtype)
+        self.last_iterations = None
+
+    def setPositions(self, positions: torch.Tensor):
+        _lib.rpy_batch_set_positions(self._h, positions.reshape(-1, 3).contiguous(), self._dtype, self.total)
+
+    def Mdot(self, forces: torch.Tensor):
+        out = torch.empty((self.total, 3), dtype=self._dtype, device=self._device)
+        _lib.rpy_batch_mdot(self._h, forces.reshape(-1, 3).contiguous(), out, self._dtype, self.total)
+        return out
+
+    def sqrtMdotW(self, W: torch.Tensor, prefactor: float = 1.0, tol: float = 1e-6, maxIter: int = 500,
+                  checkEvery: int = 4):
+        out = torch.empty((self.total, 3), dtype=self._dtype, device=self._device)
+        self.last_iterations = _lib.rpy_batch_sqrt_mdot_w(self._h, W.reshape(-1).contiguous(), prefactor, tol,
+                                                          maxIter, checkEvery, out, self._dtype, self.total,
+                                                          self.n_systems)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.rpy_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -101,6 +101,49 @@ def test_call_order_checks(lib):
         lib.rpy_destroy(h)
 
 
+def test_tile_config_accessors(lib):
+    lib.rpy_set_tile_config.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+    lib.rpy_get_tile_config.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                        ctypes.POINTER(ctypes.c_int)]
+    lib.rpy_autotune.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_void_p]
+    h = _solver(lib)
+    try:
+        tm, sp = ctypes.c_int(), ctypes.c_int()
+        assert lib.rpy_get_tile_config(h, 0, ctypes.byref(tm), ctypes.byref(sp)) == OK and (tm.value, sp.value) == (2, 0)
+        assert lib.rpy_set_tile_config(h, 1, 4, 9) == OK
+        assert lib.rpy_get_tile_config(h, 1, ctypes.byref(tm), ctypes.byref(sp)) == OK and (tm.value, sp.value) == (4, 9)
+        assert lib.rpy_set_tile_config(h, 0, 3, 0) == INVALID
+        assert lib.rpy_set_tile_config(h, 0, 2, -1) == INVALID
+        assert lib.rpy_autotune(h, None, None) == NOT_INIT
+        assert lib.rpy_initialize(h, 1.0, 1.0, 1) == OK
+        assert lib.rpy_autotune(h, None, None) == NO_POS
+    finally:
+        lib.rpy_destroy(h)
+
+
+def test_batch_create_checks(lib):
+    import numpy as np
+    P = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
+    lib.rpy_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+    one = np.ones(2)
+    out = ctypes.c_void_p()
+    bad_off = np.array([0, 3, 3], dtype=np.int64)
+    assert lib.rpy_batch_create(2, P(bad_off, ctypes.c_int64), P(one, ctypes.c_double), P(one, ctypes.c_double), 0,
+                                ctypes.byref(out)) == 5
+    off = np.array([1, 3, 4], dtype=np.int64)
+    assert lib.rpy_batch_create(2, P(off, ctypes.c_int64), P(one, ctypes.c_double), P(one, ctypes.c_double), 0,
+                                ctypes.byref(out)) == 5
+    off = np.array([0, 3, 4], dtype=np.int64)
+    neg = np.array([1.0, -1.0])
+    assert lib.rpy_batch_create(2, P(off, ctypes.c_int64), P(neg, ctypes.c_double), P(one, ctypes.c_double), 0,
+                                ctypes.byref(out)) == INVALID
+    assert lib.rpy_batch_create(2, P(off, ctypes.c_int64), P(one, ctypes.c_double), P(one, ctypes.c_double), 7,
+                                ctypes.byref(out)) == DTYPE
+    assert lib.rpy_batch_create(0, P(off, ctypes.c_int64), P(one, ctypes.c_double), P(one, ctypes.c_double), 0,
+                                ctypes.byref(out)) == INVALID
+
+
 def test_python_binding_module_fails_loudly_without_library(tmp_path, monkeypatch):
     import importlib
     import paper_2510_02135_amd._lib as L

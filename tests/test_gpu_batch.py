@@ -1,0 +1,163 @@
+"""GPU parity of the batched solver (many independent systems in one
+persistent launch; Lanczos replayed from captured HIP graphs) against the
+float64 oracle, per system, through the C interface."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import lanczos, mobility, pairloop
+from tests.gpu_util import emax, host, rounded, say, tol_for
+
+pytestmark = pytest.mark.gpu
+DTYPES = [torch.float64, torch.float32]
+
+
+def _systems(sizes, seed, phi=0.15):
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        side = workloads.cube_side(n, phi)
+        x = (rng.random((n, 3)) - 0.5) * side
+        out.append((x, rng.standard_normal((n, 3)), rng.standard_normal(3 * n)))
+    return out
+
+
+def _batch(systems, dtype, eta=None, radius=None):
+    import paper_2510_02135_amd as rpy
+    ns = [len(s[0]) for s in systems]
+    off = np.concatenate([[0], np.cumsum(ns)])
+    eta = np.full(len(ns), 1 / (6 * math.pi)) if eta is None else eta
+    radius = np.ones(len(ns)) if radius is None else radius
+    b = rpy.Batch(off, eta, radius, dtype)
+    pos = torch.tensor(np.concatenate([s[0] for s in systems]), dtype=dtype, device="cuda")
+    b.setPositions(pos)
+    return b, off
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batched_mdot_per_system(dtype):
+    sizes = [1, 2, 3, 64, 65, 130, 257, 300, 17, 511]
+    say(f"case batch mdot sizes={sizes} {dtype}")
+    systems = _systems(sizes, 11)
+    eta = np.linspace(0.5, 1.5, len(sizes))
+    rad = np.linspace(0.7, 1.4, len(sizes))
+    b, off = _batch(systems, dtype, eta, rad)
+    F = torch.tensor(np.concatenate([s[1] for s in systems]), dtype=dtype, device="cuda")
+    U = host(b.Mdot(F))
+    worst = 0.0
+    for k, (x, f, _) in enumerate(systems):
+        u_ref, _ = mobility.mdot_dense(rounded(x, dtype), rounded(f, dtype), None, rad[k], eta[k])
+        e = emax(U[off[k]:off[k + 1]], u_ref)
+        worst = max(worst, e)
+    say(f"  worst system e_max {worst:.3e}")
+    assert worst <= tol_for(dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batched_lanczos_matched_iterations_and_eager_replay(dtype):
+    """Each system against the oracle's Lanczos at the iteration count the
+    batch reports, and against the eager single-system solver stopped at
+    that iteration (every replay of the captured graphs contributes)."""
+    import paper_2510_02135_amd as rpy
+    sizes = [1, 5, 40, 97, 200, 333]
+    say(f"case batch lanczos sizes={sizes} {dtype}")
+    systems = _systems(sizes, 12, phi=0.2)
+    b, off = _batch(systems, dtype)
+    W = torch.tensor(np.concatenate([s[2] for s in systems]), dtype=dtype, device="cuda")
+    Y = host(b.sqrtMdotW(W, prefactor=0.7, tol=1e-6, checkEvery=3)).reshape(-1)
+    iters = b.last_iterations
+    say(f"  iterations {iters}")
+    a, eta = 1.0, 1 / (6 * math.pi)
+    for k, (x, f, w) in enumerate(systems):
+        xr, wr = rounded(x, dtype), rounded(w, dtype)
+        m = mobility.grand_mobility(xr, a, eta)
+        y_ref, _ = lanczos.lanczos_sqrt(lambda v: m @ v, wr, iters=iters[k], prefactor=0.7)
+        y = Y[3 * off[k]:3 * off[k + 1]]
+        e = float(np.abs(y - y_ref).max() / np.abs(y_ref).max())
+        assert e <= (1e-12 if dtype == torch.float64 else 1e-5), (k, e)
+        exact = lanczos.exact_sqrt_mdot_w(m, wr, 0.7)
+        assert np.linalg.norm(y - exact) / np.linalg.norm(exact) <= 1e-5
+        # eager single-system solver stopped at the same iteration
+        sol = rpy.Solver()
+        sol.initialize(viscosity=eta, hydrodynamicRadius=a)
+        sol.setPositions(torch.tensor(x, dtype=dtype, device="cuda"))
+        try:
+            lin, _ = sol.sqrtMdotW(torch.tensor(w, dtype=dtype, device="cuda"), prefactor=0.7, tol=1e-15,
+                                   maxIter=iters[k])
+        except rpy.NotConvergedError as err:
+            lin = err.result[0]
+        ye = host(lin).reshape(-1)
+        e2 = float(np.abs(y - ye).max() / np.abs(ye).max())
+        assert e2 <= (1e-12 if dtype == torch.float64 else 1e-5), (k, e2)
+
+
+def test_batched_repeated_calls_zero_noise_and_errors():
+    import paper_2510_02135_amd as rpy
+    say("case batch repeated / edge cases")
+    systems = _systems([30, 80, 12], 13)
+    b, off = _batch(systems, torch.float64)
+    rng = np.random.default_rng(1)
+    W1 = rng.standard_normal(3 * off[-1])
+    W2 = rng.standard_normal(3 * off[-1])
+    W2[3 * off[1]:3 * off[2]] = 0.0            # second system: zero noise -> zero output
+    t = lambda v: torch.tensor(v, dtype=torch.float64, device="cuda")
+    Y1 = host(b.sqrtMdotW(t(W1))).reshape(-1)
+    Y2 = host(b.sqrtMdotW(t(W2))).reshape(-1)
+    it2 = list(b.last_iterations)
+    Y1b = host(b.sqrtMdotW(t(W1))).reshape(-1)
+    np.testing.assert_array_equal(Y1, Y1b)
+    assert not Y2[3 * off[1]:3 * off[2]].any()
+    assert it2[1] == 0 and it2[0] > 0 and it2[2] > 0
+    for k in (0, 2):
+        x = systems[k][0]
+        m = mobility.grand_mobility(x, 1.0, 1 / (6 * math.pi))
+        y_ref, _ = lanczos.lanczos_sqrt(lambda v: m @ v, W2[3 * off[k]:3 * off[k + 1]], iters=it2[k])
+        assert np.abs(Y2[3 * off[k]:3 * off[k + 1]] - y_ref).max() <= 1e-12 * np.abs(y_ref).max()
+    with pytest.raises(rpy.NotConvergedError):
+        b.sqrtMdotW(t(W1), tol=1e-14, maxIter=4, checkEvery=2)
+    bad = W1.copy()
+    bad[7] = np.nan
+    with pytest.raises(rpy.RpyError):
+        b.sqrtMdotW(t(bad))
+    with pytest.raises(rpy.RpyError):
+        rpy.Batch([0, 5, 5], [1.0, 1.0], [1.0, 1.0])          # empty system
+
+
+def test_c4_512_systems_sampled():
+    """The 512-system workload (N log-uniform in [64, 8192], phi in
+    [0.05, 0.3]): batched Mdot on sampled rows of sampled systems against the
+    C oracle, and batched Lanczos on sampled systems against the oracle's
+    Lanczos (pair-loop products) at the reported iteration count."""
+    import paper_2510_02135_amd as rpy
+    syss = workloads.c4_systems()
+    ns = np.array([s.n for s in syss])
+    off = np.concatenate([[0], np.cumsum(ns)])
+    say(f"case c4 systems={len(syss)} total={off[-1]} sum N^2={float((ns ** 2).sum()):.3e}")
+    dt = torch.float32
+    b = rpy.Batch(off, 1 / (6 * math.pi), 1.0, dt)
+    b.setPositions(torch.tensor(np.concatenate([s.pos for s in syss]), dtype=dt, device="cuda"))
+    F = np.concatenate([s.forces for s in syss])
+    W = np.concatenate([s.w for s in syss])
+    U = host(b.Mdot(torch.tensor(F, dtype=dt, device="cuda")))
+    Y = host(b.sqrtMdotW(torch.tensor(W, dtype=dt, device="cuda"), tol=1e-6)).reshape(-1)
+    iters = np.array(b.last_iterations)
+    say(f"  iterations min {iters.min()} median {int(np.median(iters))} max {iters.max()}")
+    pick = [int(np.argmin(ns)), int(np.argmax(ns)), 5, 77, 300]
+    for k in pick:
+        s = syss[k]
+        xr = rounded(s.pos, dt)
+        rows = np.arange(0, s.n, max(1, s.n // 64))
+        u, _ = pairloop.mdot_rows(xr, rows, rounded(s.forces, dt), None, s.radius, s.viscosity)
+        e = emax(U[off[k]:off[k + 1]][rows], u)
+        assert e <= 1e-5, (k, e)
+        if s.n <= 3000:
+            wr = rounded(s.w, dt)
+            mv = lambda v: pairloop.mdot(xr, v.reshape(-1, 3), None, s.radius, s.viscosity)[0].reshape(-1)
+            y_ref, _ = lanczos.lanczos_sqrt(mv, wr, iters=int(iters[k]))
+            y = Y[3 * off[k]:3 * off[k + 1]]
+            e2 = float(np.abs(y - y_ref).max() / np.abs(y_ref).max())
+            say(f"  system {k} N={s.n} it={iters[k]} mdot {e:.2e} lanczos {e2:.2e}")
+            assert e2 <= 1e-5

@@ -151,3 +151,40 @@ def test_c2_full_size_sampled_rows(dtype):
     e = emax(host(lin)[rows], u)
     say(f"  linear-only e_max {e:.3e}")
     assert e <= tol_for(dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_every_tile_config_and_autotune_keep_parity(dtype, tmp_path):
+    """Results stay within the parity bar for every tile configuration the
+    autotuner may pick; the tuner's cache file round-trips."""
+    import paper_2510_02135_amd as rpy
+    say(f"case tile configs / autotune {dtype}")
+    s = workloads.uniform_cube(1500, 0.1, 55, torques=True)
+    xr, Fr, Tr = rounded(s.pos, dtype), rounded(s.forces, dtype), rounded(s.torques, dtype)
+    u_ref, w_ref = pairloop.mdot(xr, Fr, Tr, s.radius, s.viscosity)
+    u_lin, _ = pairloop.mdot(xr, Fr, None, s.radius, s.viscosity)
+    sol = _solver(True)
+    sol.setPositions(to_dev(s.pos, dtype))
+    F, T = to_dev(s.forces, dtype), to_dev(s.torques, dtype)
+    sol_lin = _solver(False)
+    sol_lin.setPositions(to_dev(s.pos, dtype))
+    for tm in (1, 2, 4):
+        for sp in (0, 1, 3, 6):
+            sol.setTileConfig(True, tm, sp)
+            lin, ang = sol.Mdot(F, T)
+            assert max(emax(host(lin), u_ref), emax(host(ang), w_ref)) <= tol_for(dtype), (tm, sp)
+            sol_lin.setTileConfig(False, tm, sp)
+            lin, _ = sol_lin.Mdot(F)
+            assert emax(host(lin), u_lin) <= tol_for(dtype), (tm, sp)
+    cache = tmp_path / "tiles.txt"
+    cfg_lin, cfg_ang = sol.autotune(str(cache))
+    lines = cache.read_text().strip().splitlines()
+    say(f"  tuned lin {cfg_lin} ang {cfg_ang}; cache {lines}")
+    assert len(lines) == 2 and cfg_lin[1] >= 1 and cfg_ang[1] >= 1
+    lin, ang = sol.Mdot(F, T)
+    assert max(emax(host(lin), u_ref), emax(host(ang), w_ref)) <= tol_for(dtype)
+    other = _solver(True)
+    other.setPositions(to_dev(s.pos, dtype))
+    assert other.autotune(str(cache)) == (cfg_lin, cfg_ang)
+    with pytest.raises(rpy.RpyError):
+        sol.setTileConfig(False, 3, 0)
