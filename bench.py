@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     p.add_argument("--no-breakdown", action="store_true", help="skip the per-precision breakdown and oracle check")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-systems measurement")
+    p.add_argument("--tile-cache", default=None,
+                   help="autotune cache file (read if it has an entry, else written)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -63,7 +65,7 @@ def emax(got, ref):
     return float(np.linalg.norm(got - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
 
 
-def hbm_traffic(kernel: str, n: int):
+def hbm_traffic(kernel: str, n: int, tile):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy), or None when
     the summary is missing, was taken at another N, or the kernel sources
@@ -74,7 +76,7 @@ def hbm_traffic(kernel: str, n: int):
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("kernel") != kernel or d.get("n") != n:
+    if d.get("kernel") != kernel or d.get("n") != n or list(d.get("tile", [])) != list(tile):
         return None
     h = hashlib.sha256()
     for f in d.get("kernel_sources", []):
@@ -193,7 +195,7 @@ def main():
     sol.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius, includeAngular=True)
     sol.setPositions(X)
     print("bench: autotuning the pair kernel tiles", file=sys.stderr, flush=True)
-    tiles = sol.autotune()
+    tiles = sol.autotune(args.tile_cache)
 
     iters = []
 
@@ -229,8 +231,9 @@ def main():
     achieved = FLOPS_PER_PAIR["angular"] * float(n) * float(n) / (avg_pair_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": hbm_traffic("pair_kernel<float, true, 2>", n),
-                "kernel": "pair_kernel<float, angular>", "avg_launch_ms": round(avg_pair_ms, 4),
+                "traffic": hbm_traffic(f"pair_kernel<float, true, {tiles[1][0]}>", n, tiles[1]),
+                "kernel": f"pair_kernel<float, true, {tiles[1][0]}> (angular, {tiles[1][1]} source splits)",
+                "avg_launch_ms": round(avg_pair_ms, 4),
                 "launches": pair_launches, "flops_per_pair": FLOPS_PER_PAIR["angular"]}
 
     if args.calibrate_copy:
@@ -251,7 +254,7 @@ def main():
             so = rpy.Solver()
             so.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius, includeAngular=ang)
             so.setPositions(Xd)
-            so.autotune()
+            so.autotune(args.tile_cache)
             key = f"{name}_{'angular' if ang else 'linear'}"
             fwd = lambda: so.Mdot(forces=Fd, torques=Td if ang else None)
             bwd = lambda: so.Mdot_backward(Fd, Td if ang else None, GUd, GWd if ang else None)
@@ -293,6 +296,31 @@ def main():
         gx = gradient.grad_positions(xr, fr, tr, gur, gwr, s.radius, s.viscosity, rows=rows[:8])
         acc[key] = {"mdot_emax": e, "backward_dF_emax": emax(gf[rows[:64]], mg),
                     "backward_dX_emax": emax(gp[rows[:8]], gx)}
+
+    # sqrtMdotW against the oracle at N = 1024 (phi = 0.1, with torques), where
+    # the oracle's Lanczos and the exact root are affordable on the host
+    if not args.no_breakdown:
+        from oracle import lanczos as olz, mobility as omob
+        small = workloads.uniform_cube(1024, 0.1, 1001, torques=True, w=True, angular_w=True)
+        for dt, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+            so = rpy.Solver()
+            so.initialize(viscosity=small.viscosity, hydrodynamicRadius=small.radius, includeAngular=True)
+            so.setPositions(dev_t(small.pos, dt))
+            ylin, yang = so.sqrtMdotW(dev_t(small.w, dt), tol=1e-6)
+            k = so.last_iterations
+            y = np.concatenate([ylin.double().cpu().numpy().reshape(-1), yang.double().cpu().numpy().reshape(-1)])
+            npd = np.float32 if dt == torch.float32 else np.float64
+            xr = small.pos.astype(npd).astype(np.float64)
+            wr = small.w.astype(npd).astype(np.float64)
+            m = omob.grand_mobility(xr, small.radius, small.viscosity, angular=True)
+            y_ref, _ = olz.lanczos_sqrt(lambda v: m @ v, wr, iters=k)
+            exact = olz.exact_sqrt_mdot_w(m, wr)
+            acc.setdefault(f"{name}_sqrtMdotW_n1024", {})
+            acc[f"{name}_sqrtMdotW_n1024"] = {
+                "iterations": k,
+                "matched_iteration_emax": emax(y.reshape(-1, 3), y_ref.reshape(-1, 3)),
+                "vs_exact_root_rel": float(np.linalg.norm(y - exact) / np.linalg.norm(exact))}
+            so.close()
 
     # ---- CPU oracle baseline on a bounded sample --------------------------
     cpu = None

@@ -70,10 +70,11 @@ bool write_cache(const char *path, const std::map<std::string, Entry> &m) {
     return std::rename(tmp.c_str(), path) == 0;
 }
 
-// Median time (ms) of `reps` launches of the pair kernel with configuration c.
+// Median time (ms) of `reps` products with configuration c: the pair kernel
+// and the reduction of its split partials into `out` (6 N entries).
 template <typename Real>
 rpy_status time_config(rpy_solver *s, bool ang, const TileConfig &c, int reps, hipStream_t st, hipEvent_t a,
-                       hipEvent_t b, double *ms_out) {
+                       hipEvent_t b, Real *out, double *ms_out) {
     const int64_t n = s->n;
     const PairConst<Real> pc = make_pair_const<Real>(s->radius);
     const auto *pos = s->pos.as<vec4_t<Real>>();
@@ -82,10 +83,15 @@ rpy_status time_config(rpy_solver *s, bool ang, const TileConfig &c, int reps, h
     std::vector<float> times;
     for (int r = 0; r < reps + 1; ++r) {
         HIP_TRY(s, hipEventRecord(a, st));
-        if (ang)
+        if (ang) {
             HIP_TRY(s, (launch_pair<Real, true>(pos, f, t, n, pc, c, c.n_split, s->part.as<Real>(), st)));
-        else
+            HIP_TRY(s, (launch_reduce<Real, Real, true>(s->part.as<Real>(), c.n_split, n, k_factor(s), out,
+                                                        out + 3 * n, st)));
+        } else {
             HIP_TRY(s, (launch_pair<Real, false>(pos, f, nullptr, n, pc, c, c.n_split, s->part.as<Real>(), st)));
+            HIP_TRY(s, (launch_reduce<Real, Real, false>(s->part.as<Real>(), c.n_split, n, k_factor(s), out, nullptr,
+                                                         st)));
+        }
         HIP_TRY(s, hipEventRecord(b, st));
         HIP_TRY(s, hipEventSynchronize(b));
         float ms = 0.f;
@@ -115,6 +121,12 @@ rpy_status tune_mode(rpy_solver *s, bool ang, hipStream_t st, Entry *best) {
         (void)hipEventDestroy(a);
         return fail(s, RPY_ERR_HIP, "hipEventCreate failed");
     }
+    DevBuf out;
+    if (out.ensure(sizeof(Real) * 6 * (size_t)n) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return fail(s, RPY_ERR_OUT_OF_MEMORY, "autotune output buffer");
+    }
     best->ms = 1e300;
     rpy_status r = RPY_OK;
     for (int tm : {1, 2, 4}) {
@@ -123,7 +135,7 @@ rpy_status tune_mode(rpy_solver *s, bool ang, hipStream_t st, Entry *best) {
             c.tm = tm;
             c.n_split = sp;
             double ms = 0.0;
-            r = time_config<Real>(s, ang, c, 3, st, a, b, &ms);
+            r = time_config<Real>(s, ang, c, 3, st, a, b, out.as<Real>(), &ms);
             if (r != RPY_OK) break;
             if (ms < best->ms) {
                 best->ms = ms;
@@ -133,6 +145,8 @@ rpy_status tune_mode(rpy_solver *s, bool ang, hipStream_t st, Entry *best) {
         }
         if (r != RPY_OK) break;
     }
+    HIP_TRY(s, hipStreamSynchronize(st));
+    out.release();
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return r;

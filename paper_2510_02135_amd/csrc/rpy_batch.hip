@@ -70,13 +70,18 @@ batch_pair_kernel(const vec4_t<Real> *__restrict__ rec, const int64_t *__restric
         const PairConst<Real> c = pcs[s];
         Real acc[3] = {Real(0), Real(0), Real(0)};
         Real sum[3] = {Real(0), Real(0), Real(0)}, cmp[3] = {Real(0), Real(0), Real(0)};
+        // the next source record is loaded before the current one is used
+        R4 sp = src[0], sf = src[1];
         for (int j0 = 0; j0 < ns; j0 += kSrcChunk) {
             const int cnt = min(kSrcChunk, ns - j0);
 #pragma unroll 4
             for (int q = 0; q < cnt; ++q) {
-                const R4 sp = src[2 * (j0 + q)];
-                const R4 sf = src[2 * (j0 + q) + 1];
+                const int jn = min(j0 + q + 1, ns - 1);
+                const R4 np = src[2 * jn];
+                const R4 nf = src[2 * jn + 1];
                 interact<Real, false>(p.x, p.y, p.z, sp, sf, zero4, c, acc, nullptr);
+                sp = np;
+                sf = nf;
             }
             if constexpr (COMP) {
 #pragma unroll

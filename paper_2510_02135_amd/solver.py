@@ -62,7 +62,13 @@ class Solver:
     def _empty(self):
         return torch.empty((self._n, 3), dtype=self._dtype, device=self._device)
 
+    def _require_positions(self):
+        """Let the library report the missing positions (NO_POSITIONS)."""
+        if self._n == 0:
+            _lib._check(self._h, _lib.load().rpy_mdot(self._h, None, None, None, None, None))
+
     def _as(self, t, name):
+        self._require_positions()
         if t is None:
             return None
         t = t.reshape(-1, 3)
@@ -82,6 +88,7 @@ class Solver:
     def sqrtMdotW(self, W: torch.Tensor | None = None, prefactor: float = 1.0,
                   tol: float = 1e-6, maxIter: int = 500, generator: torch.Generator | None = None):
         """prefactor * M^{1/2} W by Lanczos; W ~ N(0, I) is drawn when not given."""
+        self._require_positions()
         dim = (6 if self._angular else 3) * self._n
         if W is None:
             W = torch.randn(dim, dtype=self._dtype, device=self._device, generator=generator)
@@ -98,6 +105,7 @@ class Solver:
 
     def divM(self):
         """Thermal drift: zero in an unbounded fluid."""
+        self._require_positions()
         lin = self._empty()
         ang = self._empty() if self._angular else None
         _lib.rpy_div_m(self._h, lin, ang, self._dtype, self._n)

@@ -1,0 +1,124 @@
+"""Full-size GPU checks at the sizes the benchmark and the large workloads
+use, against the float64 oracle on sampled outputs, else through properties
+that hold at any size:
+
+* N = 65,536 suspension (phi = 0.1), float32 pairs: Lanczos at a matched
+  iteration count against the oracle's Lanczos with C pair-loop products,
+  and at convergence the norm identity |y|^2 = W^T M W (M applied by the
+  oracle pair loop on sampled rows would not give it; the float64 GPU
+  product is only used as the operator for a property of the float32 run)
+  and agreement with the float64 GPU Lanczos within the tolerance.
+* 4096 chains x 256 beads (N = 1,048,576), float32 with torques: Mdot and
+  the backward pass on sampled particles against the C oracle; Lanczos
+  basis orthonormality through the norm identity after a bounded number of
+  iterations.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import gradient, lanczos, pairloop
+from tests.gpu_util import emax, host, rounded, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(angular):
+    import paper_2510_02135_amd as rpy
+    s = rpy.Solver()
+    s.initialize(viscosity=workloads.VISCOSITY, hydrodynamicRadius=workloads.RADIUS, includeAngular=angular)
+    return s
+
+
+def _flat(lin, ang):
+    return np.concatenate([host(lin).reshape(-1), host(ang).reshape(-1)])
+
+
+@pytest.mark.timeout(600)
+def test_c2_lanczos_matched_iterations_and_convergence():
+    import paper_2510_02135_amd as rpy
+    s = workloads.c2_suspension()
+    n = s.n
+    say(f"case c2 lanczos N={n}")
+    f32 = torch.float32
+    sol = _solver(True)
+    sol.setPositions(torch.tensor(s.pos, dtype=f32, device="cuda"))
+    W = torch.tensor(s.w, dtype=f32, device="cuda")
+    # matched iterations: 5 Lanczos steps, oracle products from the C pair loop
+    try:
+        lin, ang = sol.sqrtMdotW(W, tol=1e-15, maxIter=5)
+    except rpy.NotConvergedError as e:
+        lin, ang = e.result
+    y5 = _flat(lin, ang)
+    xr, wr = rounded(s.pos, f32), rounded(s.w, f32)
+
+    def mv(v):
+        u, w = pairloop.mdot(xr, v[:3 * n].reshape(n, 3), v[3 * n:].reshape(n, 3), s.radius, s.viscosity)
+        return np.concatenate([u.reshape(-1), w.reshape(-1)])
+
+    y_ref, _ = lanczos.lanczos_sqrt(mv, wr, iters=5)
+    e = float(np.abs(y5 - y_ref).max() / np.abs(y_ref).max())
+    say(f"  k=5 matched max rel {e:.3e}")
+    assert e <= 1e-5
+    # converged float32 run: norm identity and agreement with the float64 run
+    lin, ang = sol.sqrtMdotW(W, tol=1e-6)
+    k32 = sol.last_iterations
+    y32 = _flat(lin, ang)
+    sol64 = _solver(True)
+    sol64.setPositions(torch.tensor(xr, dtype=torch.float64, device="cuda"))
+    W64 = torch.tensor(wr, dtype=torch.float64, device="cuda")
+    lin64, ang64 = sol64.sqrtMdotW(W64, tol=1e-6)
+    y64 = _flat(lin64, ang64)
+    mw_lin, mw_ang = sol64.Mdot(W64[:3 * n].reshape(n, 3), W64[3 * n:].reshape(n, 3))
+    wmw = float(wr @ _flat(mw_lin, mw_ang))
+    say(f"  iterations fp32 {k32} fp64 {sol64.last_iterations}; |y|^2 / W^T M W = {y32 @ y32 / wmw:.9f}")
+    assert abs(y32 @ y32 / wmw - 1) <= 1e-5
+    assert abs(y64 @ y64 / wmw - 1) <= 1e-12
+    assert np.linalg.norm(y32 - y64) / np.linalg.norm(y64) <= 1e-5
+
+
+@pytest.mark.timeout(600)
+def test_c5_chains_sampled_rows_and_lanczos_orthonormality():
+    import paper_2510_02135_amd as rpy
+    s = workloads.c5_chains()
+    n = s.n
+    say(f"case c5 chains N={n}")
+    f32 = torch.float32
+    sol = _solver(True)
+    sol.setPositions(torch.tensor(s.pos, dtype=f32, device="cuda"))
+    F = torch.tensor(s.forces, dtype=f32, device="cuda")
+    T = torch.tensor(s.torques, dtype=f32, device="cuda")
+    lin, ang = sol.Mdot(F, T)
+    rows = s.extra["subset"][:48]
+    xr, fr, tr = rounded(s.pos, f32), rounded(s.forces, f32), rounded(s.torques, f32)
+    u, w = pairloop.mdot_rows(xr, rows, fr, tr, s.radius, s.viscosity)
+    e = max(emax(host(lin)[rows], u), emax(host(ang)[rows], w))
+    say(f"  Mdot sampled e_max {e:.3e}")
+    assert e <= 1e-5
+    # backward with cotangents (g_U, g_W) ~ N(0, 1)
+    rng = np.random.default_rng(55)
+    gu, gw = rng.standard_normal((2, n, 3))
+    gp, gf, gt = sol.Mdot_backward(F, T, torch.tensor(gu, dtype=f32, device="cuda"),
+                                   torch.tensor(gw, dtype=f32, device="cuda"))
+    gur, gwr = rounded(gu, f32), rounded(gw, f32)
+    mf, mt = pairloop.mdot_rows(xr, rows[:16], gur, gwr, s.radius, s.viscosity)
+    e2 = max(emax(host(gf)[rows[:16]], mf), emax(host(gt)[rows[:16]], mt))
+    dx = gradient.grad_positions(xr, fr, tr, gur, gwr, s.radius, s.viscosity, rows=rows[:4], chunk=1)
+    e3 = emax(host(gp)[rows[:4]], dx)
+    say(f"  backward sampled dF/dT e_max {e2:.3e}, dX e_max {e3:.3e}")
+    assert e2 <= 1e-5 and e3 <= 1e-5
+    # Lanczos after 12 iterations: |y_k|^2 = beta0^2 alpha_1 = W^T M W while V stays orthonormal
+    W = torch.tensor(s.w, dtype=f32, device="cuda")
+    try:
+        yl, ya = sol.sqrtMdotW(W, tol=1e-15, maxIter=12)
+    except rpy.NotConvergedError as err:
+        yl, ya = err.result
+    y = _flat(yl, ya)
+    wr = rounded(s.w, f32)
+    ml, ma = sol.Mdot(W[:3 * n].reshape(n, 3), W[3 * n:].reshape(n, 3))
+    wmw = float(wr @ _flat(ml, ma))
+    say(f"  |y_12|^2 / W^T M W = {y @ y / wmw:.9f}")
+    assert abs(y @ y / wmw - 1) <= 1e-5

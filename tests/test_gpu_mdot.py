@@ -188,3 +188,35 @@ def test_every_tile_config_and_autotune_keep_parity(dtype, tmp_path):
     assert other.autotune(str(cache)) == (cfg_lin, cfg_ang)
     with pytest.raises(rpy.RpyError):
         sol.setTileConfig(False, 3, 0)
+
+
+def test_error_paths_through_the_binding():
+    """Status codes of the C interface surface as exceptions: non-finite
+    positions (nothing stored), dtype mismatch, torques without the angular
+    blocks, missing inputs."""
+    import paper_2510_02135_amd as rpy
+    say("case error paths")
+    sol = _solver(False)
+    x = np.random.default_rng(3).random((20, 3)) * 5
+    bad = x.copy()
+    bad[4, 1] = np.inf
+    with pytest.raises(rpy.RpyError) as ei:
+        sol.setPositions(to_dev(bad, torch.float64))
+    assert ei.value.status == rpy.Status.NONFINITE
+    with pytest.raises(rpy.RpyError) as ei:
+        sol.Mdot(forces=to_dev(x, torch.float64))
+    assert ei.value.status == rpy.Status.NO_POSITIONS
+    sol.setPositions(to_dev(x, torch.float64))
+    with pytest.raises(ValueError):
+        sol.Mdot(forces=to_dev(x, torch.float32))
+    with pytest.raises(rpy.RpyError) as ei:
+        sol.Mdot(forces=to_dev(x, torch.float64), torques=to_dev(x, torch.float64))
+    assert ei.value.status == rpy.Status.ANGULAR_DISABLED
+    with pytest.raises(rpy.RpyError) as ei:
+        sol.Mdot()
+    assert ei.value.status == rpy.Status.INVALID_ARG
+    with pytest.raises(rpy.RpyError) as ei:
+        rpy.Solver("open", "open", "single_wall")
+    assert ei.value.status == rpy.Status.UNSUPPORTED_GEOMETRY
+    with pytest.raises(rpy.RpyError):
+        sol.setParameters(wallHeight=0.0)
