@@ -183,44 +183,70 @@ hipError_t launch_pair(const vec4_t<Real> *pos, const vec4_t<Real> *f, const vec
 // ---------------------------------------------------------------------------
 // reduction over source splits + epilogue (x k, AoS store)
 // ---------------------------------------------------------------------------
+// One thread per (target i, component c = blockIdx.y); the loads of four
+// splits are issued ahead of the (sequential, fixed-order) compensated sum.
 template <typename Real, typename Tout, bool ANG>
-__global__ void reduce_kernel(const Real *__restrict__ part, int n_split, int n, double k,
-                              Tout *__restrict__ lin, Tout *__restrict__ ang) {
+__global__ void __launch_bounds__(256)
+reduce_kernel(const Real *__restrict__ part, int n_split, int n, double k, Tout *__restrict__ lin,
+              Tout *__restrict__ ang) {
     constexpr int NC = ANG ? 6 : 3;
     constexpr bool COMP = std::is_same<Real, float>::value;
+    constexpr int U = 4;
+    const int c = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n || (c >= 3 && !ang)) return;
     const size_t nn = (size_t)n;
     const size_t stride = (size_t)(COMP ? 2 * NC : NC) * nn;
+    const Real *p0 = part + (size_t)c * nn + i;
+    Tout v;
+    if constexpr (COMP) {
+        const Real *p1 = part + (size_t)(NC + c) * nn + i;
+        float s = 0.f, cp = 0.f, extra = 0.f;
+        int q = 0;
+        for (; q + U <= n_split; q += U) {
+            float x[U], e[U];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        Tout v;
-        if constexpr (COMP) {
-            float s = 0.f, cp = 0.f, extra = 0.f;
-            for (int q = 0; q < n_split; ++q) {
-                neumaier(s, cp, (float)part[q * stride + (size_t)c * nn + i]);
-                extra += (float)part[q * stride + (size_t)(NC + c) * nn + i];
+            for (int u = 0; u < U; ++u) {
+                x[u] = p0[(size_t)(q + u) * stride];
+                e[u] = p1[(size_t)(q + u) * stride];
             }
-            // combine in double, then round once to the output type
-            v = (Tout)(k * ((double)s + ((double)cp + (double)extra)));
-        } else {
-            double s = 0.0;
-            for (int q = 0; q < n_split; ++q) s += (double)part[q * stride + (size_t)c * nn + i];
-            v = (Tout)(k * s);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                neumaier(s, cp, x[u]);
+                extra += e[u];
+            }
         }
-        if (c < 3)
-            lin[3 * (size_t)i + c] = v;
-        else if (ang)
-            ang[3 * (size_t)i + (c - 3)] = v;
+        for (; q < n_split; ++q) {
+            neumaier(s, cp, (float)p0[(size_t)q * stride]);
+            extra += (float)p1[(size_t)q * stride];
+        }
+        // combine in double, then round once to the output type
+        v = (Tout)(k * ((double)s + ((double)cp + (double)extra)));
+    } else {
+        double s = 0.0;
+        int q = 0;
+        for (; q + U <= n_split; q += U) {
+            double x[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[u] = (double)p0[(size_t)(q + u) * stride];
+#pragma unroll
+            for (int u = 0; u < U; ++u) s += x[u];
+        }
+        for (; q < n_split; ++q) s += (double)p0[(size_t)q * stride];
+        v = (Tout)(k * s);
     }
+    if (c < 3)
+        lin[3 * (size_t)i + c] = v;
+    else
+        ang[3 * (size_t)i + (c - 3)] = v;
 }
 
 template <typename Real, typename Tout, bool ANG>
 hipError_t launch_reduce(const Real *part, int n_split, int64_t n, double k, Tout *lin, Tout *ang,
                          hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL((reduce_kernel<Real, Tout, ANG>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                       st, part, n_split, (int)n, k, lin, ang);
+    hipLaunchKernelGGL((reduce_kernel<Real, Tout, ANG>), dim3((unsigned)((n + 255) / 256), ANG ? 6 : 3), dim3(256),
+                       0, st, part, n_split, (int)n, k, lin, ang);
     return hipGetLastError();
 }
 

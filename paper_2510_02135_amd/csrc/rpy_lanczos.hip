@@ -13,11 +13,13 @@
 //     |y_k - y_{k-1}| / |y_k| for y_k = beta_0 V_k s_k because V_k is
 //     orthonormal;
 //   v_{k+1} = w / beta_k.
-// The host reads a 4-double status block after each iteration to decide
+// The host reads a small status block after each iteration to decide
 // whether to stop (first k >= 2 with increment < tol; a clearly negative
 // Ritz value; beta_k ~ 0 meaning the Krylov space is invariant).  The
-// final y = prefactor * beta_0 V_k s_k is formed on the device and written
-// in the caller's dtype.
+// eigensolver runs only at iterations where a cheap quadrature estimate of
+// the increment says the test may pass.  The final
+// y = prefactor * beta_0 V_k s_k is formed on the device and written in the
+// caller's dtype.
 //
 // Reductions are two-stage with a fixed block count and fixed order, so the
 // result does not depend on scheduling.
@@ -38,8 +40,9 @@ constexpr int kRedBlocks = 256;    // blocks of the first reduction stage
 constexpr int kRedThreads = 256;
 
 // status block (double): [0] beta0, [1] relative increment, [2] flags,
-// [3] running max(|alpha|, beta), [4] first breakdown iteration (0 = none)
-enum { ST_BETA0 = 0, ST_INCR = 1, ST_FLAGS = 2, ST_TSCALE = 3, ST_BREAK = 4, ST_SIZE = 8 };
+// [3] running max(|alpha|, beta), [4] first breakdown iteration (0 = none),
+// [5] estimated relative increment (monitor)
+enum { ST_BETA0 = 0, ST_INCR = 1, ST_FLAGS = 2, ST_TSCALE = 3, ST_BREAK = 4, ST_EST = 5, ST_SIZE = 8 };
 enum { FLAG_NOT_SPD = 1, FLAG_NONFINITE = 2 };
 
 // partial[b] = sum over the b-th strided slice of a[i] * b[i]
@@ -91,44 +94,25 @@ __global__ void sumsq_partial(const Tin *__restrict__ w, int64_t n, double *__re
 }
 
 // partial[b * k + j] = sum over block b's rows of V[j][i] w[i], j < k.
-// Block b owns one contiguous slab of rows.  Columns are taken eight at a
-// time: each thread accumulates eight dot products over its rows, the wave
-// reduces them with butterfly shuffles and one barrier combines the waves.
-constexpr int kGemvCols = 8;
+// Block b owns one contiguous slab of rows; each wavefront takes every
+// fourth basis column, accumulates its slab with coalesced loads and
+// reduces across lanes by shuffles, so no workgroup barrier is needed.
+constexpr int kGemvBlocks = 1024;
 __global__ void __launch_bounds__(kRedThreads)
 gemv_t_partial(const double *__restrict__ V, int64_t ld, int k, const double *__restrict__ w, int64_t n,
                double *__restrict__ partial) {
     constexpr int kWaves = kRedThreads / 64;
-    __shared__ double sh[kGemvCols][kWaves];
     int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    chunk = (chunk + blockDim.x - 1) / blockDim.x * blockDim.x;
+    chunk = (chunk + 63) / 64 * 64;
     const int64_t i0 = (int64_t)blockIdx.x * chunk;
     const int64_t i1 = std::min<int64_t>(n, i0 + chunk);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int j0 = 0; j0 < k; j0 += kGemvCols) {
-        double acc[kGemvCols];
-#pragma unroll
-        for (int c = 0; c < kGemvCols; ++c) acc[c] = 0.0;
-        const int nc = std::min(kGemvCols, k - j0);
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
-            const double wi = w[i];
-#pragma unroll
-            for (int c = 0; c < kGemvCols; ++c)
-                if (c < nc) acc[c] = fma(V[(size_t)(j0 + c) * ld + i], wi, acc[c]);
-        }
-#pragma unroll
-        for (int c = 0; c < kGemvCols; ++c) {
-            const double v = wave_sum(acc[c]);
-            if (lane == 0) sh[c][wv] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < nc) {
-            double t = 0.0;
-#pragma unroll
-            for (int q = 0; q < kWaves; ++q) t += sh[threadIdx.x][q];
-            partial[(size_t)blockIdx.x * k + j0 + threadIdx.x] = t;
-        }
-        __syncthreads();
+    for (int j = wv; j < k; j += kWaves) {
+        const double *col = V + (size_t)j * ld;
+        double acc = 0.0;
+        for (int64_t i = i0 + lane; i < i1; i += 64) acc = fma(col[i], w[i], acc);
+        acc = wave_sum(acc);
+        if (lane == 0) partial[(size_t)blockIdx.x * k + j] = acc;
     }
 }
 
@@ -188,9 +172,112 @@ tridiag_sqrt_kernel(const double *__restrict__ alpha, const double *__restrict__
                        blockIdx.x == 1 ? status + ST_FLAGS : nullptr);
 }
 
+// Estimate of s = T^{1/2} e_1 for the leading kk x kk block of the
+// tridiagonal (alpha, beta), without an eigendecomposition; it only decides
+// when the exact test is worth running.  With
+// x^{-1/2} = (1/pi) int exp(u/2) / (x + exp(u)) du over the real line (the
+// substitution t^2 = e^u in the standard integral (2/pi) int_0^inf
+// dt / (x + t^2)), the trapezoid rule with step h gives
+//   T^{1/2} e_1 = T T^{-1/2} e_1 ~ T sum_l w_l (T + c_l I)^{-1} e_1,
+//   c_l = exp(u_l), w_l = (h/pi) exp(u_l/2).
+// The integrand is analytic in the strip |Im u| < pi, so the rule's error
+// falls like exp(-2 pi^2 / h) (about 1e-21 here); the nodes span the
+// Gershgorin bound g of T down to 1e-10 g with a margin of 40 on either side,
+// which leaves truncation terms below 1e-16 relative for eigenvalues in that
+// range.  Thread l < kMonNodes solves (T + c_l I) y = e_1 by the Thomas
+// algorithm (elimination without pivoting is stable for these SPD
+// systems).  Meanwhile one lane of an extra wavefront factors
+// T - 1e-10 g I = L D L^T: a non-positive pivot means T has an eigenvalue
+// below the quadrature's range (or a negative one), and the estimate is then
+// reported as NaN, which sends the caller to the exact test.  Workgroup b
+// handles kk = k-1+b.
+constexpr int kMonNodes = 256;
+constexpr int kMonThreads = kMonNodes + 64;
+__global__ void __launch_bounds__(kMonThreads)
+lanczos_monitor_kernel(const double *__restrict__ alpha, const double *__restrict__ beta, int k,
+                       double *__restrict__ scratch, int64_t sstride, double *__restrict__ est0,
+                       double *__restrict__ est1) {
+    __shared__ double a[kMaxK], b[kMaxK], q[kMaxK];
+    __shared__ double bound;
+    __shared__ int indefinite;
+    const int kk = k - 1 + (int)blockIdx.x;
+    double *est = blockIdx.x == 0 ? est0 : est1;
+    if (kk <= 0) return;
+    const int tid = threadIdx.x;
+    double *bp = scratch + (size_t)blockIdx.x * sstride;   // pivots b'_i, node index fastest
+    double *dp = bp + (size_t)kMaxK * kMonNodes;            // d'_i, then w_l y_i
+    for (int i = tid; i < kk; i += blockDim.x) {
+        a[i] = alpha[i];
+        b[i] = (i + 1 < kk) ? beta[i] : 0.0;
+    }
+    if (tid == 0) indefinite = 0;
+    __syncthreads();
+    if (tid == 0) {
+        double g = 0.0;
+        for (int i = 0; i < kk; ++i) g = fmax(g, a[i] + (i > 0 ? fabs(b[i - 1]) : 0.0) + fabs(b[i]));
+        bound = g > 0.0 ? g : 1.0;
+    }
+    __syncthreads();
+    const int l = tid;
+    if (l >= kMonNodes) {
+        if (l == kMonNodes) {
+            const double shift = 1e-10 * bound;
+            double piv = a[0] - shift;
+            bool pd = piv > 0.0;
+            for (int i = 1; i < kk && pd; ++i) {
+                piv = a[i] - shift - b[i - 1] * (b[i - 1] / piv);
+                pd = piv > 0.0;
+            }
+            if (!pd) indefinite = 1;
+        }
+    } else {
+        const double u_hi = log(bound) + 40.0, u_lo = log(bound) + log(1e-10) - 40.0;
+        const double h = (u_hi - u_lo) / (double)(kMonNodes - 1);
+        const double ul = u_lo + h * l;
+        const double c = exp(ul), wl = h / M_PI * exp(0.5 * ul);
+        // forward elimination
+        double bprev = a[0] + c, dprev = 1.0;
+        bp[l] = bprev;
+        dp[l] = dprev;
+        for (int i = 1; i < kk; ++i) {
+            const double m = b[i - 1] / bprev;
+            bprev = a[i] + c - m * b[i - 1];
+            dprev = -m * dprev;
+            bp[(size_t)i * kMonNodes + l] = bprev;
+            dp[(size_t)i * kMonNodes + l] = dprev;
+        }
+        // back substitution; w_l y_i replaces d'_i
+        double ynext = dprev / bprev;
+        dp[(size_t)(kk - 1) * kMonNodes + l] = wl * ynext;
+        for (int i = kk - 2; i >= 0; --i) {
+            const double y = (dp[(size_t)i * kMonNodes + l] - b[i] * ynext) / bp[(size_t)i * kMonNodes + l];
+            dp[(size_t)i * kMonNodes + l] = wl * y;
+            ynext = y;
+        }
+    }
+    __syncthreads();
+    // q_i = sum_l w_l y_{l,i}: one wavefront per row, coalesced
+    const int lane = tid & 63, wv = tid >> 6;
+    for (int i = wv; i < kk && wv < kMonNodes / 64; i += kMonNodes / 64) {
+        const double *row = dp + (size_t)i * kMonNodes;
+        double acc = 0.0;
+        for (int n = lane; n < kMonNodes; n += 64) acc += row[n];
+        acc = wave_sum(acc);
+        if (lane == 0) q[i] = acc;
+    }
+    __syncthreads();
+    const double poison = indefinite ? NAN : 0.0;
+    for (int i = tid; i < kk; i += blockDim.x) {
+        double v = a[i] * q[i];
+        if (i > 0) v = fma(b[i - 1], q[i - 1], v);
+        if (i + 1 < kk) v = fma(b[i], q[i + 1], v);
+        est[i] = v + poison;
+    }
+}
+
 // status[ST_INCR] = |s1 - [s0; 0]| / |s1| for s0 of length k-1, s1 of length k.
 __global__ void increment_kernel(const double *__restrict__ s0, const double *__restrict__ s1, int k,
-                                 double *__restrict__ status) {
+                                 double *__restrict__ status, int slot) {
     __shared__ double red[kRedThreads];
     double num = 0.0, den = 0.0;
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
@@ -201,7 +288,7 @@ __global__ void increment_kernel(const double *__restrict__ s0, const double *__
     }
     num = block_sum(num, red);
     den = block_sum(den, red);
-    if (threadIdx.x == 0) status[ST_INCR] = (k >= 2 && den > 0.0) ? sqrt(num / den) : INFINITY;
+    if (threadIdx.x == 0) status[slot] = (k >= 2 && den > 0.0) ? sqrt(num / den) : INFINITY;
 }
 
 // After beta_k: track max(|alpha|, beta) and record the first breakdown
@@ -230,6 +317,8 @@ struct LanczosWork {
     int cap = 0;
     double *w = nullptr, *alpha = nullptr, *beta = nullptr, *h = nullptr, *red = nullptr;
     double *s = nullptr, *s_prev = nullptr, *Q = nullptr, *status = nullptr;
+    double *est0 = nullptr, *est1 = nullptr, *mon = nullptr;
+    int64_t mon_stride = 0;
 };
 
 int grid_for(int64_t n) { return (int)std::min<int64_t>(2048, std::max<int64_t>(1, (n + 255) / 256)); }
@@ -251,9 +340,12 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
     const size_t basis_bytes = (size_t)(kmax + 1) * ld * sizeof(double);
     HIP_TRY(s, s->lz_basis.ensure(basis_bytes));
     HIP_TRY(s, s->lz_w.ensure((size_t)ld * sizeof(double)));
-    HIP_TRY(s, s->lz_scal.ensure(sizeof(double) * (ST_SIZE + 6 * (size_t)(kMaxK + 1))));
-    HIP_TRY(s, s->lz_red.ensure(sizeof(double) * (size_t)kRedBlocks * (kMaxK + 1)));
+    HIP_TRY(s, s->lz_scal.ensure(sizeof(double) * (ST_SIZE + 8 * (size_t)(kMaxK + 1))));
+    HIP_TRY(s, s->lz_red.ensure(sizeof(double) * (size_t)kGemvBlocks * (kMaxK + 1)));
     HIP_TRY(s, s->lz_q.ensure(sizeof(double) * 2 * (size_t)kmax * kmax));
+    // monitor scratch: per workgroup, pivots and right-hand sides of kMonNodes systems
+    const int64_t mon_stride = 2 * (int64_t)kMaxK * kMonNodes;
+    HIP_TRY(s, s->lz_mon.ensure(sizeof(double) * 2 * (size_t)mon_stride));
     if (!s->host_scal) HIP_TRY(s, hipHostMalloc((void **)&s->host_scal, sizeof(double) * 8, hipHostMallocDefault));
     LanczosWork L;
     L.V = s->lz_basis.as<double>();
@@ -266,6 +358,10 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
     L.h = L.beta + (kMaxK + 1);
     L.s = L.h + (kMaxK + 1);
     L.s_prev = L.s + (kMaxK + 1);
+    L.est0 = L.s_prev + (kMaxK + 1);
+    L.est1 = L.est0 + (kMaxK + 1);
+    L.mon = s->lz_mon.as<double>();
+    L.mon_stride = mon_stride;
     L.red = s->lz_red.as<double>();
     L.Q = s->lz_q.as<double>();
 
@@ -292,16 +388,17 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
     hipLaunchKernelGGL((init_basis<Tio>), dim3(grid_for(n)), dim3(256), 0, st, L.V, w_in, L.status + ST_BETA0, n);
     HIP_TRY(s, hipGetLastError());
 
-    // The increment test needs s_{k-1} and s_k, both produced by one launch
-    // of the eigensolver; it is evaluated at iterations predicted from the
-    // observed convergence rate (and always at max_iter), and the host only
-    // waits for the device at those iterations.  RPY_LANCZOS_CHECK=every
-    // evaluates it at every iteration.
+    // The increment test needs s_{k-1} and s_k from the eigensolver.  Each
+    // iteration k >= 2 runs the quadrature monitor instead, and the exact
+    // test runs only when the estimated increment is within 1% of tol (or is
+    // not finite, or at max_iter, or after a breakdown), so the loop stops
+    // at the same first k as testing every iteration.  RPY_LANCZOS_CHECK=every
+    // runs the exact test at every iteration.
     const char *check_env = std::getenv("RPY_LANCZOS_CHECK");
     const bool check_every = check_env && std::string(check_env) == "every";
     const int g = grid_for(n);
-    int k = 0, kf = 0, next_check = 2, prev_k = -1;
-    double incr = INFINITY, prev_incr = INFINITY;
+    int k = 0, kf = 0;
+    double incr = INFINITY;
     bool converged = false, not_spd = false;
     for (k = 1; k <= kmax; ++k) {
         const double *vk = L.V + (size_t)(k - 1) * ld;
@@ -325,8 +422,8 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
         hipLaunchKernelGGL(axpy_dev, dim3(g), dim3(256), 0, st, L.w, vk, L.alpha + (k - 1), -1.0, n);
         // classical Gram-Schmidt against V_k, twice
         for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(gemv_t_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, L.V, ld, k, L.w, n, L.red);
-            hipLaunchKernelGGL(gemv_t_final, dim3(k), dim3(kRedThreads), 0, st, L.red, kRedBlocks, k, L.h);
+            hipLaunchKernelGGL(gemv_t_partial, dim3(kGemvBlocks), dim3(kRedThreads), 0, st, L.V, ld, k, L.w, n, L.red);
+            hipLaunchKernelGGL(gemv_t_final, dim3(k), dim3(kRedThreads), 0, st, L.red, kGemvBlocks, k, L.h);
             hipLaunchKernelGGL(gemv_n_sub, dim3(g), dim3(256), 0, st, L.V, ld, k, L.h, L.w, n);
         }
         // beta_k = |w|, breakdown bookkeeping, v_{k+1}
@@ -335,10 +432,23 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
         hipLaunchKernelGGL(finish_iter_kernel, dim3(1), dim3(64), 0, st, L.alpha, L.beta, k, L.status);
         HIP_TRY(s, hipGetLastError());
         const bool last = (k == kmax);
-        if (k >= next_check || last || check_every) {
+        bool exact = last || check_every;
+        if (!exact && k >= 2) {
+            hipLaunchKernelGGL(lanczos_monitor_kernel, dim3(2), dim3(kMonThreads), 0, st, L.alpha, L.beta, k, L.mon,
+                               L.mon_stride, L.est0, L.est1);
+            hipLaunchKernelGGL(increment_kernel, dim3(1), dim3(kRedThreads), 0, st, L.est0, L.est1, k, L.status,
+                               (int)ST_EST);
+            HIP_TRY(s, hipGetLastError());
+            HIP_TRY(s, hipMemcpyAsync(s->host_scal, L.status, sizeof(double) * ST_SIZE, hipMemcpyDeviceToHost, st));
+            HIP_TRY(s, hipStreamSynchronize(st));
+            const double est = s->host_scal[ST_EST];
+            exact = s->host_scal[ST_BREAK] > 0.0 || !std::isfinite(est) || est < tol * 1.01;
+        }
+        if (exact) {
             hipLaunchKernelGGL(tridiag_sqrt_kernel, dim3(2), dim3(kEigThreads), 0, st, L.alpha, L.beta, k, L.s_prev,
                                L.s, L.Q, (int64_t)kmax * kmax, L.status);
-            hipLaunchKernelGGL(increment_kernel, dim3(1), dim3(kRedThreads), 0, st, L.s_prev, L.s, k, L.status);
+            hipLaunchKernelGGL(increment_kernel, dim3(1), dim3(kRedThreads), 0, st, L.s_prev, L.s, k, L.status,
+                               (int)ST_INCR);
             HIP_TRY(s, hipGetLastError());
             HIP_TRY(s, hipMemcpyAsync(s->host_scal, L.status, sizeof(double) * ST_SIZE, hipMemcpyDeviceToHost, st));
             HIP_TRY(s, hipStreamSynchronize(st));
@@ -360,20 +470,6 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
                 break;
             }
             if (last) break;
-            // next evaluation: half way to the iteration where the observed
-            // geometric decrease of the increment would cross tol (an
-            // evaluation costs less than an iteration, and convergence tends
-            // to accelerate, so the schedule errs early)
-            int step = std::max(1, k / 8);
-            if (prev_k > 0 && std::isfinite(incr) && incr > 0.0 && incr < prev_incr) {
-                const double rate = std::log(incr / prev_incr) / (double)(k - prev_k);
-                const double remaining = std::log(tol / incr) / rate;
-                step = (int)std::floor(0.5 * remaining);
-                step = std::max(1, std::min(step, std::max(1, k / 4)));
-            }
-            prev_k = k;
-            prev_incr = incr;
-            next_check = k + step;
         }
         hipLaunchKernelGGL(next_basis_kernel, dim3(g), dim3(256), 0, st, L.V + (size_t)k * ld, L.w, L.beta + (k - 1),
                            L.status, n);
