@@ -18,9 +18,11 @@ Also reported (outside the timed steps, same data): float32 and float64
 pair-interactions/s of one Mdot (translational, and with torques), the
 backward/forward time ratio, the roofline position of the dominant kernel
 (the float32 angular pair kernel, timed with HIP events on its own stream
-inside the timed steps), the max relative error of each result against the
-float64 CPU oracle on sampled particles, and the oracle's own rate on a
-bounded sample of the same workload on the host cores.
+inside the timed steps), the HBM rate of the Lanczos vector operations (the
+Gram-Schmidt passes, timed the same way, algorithmic bytes), the max
+relative error of each result against the float64 CPU oracle on sampled
+particles, and the oracle's own rate on a bounded sample of the same
+workload on the host cores.
 """
 from __future__ import annotations
 
@@ -38,6 +40,7 @@ if ROOT not in sys.path:
 METRIC = "RPY pair-interactions/s for M·F, FP32 vs FP64, N=65,536; backward/forward"
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
 FLOPS_PER_PAIR = {"linear": 34, "angular": 84}
 
 
@@ -147,9 +150,24 @@ def bench_batched(rpy, workloads, dev, stream, timed):
             "per_system_lanczos_iterations_median": float(np.median(it_ps))}
 
 
-def timed(fn, reps, stream):
-    """Median milliseconds of fn() over reps runs, HIP events on `stream`."""
+def host_cpu_model():
+    """The host CPU's model name from /proc/cpuinfo (None if unreadable)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def timed(fn, reps, stream, warmup=0):
+    """Median milliseconds of fn() over reps runs after `warmup` untimed
+    runs, HIP events on `stream`."""
     import torch
+    for _ in range(warmup):
+        fn()
     times = []
     for _ in range(reps):
         a = torch.cuda.Event(enable_timing=True)
@@ -221,6 +239,7 @@ def main():
     elapsed = time.perf_counter() - t0
     pair_ms, pair_launches, pair_pairs = _lib.rpy_kernel_time(sol._h, "pair")
     adj_ms, adj_launches, _ = _lib.rpy_kernel_time(sol._h, "adjoint")
+    cgs_ms, cgs_records, cgs_bytes = _lib.rpy_kernel_time(sol._h, "lanczos_cgs")
     _lib.rpy_enable_timing(sol._h, False)
     ms_per_step = 1e3 * elapsed / args.steps
     products = sum(1 + k for k in iters)
@@ -235,6 +254,15 @@ def main():
                 "kernel": f"pair_kernel<float, true, {tiles[1][0]}> (angular, {tiles[1][1]} source splits)",
                 "avg_launch_ms": round(avg_pair_ms, 4),
                 "launches": pair_launches, "flops_per_pair": FLOPS_PER_PAIR["angular"]}
+
+    # Lanczos vector operations: the two classical Gram-Schmidt passes of
+    # every iteration (HBM-bound), algorithmic bytes over their event time
+    cgs_gbps = cgs_bytes / (cgs_ms * 1e-3) / 1e9 if cgs_ms > 0 else None
+    lanczos_cgs = {"bound": "hbm", "achieved": None if cgs_gbps is None else round(cgs_gbps, 1),
+                   "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                   "frac": None if cgs_gbps is None else round(cgs_gbps / PEAK_HBM_GBPS, 4),
+                   "iterations_timed": cgs_records, "ms_per_step": round(cgs_ms / args.steps, 3),
+                   "bytes_per_step": cgs_bytes / args.steps}
 
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
@@ -258,10 +286,8 @@ def main():
             key = f"{name}_{'angular' if ang else 'linear'}"
             fwd = lambda: so.Mdot(forces=Fd, torques=Td if ang else None)
             bwd = lambda: so.Mdot_backward(Fd, Td if ang else None, GUd, GWd if ang else None)
-            fwd()
-            bwd()
-            tf = timed(fwd, 5, stream)
-            tb = timed(bwd, 3, stream)
+            tf = timed(fwd, 10, stream, warmup=3)
+            tb = timed(bwd, 10, stream, warmup=3)
             breakdown[key] = {"mdot_ms": round(tf, 4), "pairs_per_s": float(n) * n / (tf * 1e-3),
                               "backward_ms": round(tb, 4), "backward_over_forward": round(tb / tf, 3)}
             lin, angv = fwd()
@@ -332,13 +358,19 @@ def main():
         rate = len(probe) * n / (time.perf_counter() - t1)
         m = int(min(n, max(64, args.cpu_seconds * rate / n)))
         sample = np.sort(np.random.default_rng(7).choice(n, size=m, replace=False))
+        reps = 0
         t1 = time.perf_counter()
-        pairloop.mdot_rows(s.pos, sample, s.forces, s.torques, s.radius, s.viscosity)
-        dt_cpu = time.perf_counter() - t1
-        cpu = {"value": m * float(n) / dt_cpu, "unit": "pair-interactions/s", "cores": pairloop.threads(),
+        while True:   # whole passes over the sample until cpu_seconds have passed
+            pairloop.mdot_rows(s.pos, sample, s.forces, s.torques, s.radius, s.viscosity)
+            reps += 1
+            dt_cpu = time.perf_counter() - t1
+            if dt_cpu >= args.cpu_seconds:
+                break
+        cpu = {"value": reps * m * float(n) / dt_cpu, "unit": "pair-interactions/s", "cores": pairloop.threads(),
                "kind": "oracle",
-               "sample": f"{m} target rows x {n} sources of the same workload, linear+angular Mdot, "
-                         f"float64 C/OpenMP pair loop ({dt_cpu:.1f} s)"}
+               "sample": f"{reps} x ({m} target rows x {n} sources) of the same workload, linear+angular Mdot, "
+                         f"float64 C/OpenMP pair loop ({dt_cpu:.1f} s)",
+               "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count()}
 
     out = {
         "metric": METRIC,
@@ -359,6 +391,7 @@ def main():
                    "n": n, "lanczos_iterations": iters, "m_products_per_step": products / args.steps},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "lanczos_vector_ops": lanczos_cgs,
         "breakdown": breakdown,
         "accuracy_vs_fp64_oracle": acc,
         "batched": batched,

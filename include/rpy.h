@@ -192,13 +192,16 @@ rpy_status rpy_batch_mdot(rpy_batch *b, const void *forces, void *lin_out, void 
 /*
  * lin_out = prefactor * M_s^{1/2} w_s for every system (device w of
  * 3 x total entries, lin_out total x 3) by Lanczos (Sec. 3.3) with the
- * stopping rule of rpy_sqrt_mdot_w applied to each system separately.  All
- * systems advance together; one iteration (persistent pair kernel for all
- * systems, segmented float64 vector operations) is one replay of a
- * captured HIP graph, and a second graph runs the per-system eigensolves
- * and convergence tests every `check_every` iterations (>= 1).  iters_out
- * (host, n_systems entries, may be NULL) receives each system's iteration
- * count.  Synchronises hip_stream.  Returns RPY_ERR_NOT_CONVERGED if any
+ * stopping rule of rpy_sqrt_mdot_w applied to each system separately:
+ * each system stops at the first k >= 2 meeting it, as if it were solved
+ * alone.  All systems advance together; one iteration (persistent pair
+ * kernel for all systems, segmented float64 vector operations, the
+ * per-system stopping test decided on the device) is one replay of a
+ * captured HIP graph.  The host polls the number of systems still active
+ * every `check_every` iterations (>= 1); a larger value saves host round
+ * trips at the price of up to check_every - 1 idle replays at the end, and
+ * does not change any result.  iters_out (host, n_systems entries, may be
+ * NULL) receives each system's iteration count.  Synchronises hip_stream.  Returns RPY_ERR_NOT_CONVERGED if any
  * system reached max_iter (all results written), RPY_ERR_NOT_SPD if any
  * system's matrix was found indefinite.
  */
@@ -234,24 +237,29 @@ rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_pe
 rpy_status rpy_autotune(rpy_solver *s, const char *cache_path, void *hip_stream);
 
 /* Kernel classes reported by rpy_kernel_time. */
-typedef enum { RPY_KERNEL_PAIR = 0, RPY_KERNEL_ADJOINT = 1 } rpy_kernel;
+typedef enum { RPY_KERNEL_PAIR = 0, RPY_KERNEL_ADJOINT = 1, RPY_KERNEL_LANCZOS_CGS = 2 } rpy_kernel;
 
 /*
  * Instrumentation, not part of the method: with `enable` != 0 the solver
- * records a HIP event pair around every launch of its pair kernel (forward
- * products, including those inside sqrtMdotW) and of its adjoint kernel, on
- * the stream of the call.  Enabling (or re-enabling) clears the records.
+ * records a HIP event pair, on the stream of the call, around every launch
+ * of its pair kernel (forward products, including those inside sqrtMdotW),
+ * of its adjoint kernel, and around the two classical Gram-Schmidt passes of
+ * every Lanczos iteration (four launches: two projections V^T w and two
+ * updates w -= V h).  Enabling (or re-enabling) clears the records.
  */
 rpy_status rpy_enable_timing(rpy_solver *s, int enable);
 
 /*
- * Sum of the recorded launch durations of one kernel class in milliseconds,
- * the number of launches and the number of ordered particle pairs they
- * evaluated.  Waits for the recorded events (host blocking).  Any output
- * pointer may be NULL.
+ * Sum of the recorded durations of one kernel class in milliseconds, the
+ * number of records and the work they did: ordered particle pairs for
+ * RPY_KERNEL_PAIR and RPY_KERNEL_ADJOINT; algorithmic HBM bytes for
+ * RPY_KERNEL_LANCZOS_CGS (per pass at iteration k with basis vectors of n
+ * doubles: (k + 1) n reads for V^T w, (k + 1) n reads and n writes for the
+ * update, times 8 bytes).  Waits for the recorded events (host blocking).
+ * Any output pointer may be NULL.
  */
 rpy_status rpy_kernel_time(rpy_solver *s, rpy_kernel kernel, double *ms_total, int64_t *launches,
-                           double *pairs);
+                           double *work);
 
 /* Message describing the last failure of `s` ("" if none); owned by `s`. */
 const char *rpy_last_error(const rpy_solver *s);

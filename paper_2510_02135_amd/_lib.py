@@ -261,16 +261,18 @@ def rpy_enable_timing(h, enable: bool = True):
     _check(h, load().rpy_enable_timing(h, int(bool(enable))))
 
 
-KERNEL = {"pair": 0, "adjoint": 1}
+KERNEL = {"pair": 0, "adjoint": 1, "lanczos_cgs": 2}
 
 
 def rpy_kernel_time(h, kernel: str = "pair"):
-    """(total milliseconds, launches, pairs) recorded for a kernel class."""
+    """(total milliseconds, records, work) recorded for a kernel class; work
+    is ordered pairs for "pair" and "adjoint", algorithmic HBM bytes for
+    "lanczos_cgs"."""
     ms = ctypes.c_double(0.0)
     n = ctypes.c_int64(0)
-    pairs = ctypes.c_double(0.0)
-    _check(h, load().rpy_kernel_time(h, KERNEL[kernel], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(pairs)))
-    return ms.value, n.value, pairs.value
+    work = ctypes.c_double(0.0)
+    _check(h, load().rpy_kernel_time(h, KERNEL[kernel], ctypes.byref(ms), ctypes.byref(n), ctypes.byref(work)))
+    return ms.value, n.value, work.value
 
 
 def rpy_last_error(h) -> str:

@@ -7,7 +7,7 @@
 //   dL/dF, dL/dT = M g                  (the grand mobility is symmetric)
 //   dL/dX_k      = sum_j [ grad Phi(g_k, s_j; d) - grad Phi(g_j, s_k; -d) ],
 //                  d = X_k - X_j,  Phi(g, s; r) = g^T M(r) s.
-// With the k-unit scalar functions of rpy_internal.hpp (A, B, G, D, E and
+// With the k-unit scalar functions of rpy_pair.hpp (A, B, G, D, E and
 // X_r := X'(r)/r, so that X'(r) rhat = X_r d) the pair term is
 //   dX += d [ A_r (gUk.Fj + gUj.Fk) + B_r ((d.gUk)(d.Fj) + (d.gUj)(d.Fk))
 //            + G_r (gUk.(Tj x d) + gWk.(Fj x d) - gUj.(Tk x d) - gWj.(Fk x d))

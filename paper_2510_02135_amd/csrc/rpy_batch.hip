@@ -13,16 +13,21 @@
 // sequence of one iteration is captured once into a HIP graph and replayed;
 // float64 vector operations are segmented (every block of the segmented
 // kernels lies inside one system) with fixed-order two-stage reductions, and
-// converged systems drop out of all work.  A second graph runs, every
-// `check_every` iterations, one eigensolver workgroup pair per system
-// (s_{k-1} and s_k), the per-system increment test of the single-system
-// solver, and writes the result of each system as it converges.
+// converged systems drop out of all work.  Every iteration ends with the
+// stopping rule of the single-system solver, decided on the device per
+// system: the quadrature monitor estimates each system's increment, and only
+// systems whose estimate is near tol (or that broke down, or reached
+// max_iter) run the exact eigensolves of T_{k-1} and T_k and the increment
+// test; a system that stops writes its result at once.  The host only polls
+// the number of systems still active, every `check_every` iterations.
 #include "rpy_device.hpp"
+#include "rpy_krylov.hpp"
 #include "rpy_internal.hpp"
 #include "rpy_solver_ops.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -38,8 +43,9 @@ constexpr int kSegThreads = 256;
 
 // per-system status (double): beta0, increment, not-SPD flag, running
 // max(|alpha|, beta), first breakdown iteration, iterations at stop
-// (0 while active), result code (0 ok, 1 not converged, 2 not SPD), spare
-enum { BS_BETA0 = 0, BS_INCR, BS_NSPD, BS_TSCALE, BS_BREAK, BS_DONE, BS_CODE, BS_SIZE = 8 };
+// (0 while active), result code (0 ok, 1 not converged, 2 not SPD),
+// estimated increment (quadrature monitor)
+enum { BS_BETA0 = 0, BS_INCR, BS_NSPD, BS_TSCALE, BS_BREAK, BS_DONE, BS_CODE, BS_EST, BS_SIZE = 8 };
 
 // ---------------------------------------------------------------------------
 // persistent batched pair kernel
@@ -347,9 +353,9 @@ __global__ void advance_k(int *kdev) {
 __global__ void __launch_bounds__(kEigThreads)
 batch_tridiag(const double *__restrict__ alpha, const double *__restrict__ beta, int64_t lstride,
               double *__restrict__ s_prev, double *__restrict__ s_cur, double *__restrict__ Q, int64_t qstride,
-              double *__restrict__ status, const int *__restrict__ active, const int *__restrict__ kdev) {
+              double *__restrict__ status, const int *__restrict__ need, const int *__restrict__ kdev) {
     const int s = blockIdx.y;
-    if (active[s] == 0) return;
+    if (need[s] == 0) return;
     const int kc = kdev[0] - 1;
     const int kk = kc - 1 + (int)blockIdx.x;
     if (kk <= 0) return;
@@ -359,13 +365,16 @@ batch_tridiag(const double *__restrict__ alpha, const double *__restrict__ beta,
                        blockIdx.x == 1 ? status + (size_t)s * BS_SIZE + BS_NSPD : nullptr);
 }
 
+// status[slot] of system s = |b - [a; 0]| / |b| for the vectors a (length
+// k-1) and b (length k) of the system, k = kdev[0] - koff; systems with
+// gate[s] == 0 are skipped.
 __global__ void batch_increment(const double *__restrict__ s_prev, const double *__restrict__ s_cur, int64_t lstride,
-                                double *__restrict__ status, const int *__restrict__ active,
-                                const int *__restrict__ kdev) {
+                                double *__restrict__ status, const int *__restrict__ gate,
+                                const int *__restrict__ kdev, int koff, int slot) {
     __shared__ double red[kSegThreads];
     const int s = blockIdx.x;
-    if (active[s] == 0) return;
-    const int k = kdev[0] - 1;
+    if (gate[s] == 0) return;
+    const int k = kdev[0] - koff;
     const double *a = s_prev + (size_t)s * lstride, *b = s_cur + (size_t)s * lstride;
     double num = 0.0, den = 0.0;
     for (int i = threadIdx.x; i < k; i += blockDim.x) {
@@ -376,19 +385,57 @@ __global__ void batch_increment(const double *__restrict__ s_prev, const double 
     }
     num = block_sum(num, red);
     den = block_sum(den, red);
-    if (threadIdx.x == 0) status[(size_t)s * BS_SIZE + BS_INCR] = (k >= 2 && den > 0.0) ? sqrt(num / den) : INFINITY;
+    if (threadIdx.x == 0) status[(size_t)s * BS_SIZE + slot] = (k >= 2 && den > 0.0) ? sqrt(num / den) : INFINITY;
 }
 
-// Stopping decisions of every active system after iteration kc; systems
-// that stop are marked in `fresh` for the combine kernel.  kdev[1] receives
-// the number of systems still active.
+// quadrature estimates of s_{k-1} (workgroup x = 0) and s_k (x = 1) of every
+// active system at the current iteration k = kdev[0], k >= 2
+__global__ void __launch_bounds__(kMonThreads)
+batch_monitor(const double *__restrict__ alpha, const double *__restrict__ beta, int64_t lstride,
+              double *__restrict__ scratch, int64_t sstride, double *__restrict__ est_prev,
+              double *__restrict__ est_cur, const int *__restrict__ active, const int *__restrict__ kdev) {
+    const int s = blockIdx.y;
+    if (active[s] == 0) return;
+    const int k = kdev[0];
+    const int kk = k - 1 + (int)blockIdx.x;
+    if (k < 2 || kk <= 0) return;
+    monitor_block(alpha + (size_t)s * lstride, beta + (size_t)s * lstride, k, kk,
+                  scratch + ((size_t)s * 2 + blockIdx.x) * sstride,
+                  (blockIdx.x == 0 ? est_prev : est_cur) + (size_t)s * lstride);
+}
+
+// need[s] = 1 for the active systems that take the exact test after
+// iteration k = kdev[0]: estimated increment below 1.01 tol or not finite,
+// a recorded breakdown, the iteration cap, or every iteration (`every`)
+__global__ void batch_flag(const double *__restrict__ status, const int *__restrict__ active, int *__restrict__ need,
+                           int nsys, int kcap, double tol, int every, const int *__restrict__ kdev) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys) return;
+    const int k = kdev[0];
+    const double *st = status + (size_t)s * BS_SIZE;
+    int f = 0;
+    if (active[s] != 0) {
+        const double est = st[BS_EST];
+        f = every || k >= kcap || st[BS_BREAK] > 0.0 || (k >= 2 && (!isfinite(est) || est < tol * 1.01));
+    }
+    need[s] = f;
+}
+
+// Stopping decisions after iteration kc of the active systems that took the
+// exact test; systems that stop are marked in `fresh` for the combine
+// kernel.  kdev[1] receives the number of systems still active.
 __global__ void batch_converge(double *__restrict__ status, int *__restrict__ active, int *__restrict__ fresh,
-                               int kcap, int nsys, double tol, int *__restrict__ kdev) {
+                               const int *__restrict__ need, int kcap, int nsys, double tol,
+                               int *__restrict__ kdev) {
     __shared__ int cnt[kSegThreads];
     const int kc = kdev[0] - 1;
     int mine = 0;
     for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
         if (active[s] == 0) continue;
+        if (need[s] == 0) {   // not tested this iteration: stays active
+            ++mine;
+            continue;
+        }
         double *st = status + (size_t)s * BS_SIZE;
         const int kb = (int)st[BS_BREAK];
         int done = 0;
@@ -486,7 +533,7 @@ struct rpy_batch {
     int max_sys_n = 0;
     DevBuf d_off, d_kfac, d_pc, d_tasks, d_counter, d_rec, d_flag;
     DevBuf d_blk_sys, d_blk_lo, d_blk_hi, d_sys_b0, d_sys_b1, d_kmax;
-    DevBuf V, w, lanc, red, Q, status, ints, pref;
+    DevBuf V, w, lanc, red, Q, status, ints, pref, mon;
     unsigned *host_u = nullptr;
     int *host_i = nullptr;
     std::string err;
@@ -532,9 +579,10 @@ rpy_status batch_mdot_typed(rpy_batch *b, const Real *F, Real *out, hipStream_t 
     return RPY_OK;
 }
 
-// Enqueue one Lanczos iteration for all active systems (captured into a graph).
+// Enqueue one Lanczos iteration for all active systems, with its stopping
+// test, as one graph.
 template <typename Real>
-void enqueue_iteration(rpy_batch *b, int kcap, hipStream_t st) {
+void enqueue_iteration(rpy_batch *b, int kcap, double tol, int every, Real *out, hipStream_t st) {
     const int64_t n = 3 * b->ntot;
     const int64_t ld = (n + 63) / 64 * 64;
     const int64_t L = kcap + 1;
@@ -570,29 +618,28 @@ void enqueue_iteration(rpy_batch *b, int kcap, hipStream_t st) {
     hipLaunchKernelGGL(seg_finish_iter, gs, dim3(256), 0, st, alpha, beta, L, b->nsys, active, kdev,
                        b->d_kmax.as<int>(), b->status.as<double>());
     hipLaunchKernelGGL(seg_next_basis, gb, tb, 0, st, V, ld, w, beta, L, b->status.as<double>(), m, active, kdev);
-    hipLaunchKernelGGL(advance_k, dim3(1), dim3(64), 0, st, kdev);
-}
-
-// Enqueue the per-system check: eigensolves, increments, stopping, output of stopped systems.
-template <typename Tout>
-void enqueue_check(rpy_batch *b, int kcap, double tol, Tout *out, hipStream_t st) {
-    const int64_t n = 3 * b->ntot;
-    const int64_t ld = (n + 63) / 64 * 64;
-    const int64_t L = kcap + 1;
-    double *lan = b->lanc.as<double>();
-    double *alpha = lan, *beta = lan + b->nsys * L;
+    // which systems take the exact test at this k
     double *s_prev = lan + 3 * b->nsys * L, *s_cur = lan + 4 * b->nsys * L;
-    int *ints = b->ints.as<int>();
-    int *kdev = ints, *active = ints + 2, *fresh = ints + 2 + b->nsys;
-    const SegMap m = seg_map(b);
+    double *e_prev = lan + 5 * b->nsys * L, *e_cur = lan + 6 * b->nsys * L;
+    int *fresh = ints + 2 + b->nsys, *need = ints + 3 + 2 * b->nsys;
+    if (!every) {
+        hipLaunchKernelGGL(batch_monitor, dim3(2, (unsigned)b->nsys), dim3(kMonThreads), 0, st, alpha, beta, L,
+                           b->mon.as<double>(), (int64_t)kcap * kMonNodes, e_prev, e_cur, active, kdev);
+        hipLaunchKernelGGL(batch_increment, dim3((unsigned)b->nsys), dim3(kSegThreads), 0, st, e_prev, e_cur, L,
+                           b->status.as<double>(), active, kdev, 0, (int)BS_EST);
+    }
+    hipLaunchKernelGGL(batch_flag, gs, dim3(256), 0, st, b->status.as<double>(), active, need, b->nsys, kcap, tol,
+                       every, kdev);
+    hipLaunchKernelGGL(advance_k, dim3(1), dim3(64), 0, st, kdev);
+    // exact test of the flagged systems (kc = kdev[0] - 1 from here on)
     hipLaunchKernelGGL(batch_tridiag, dim3(2, (unsigned)b->nsys), dim3(kEigThreads), 0, st, alpha, beta, L, s_prev,
-                       s_cur, b->Q.as<double>(), (int64_t)kcap * kcap, b->status.as<double>(), active, kdev);
+                       s_cur, b->Q.as<double>(), (int64_t)kcap * kcap, b->status.as<double>(), need, kdev);
     hipLaunchKernelGGL(batch_increment, dim3((unsigned)b->nsys), dim3(kSegThreads), 0, st, s_prev, s_cur, L,
-                       b->status.as<double>(), active, kdev);
-    hipLaunchKernelGGL(batch_converge, dim3(1), dim3(kSegThreads), 0, st, b->status.as<double>(), active, fresh, kcap,
-                       b->nsys, tol, kdev);
-    hipLaunchKernelGGL((batch_combine<Tout>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, b->V.as<double>(), ld,
-                       s_cur, L, b->status.as<double>(), fresh, b->pref.as<double>(), m, out);
+                       b->status.as<double>(), need, kdev, 1, (int)BS_INCR);
+    hipLaunchKernelGGL(batch_converge, dim3(1), dim3(kSegThreads), 0, st, b->status.as<double>(), active, fresh, need,
+                       kcap, b->nsys, tol, kdev);
+    hipLaunchKernelGGL((batch_combine<Real>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, V, ld, s_cur, L,
+                       b->status.as<double>(), fresh, b->pref.as<double>(), m, out);
     hipLaunchKernelGGL(clear_ints, dim3((unsigned)((b->nsys + 255) / 256)), dim3(256), 0, st, fresh, b->nsys);
 }
 
@@ -605,11 +652,12 @@ rpy_status batch_sqrt_typed(rpy_batch *b, const Real *w_in, double prefactor, do
     const int64_t L = kcap + 1;
     BHIP(b, b->V.ensure((size_t)(kcap + 1) * ld * sizeof(double)));
     BHIP(b, b->w.ensure((size_t)ld * sizeof(double)));
-    BHIP(b, b->lanc.ensure((size_t)5 * b->nsys * L * sizeof(double)));
+    BHIP(b, b->lanc.ensure((size_t)7 * b->nsys * L * sizeof(double)));
+    BHIP(b, b->mon.ensure((size_t)b->nsys * 2 * kcap * kMonNodes * sizeof(double)));
     BHIP(b, b->red.ensure((size_t)b->nblk * std::max(kcap, 1) * sizeof(double)));
     BHIP(b, b->Q.ensure((size_t)b->nsys * 2 * kcap * kcap * sizeof(double)));
     BHIP(b, b->status.ensure((size_t)b->nsys * BS_SIZE * sizeof(double)));
-    BHIP(b, b->ints.ensure((size_t)(3 + 2 * b->nsys) * sizeof(int)));
+    BHIP(b, b->ints.ensure((size_t)(3 + 3 * b->nsys) * sizeof(int)));
     BHIP(b, b->pref.ensure(sizeof(double)));
     int *ints = b->ints.as<int>();
     int *kdev = ints, *active = ints + 2, *fresh = ints + 2 + b->nsys, *nonfin = ints + 2 + 2 * b->nsys;
@@ -639,40 +687,35 @@ rpy_status batch_sqrt_typed(rpy_batch *b, const Real *w_in, double prefactor, do
     BHIP(b, hipStreamSynchronize(st));
     if (b->host_i[0] != 0) return bfail(b, RPY_ERR_NONFINITE, "the noise vector W is not finite");
 
-    // capture one iteration and one check as graphs
+    // capture one iteration (with its stopping test) as a graph
+    const char *check_env = std::getenv("RPY_LANCZOS_CHECK");
+    const int every = (check_env && std::string(check_env) == "every") ? 1 : 0;
     hipStream_t cap = nullptr;
     BHIP(b, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipGraph_t g_iter = nullptr, g_check = nullptr;
-    hipGraphExec_t x_iter = nullptr, x_check = nullptr;
+    hipGraph_t g_iter = nullptr;
+    hipGraphExec_t x_iter = nullptr;
     auto cleanup = [&]() {
         if (x_iter) (void)hipGraphExecDestroy(x_iter);
-        if (x_check) (void)hipGraphExecDestroy(x_check);
         if (g_iter) (void)hipGraphDestroy(g_iter);
-        if (g_check) (void)hipGraphDestroy(g_check);
         (void)hipStreamDestroy(cap);
     };
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        enqueue_iteration<Real>(b, kcap, cap);
+        enqueue_iteration<Real>(b, kcap, tol, every, out, cap);
         e = hipStreamEndCapture(cap, &g_iter);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&x_iter, g_iter, nullptr, nullptr, 0);
-    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        enqueue_check<Real>(b, kcap, tol, out, cap);
-        e = hipStreamEndCapture(cap, &g_check);
-    }
-    if (e == hipSuccess) e = hipGraphInstantiate(&x_check, g_check, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         cleanup();
         return bhip(b, e, "graph capture of the batched Lanczos iteration");
     }
+    // systems stop on the device at their own first k meeting the rule; the
+    // host polls the number still active every check_every iterations
     int n_active = 1;
     for (int k = 1; k <= kcap && n_active > 0; ++k) {
         e = hipGraphLaunch(x_iter, st);
-        if (e == hipSuccess && ((k >= 2 && k % check_every == 0) || k == kcap)) {
-            e = hipGraphLaunch(x_check, st);
-            if (e == hipSuccess) e = hipMemcpyAsync(b->host_i, kdev + 1, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess && (k % check_every == 0 || k == kcap)) {
+            e = hipMemcpyAsync(b->host_i, kdev + 1, sizeof(int), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e == hipSuccess) n_active = b->host_i[0];
         }
@@ -844,7 +887,7 @@ void rpy_batch_destroy(rpy_batch *b) {
     if (!b) return;
     for (DevBuf *d : {&b->d_off, &b->d_kfac, &b->d_pc, &b->d_tasks, &b->d_counter, &b->d_rec, &b->d_flag,
                       &b->d_blk_sys, &b->d_blk_lo, &b->d_blk_hi, &b->d_sys_b0, &b->d_sys_b1, &b->d_kmax, &b->V,
-                      &b->w, &b->lanc, &b->red, &b->Q, &b->status, &b->ints, &b->pref})
+                      &b->w, &b->lanc, &b->red, &b->Q, &b->status, &b->ints, &b->pref, &b->mon})
         d->release();
     if (b->host_u) (void)hipHostFree(b->host_u);
     if (b->host_i) (void)hipHostFree(b->host_i);

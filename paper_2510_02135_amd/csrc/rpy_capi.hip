@@ -218,16 +218,16 @@ rpy_status rpy_div_m(rpy_solver *s, void *lin_out, void *ang_out, void *hip_stre
 rpy_status rpy_enable_timing(rpy_solver *s, int enable) {
     if (!s) return RPY_ERR_INVALID_ARG;
     s->timing = enable != 0;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
         s->ev_used[k] = 0;
         s->ev_pairs[k] = 0.0;
     }
     return RPY_OK;
 }
 
-rpy_status rpy_kernel_time(rpy_solver *s, rpy_kernel kernel, double *ms_total, int64_t *launches, double *pairs) {
+rpy_status rpy_kernel_time(rpy_solver *s, rpy_kernel kernel, double *ms_total, int64_t *launches, double *work) {
     if (!s) return RPY_ERR_INVALID_ARG;
-    if ((int)kernel < 0 || (int)kernel > 1) return fail(s, RPY_ERR_INVALID_ARG, "unknown kernel class");
+    if ((int)kernel < 0 || (int)kernel > 2) return fail(s, RPY_ERR_INVALID_ARG, "unknown kernel class");
     const int k = (int)kernel;
     double total = 0.0;
     for (size_t i = 0; i < s->ev_used[k]; ++i) {
@@ -238,7 +238,7 @@ rpy_status rpy_kernel_time(rpy_solver *s, rpy_kernel kernel, double *ms_total, i
     }
     if (ms_total) *ms_total = total;
     if (launches) *launches = (int64_t)s->ev_used[k];
-    if (pairs) *pairs = s->ev_pairs[k];
+    if (work) *work = s->ev_pairs[k];
     return RPY_OK;
 }
 

@@ -3,7 +3,7 @@
 // U = M(X) [F; T] summed over all ordered pairs, self pair included (the
 // N-body solver of Sec. 3.5, blocks of eq. (block_mobility) with the
 // generalised Rotne-Prager-Yamakawa tensors; the coefficient functions are
-// listed with PairConst in rpy_internal.hpp).
+// listed with PairConst in rpy_pair.hpp).
 //
 // Work decomposition
 //   grid.x : target blocks of 256*TM targets (TM targets per lane, strided

@@ -24,6 +24,7 @@
 // Reductions are two-stage with a fixed block count and fixed order, so the
 // result does not depend on scheduling.
 #include "rpy_device.hpp"
+#include "rpy_krylov.hpp"
 #include "rpy_internal.hpp"
 #include "rpy_solver_ops.hpp"
 
@@ -94,25 +95,35 @@ __global__ void sumsq_partial(const Tin *__restrict__ w, int64_t n, double *__re
 }
 
 // partial[b * k + j] = sum over block b's rows of V[j][i] w[i], j < k.
-// Block b owns one contiguous slab of rows; each wavefront takes every
-// fourth basis column, accumulates its slab with coalesced loads and
-// reduces across lanes by shuffles, so no workgroup barrier is needed.
+// Block b owns one contiguous slab of rows; each wavefront takes groups of
+// kCols basis columns (every kWaves-th group), keeps the loads of all of
+// them in flight while it walks its slab with coalesced reads, and reduces
+// across lanes by shuffles, so no workgroup barrier is needed.
 constexpr int kGemvBlocks = 1024;
 __global__ void __launch_bounds__(kRedThreads)
 gemv_t_partial(const double *__restrict__ V, int64_t ld, int k, const double *__restrict__ w, int64_t n,
                double *__restrict__ partial) {
-    constexpr int kWaves = kRedThreads / 64;
+    constexpr int kWaves = kRedThreads / 64, kCols = 4;
     int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     chunk = (chunk + 63) / 64 * 64;
     const int64_t i0 = (int64_t)blockIdx.x * chunk;
     const int64_t i1 = std::min<int64_t>(n, i0 + chunk);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int j = wv; j < k; j += kWaves) {
-        const double *col = V + (size_t)j * ld;
-        double acc = 0.0;
-        for (int64_t i = i0 + lane; i < i1; i += 64) acc = fma(col[i], w[i], acc);
-        acc = wave_sum(acc);
-        if (lane == 0) partial[(size_t)blockIdx.x * k + j] = acc;
+    for (int j0 = wv * kCols; j0 < k; j0 += kWaves * kCols) {
+        const int nc = std::min(kCols, k - j0);
+        const double *col = V + (size_t)j0 * ld;
+        double acc[kCols] = {};
+        for (int64_t i = i0 + lane; i < i1; i += 64) {
+            const double wi = w[i];
+#pragma unroll
+            for (int c = 0; c < kCols; ++c)
+                if (c < nc) acc[c] = fma(col[(size_t)c * ld + i], wi, acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) {
+            const double r = wave_sum(acc[c]);
+            if (lane == 0 && c < nc) partial[(size_t)blockIdx.x * k + j0 + c] = r;
+        }
     }
 }
 
@@ -172,107 +183,15 @@ tridiag_sqrt_kernel(const double *__restrict__ alpha, const double *__restrict__
                        blockIdx.x == 1 ? status + ST_FLAGS : nullptr);
 }
 
-// Estimate of s = T^{1/2} e_1 for the leading kk x kk block of the
-// tridiagonal (alpha, beta), without an eigendecomposition; it only decides
-// when the exact test is worth running.  With
-// x^{-1/2} = (1/pi) int exp(u/2) / (x + exp(u)) du over the real line (the
-// substitution t^2 = e^u in the standard integral (2/pi) int_0^inf
-// dt / (x + t^2)), the trapezoid rule with step h gives
-//   T^{1/2} e_1 = T T^{-1/2} e_1 ~ T sum_l w_l (T + c_l I)^{-1} e_1,
-//   c_l = exp(u_l), w_l = (h/pi) exp(u_l/2).
-// The integrand is analytic in the strip |Im u| < pi, so the rule's error
-// falls like exp(-2 pi^2 / h) (about 1e-21 here); the nodes span the
-// Gershgorin bound g of T down to 1e-10 g with a margin of 40 on either side,
-// which leaves truncation terms below 1e-16 relative for eigenvalues in that
-// range.  Thread l < kMonNodes solves (T + c_l I) y = e_1 by the Thomas
-// algorithm (elimination without pivoting is stable for these SPD
-// systems).  Meanwhile one lane of an extra wavefront factors
-// T - 1e-10 g I = L D L^T: a non-positive pivot means T has an eigenvalue
-// below the quadrature's range (or a negative one), and the estimate is then
-// reported as NaN, which sends the caller to the exact test.  Workgroup b
-// handles kk = k-1+b.
-constexpr int kMonNodes = 256;
-constexpr int kMonThreads = kMonNodes + 64;
+// Quadrature estimates of s_{k-1} (workgroup 0) and s_k (workgroup 1);
+// see monitor_block.
 __global__ void __launch_bounds__(kMonThreads)
 lanczos_monitor_kernel(const double *__restrict__ alpha, const double *__restrict__ beta, int k,
                        double *__restrict__ scratch, int64_t sstride, double *__restrict__ est0,
                        double *__restrict__ est1) {
-    __shared__ double a[kMaxK], b[kMaxK], q[kMaxK];
-    __shared__ double bound;
-    __shared__ int indefinite;
     const int kk = k - 1 + (int)blockIdx.x;
-    double *est = blockIdx.x == 0 ? est0 : est1;
     if (kk <= 0) return;
-    const int tid = threadIdx.x;
-    double *bp = scratch + (size_t)blockIdx.x * sstride;   // pivots b'_i, node index fastest
-    double *dp = bp + (size_t)kMaxK * kMonNodes;            // d'_i, then w_l y_i
-    for (int i = tid; i < kk; i += blockDim.x) {
-        a[i] = alpha[i];
-        b[i] = (i + 1 < kk) ? beta[i] : 0.0;
-    }
-    if (tid == 0) indefinite = 0;
-    __syncthreads();
-    if (tid == 0) {
-        double g = 0.0;
-        for (int i = 0; i < kk; ++i) g = fmax(g, a[i] + (i > 0 ? fabs(b[i - 1]) : 0.0) + fabs(b[i]));
-        bound = g > 0.0 ? g : 1.0;
-    }
-    __syncthreads();
-    const int l = tid;
-    if (l >= kMonNodes) {
-        if (l == kMonNodes) {
-            const double shift = 1e-10 * bound;
-            double piv = a[0] - shift;
-            bool pd = piv > 0.0;
-            for (int i = 1; i < kk && pd; ++i) {
-                piv = a[i] - shift - b[i - 1] * (b[i - 1] / piv);
-                pd = piv > 0.0;
-            }
-            if (!pd) indefinite = 1;
-        }
-    } else {
-        const double u_hi = log(bound) + 40.0, u_lo = log(bound) + log(1e-10) - 40.0;
-        const double h = (u_hi - u_lo) / (double)(kMonNodes - 1);
-        const double ul = u_lo + h * l;
-        const double c = exp(ul), wl = h / M_PI * exp(0.5 * ul);
-        // forward elimination
-        double bprev = a[0] + c, dprev = 1.0;
-        bp[l] = bprev;
-        dp[l] = dprev;
-        for (int i = 1; i < kk; ++i) {
-            const double m = b[i - 1] / bprev;
-            bprev = a[i] + c - m * b[i - 1];
-            dprev = -m * dprev;
-            bp[(size_t)i * kMonNodes + l] = bprev;
-            dp[(size_t)i * kMonNodes + l] = dprev;
-        }
-        // back substitution; w_l y_i replaces d'_i
-        double ynext = dprev / bprev;
-        dp[(size_t)(kk - 1) * kMonNodes + l] = wl * ynext;
-        for (int i = kk - 2; i >= 0; --i) {
-            const double y = (dp[(size_t)i * kMonNodes + l] - b[i] * ynext) / bp[(size_t)i * kMonNodes + l];
-            dp[(size_t)i * kMonNodes + l] = wl * y;
-            ynext = y;
-        }
-    }
-    __syncthreads();
-    // q_i = sum_l w_l y_{l,i}: one wavefront per row, coalesced
-    const int lane = tid & 63, wv = tid >> 6;
-    for (int i = wv; i < kk && wv < kMonNodes / 64; i += kMonNodes / 64) {
-        const double *row = dp + (size_t)i * kMonNodes;
-        double acc = 0.0;
-        for (int n = lane; n < kMonNodes; n += 64) acc += row[n];
-        acc = wave_sum(acc);
-        if (lane == 0) q[i] = acc;
-    }
-    __syncthreads();
-    const double poison = indefinite ? NAN : 0.0;
-    for (int i = tid; i < kk; i += blockDim.x) {
-        double v = a[i] * q[i];
-        if (i > 0) v = fma(b[i - 1], q[i - 1], v);
-        if (i + 1 < kk) v = fma(b[i], q[i + 1], v);
-        est[i] = v + poison;
-    }
+    monitor_block(alpha, beta, k, kk, scratch + (size_t)blockIdx.x * sstride, blockIdx.x == 0 ? est0 : est1);
 }
 
 // status[ST_INCR] = |s1 - [s0; 0]| / |s1| for s0 of length k-1, s1 of length k.
@@ -343,8 +262,8 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
     HIP_TRY(s, s->lz_scal.ensure(sizeof(double) * (ST_SIZE + 8 * (size_t)(kMaxK + 1))));
     HIP_TRY(s, s->lz_red.ensure(sizeof(double) * (size_t)kGemvBlocks * (kMaxK + 1)));
     HIP_TRY(s, s->lz_q.ensure(sizeof(double) * 2 * (size_t)kmax * kmax));
-    // monitor scratch: per workgroup, pivots and right-hand sides of kMonNodes systems
-    const int64_t mon_stride = 2 * (int64_t)kMaxK * kMonNodes;
+    // monitor scratch: per workgroup, one vector of kMonNodes systems
+    const int64_t mon_stride = (int64_t)kmax * kMonNodes;
     HIP_TRY(s, s->lz_mon.ensure(sizeof(double) * 2 * (size_t)mon_stride));
     if (!s->host_scal) HIP_TRY(s, hipHostMalloc((void **)&s->host_scal, sizeof(double) * 8, hipHostMallocDefault));
     LanczosWork L;
@@ -421,11 +340,14 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
         hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, L.red, kRedBlocks, L.alpha + (k - 1), 0);
         hipLaunchKernelGGL(axpy_dev, dim3(g), dim3(256), 0, st, L.w, vk, L.alpha + (k - 1), -1.0, n);
         // classical Gram-Schmidt against V_k, twice
+        hipEvent_t cgs0 = timing_begin(s, RPY_KERNEL_LANCZOS_CGS, 2.0 * (2.0 * k + 3.0) * (double)n * 8.0);
+        if (cgs0) HIP_TRY(s, hipEventRecord(cgs0, st));
         for (int pass = 0; pass < 2; ++pass) {
             hipLaunchKernelGGL(gemv_t_partial, dim3(kGemvBlocks), dim3(kRedThreads), 0, st, L.V, ld, k, L.w, n, L.red);
             hipLaunchKernelGGL(gemv_t_final, dim3(k), dim3(kRedThreads), 0, st, L.red, kGemvBlocks, k, L.h);
             hipLaunchKernelGGL(gemv_n_sub, dim3(g), dim3(256), 0, st, L.V, ld, k, L.h, L.w, n);
         }
+        if (hipEvent_t cgs1 = timing_end(s, RPY_KERNEL_LANCZOS_CGS)) HIP_TRY(s, hipEventRecord(cgs1, st));
         // beta_k = |w|, breakdown bookkeeping, v_{k+1}
         hipLaunchKernelGGL(dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, L.w, L.w, n, L.red);
         hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, L.red, kRedBlocks, L.beta + (k - 1), 1);

@@ -121,6 +121,23 @@ def test_tile_config_accessors(lib):
         lib.rpy_destroy(h)
 
 
+def test_timing_accessors(lib):
+    """Instrumentation classes 0..2 (pair, adjoint, Lanczos Gram-Schmidt)
+    report nothing before any launch; other classes are rejected."""
+    h = _solver(lib)
+    lib.rpy_kernel_time.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
+    assert lib.rpy_enable_timing(h, 1) == OK
+    for kind in (0, 1, 2):
+        ms, n, work = ctypes.c_double(-1), ctypes.c_int64(-1), ctypes.c_double(-1)
+        assert lib.rpy_kernel_time(h, kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(work)) == OK
+        assert (ms.value, n.value, work.value) == (0.0, 0, 0.0)
+    for kind in (-1, 3):
+        assert lib.rpy_kernel_time(h, kind, None, None, None) == INVALID
+    assert lib.rpy_enable_timing(h, 0) == OK
+    lib.rpy_destroy(h)
+
+
 def test_batch_create_checks(lib):
     import numpy as np
     P = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
