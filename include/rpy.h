@@ -144,6 +144,66 @@ rpy_status rpy_sqrt_mdot_w(rpy_solver *s, const void *w, double prefactor, doubl
 rpy_status rpy_div_m(rpy_solver *s, void *lin_out, void *ang_out, void *hip_stream);
 
 /*
+ * One random finite difference of the thermal drift (eq. (rfd), Sec. 3.4):
+ *   [lin; ang] = (1/delta) [ M(X + delta/2 W_X) W - M(X - delta/2 W_X) W ]
+ * w: device, 3N entries (6N with include_angular: linear first, as for
+ * rpy_sqrt_mdot_w), in the dtype of the stored positions; W_X is its first
+ * 3N entries, the only part that displaces the particles (orientation does
+ * not enter M).  delta > 0 is an absolute length (the paper leaves its size
+ * open; 1e-3 a in float32 and 1e-4 a in float64 balance the O(delta^2)
+ * bias against rounding amplified by 1/delta).  The displaced positions are
+ * formed in float64 without fused multiply-add and rounded once to the
+ * stored precision; the stored positions are not changed.  The two products
+ * are reduced in float64, differenced and rounded once.  lin_out (n x 3)
+ * and, with include_angular, ang_out (n x 3) are required.  Averaged over
+ * W ~ N(0, I) the sample tends to d_X . M + O(delta^2), zero in open space.
+ * Asynchronous.  RPY_ERR_INVALID_ARG for delta <= 0 or not finite.
+ */
+rpy_status rpy_div_m_rfd(rpy_solver *s, const void *w, double delta, void *lin_out, void *ang_out,
+                         void *hip_stream);
+
+/*
+ * Euler-Maruyama velocities of eq. (bdhi) (Sec. 3.2, LangevinVelocities):
+ *   [lin; ang] = M [F; T] + sqrt(2 kbt / dt) M^{1/2} W + kbt d_X . M,
+ * so that X + dt * lin is one Euler-Maruyama step.  In open space the drift
+ * term is zero.  forces / torques as for rpy_mdot (either may be NULL,
+ * meaning zero; torques need include_angular); w as for rpy_sqrt_mdot_w
+ * (required when kbt > 0, ignored when kbt == 0); the noise term uses the
+ * Lanczos solver with tol and max_iter and is added to the deterministic
+ * part in float64 before one rounding to the solver's dtype.  dt > 0,
+ * kbt >= 0.  lin_out (n x 3) and, with include_angular, ang_out (n x 3) are
+ * required.  iters_out (host, may be NULL) receives the Lanczos iteration
+ * count (0 when kbt == 0).  Synchronises hip_stream when kbt > 0.  Returns
+ * RPY_ERR_NOT_CONVERGED (outputs written with the last Lanczos iterate) or
+ * RPY_ERR_NOT_SPD as rpy_sqrt_mdot_w does.
+ */
+rpy_status rpy_langevin_velocities(rpy_solver *s, const void *forces, const void *torques, const void *w,
+                                   double dt, double kbt, double tol, int max_iter, void *lin_out,
+                                   void *ang_out, int *iters_out, void *hip_stream);
+
+/*
+ * One step of the stochastic Adams-Bashforth scheme used for eq. (bdhi) in
+ * Sec. 5.1, from the stored positions X^n:
+ *   pos_out = X^n + dt (3/2 u^n - 1/2 u^{n-1}) + sqrt(2 kbt dt) (M^n)^{1/2} W^n
+ *   ang_out = dt (3/2 w^n - 1/2 w^{n-1}) + (angular rows of the noise)
+ * with [u; w]^n = M^n [F^n; T^n] + kbt (d_X . M)^n (the drift is zero in
+ * open space).  history (device, 3N entries, 6N with include_angular, linear
+ * first, solver dtype) holds [u; w]^{n-1} on entry when have_history != 0
+ * and receives [u; w]^n on exit; with have_history == 0 the step is the
+ * Euler-Maruyama step (coefficients 1 and 0), which is how a run starts.
+ * The stored positions are not changed: the caller computes the next forces
+ * at pos_out and calls rpy_set_positions(pos_out) before the next step.
+ * pos_out (n x 3) and, with include_angular, ang_out (n x 3; the rotation
+ * increment of the step) are required; w, tol, max_iter, iters_out and the
+ * return codes are as for rpy_langevin_velocities (on NOT_CONVERGED the step
+ * is completed with the last Lanczos iterate).  Synchronises hip_stream when
+ * kbt > 0.
+ */
+rpy_status rpy_ab2_step(rpy_solver *s, const void *forces, const void *torques, const void *w, double dt,
+                        double kbt, double tol, int max_iter, void *history, int have_history, void *pos_out,
+                        void *ang_out, int *iters_out, void *hip_stream);
+
+/*
  * Adjoint of rpy_mdot at the stored positions (an addition beside the
  * paper's method): for cotangents g_U = grad_lin and g_W = grad_ang of a
  * scalar loss with respect to the Mdot outputs, writes

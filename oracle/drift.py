@@ -44,15 +44,25 @@ def divergence_fd(x, delta, a, eta, angular: bool = False):
     return out
 
 
-def rfd_sample(x, w, delta, a, eta, angular: bool = False):
+def rfd_sample(x, w, delta, a, eta, angular: bool = False, round_positions=None, mdot=None):
     """One random finite difference of eq. (rfd) for the noise vector ``w``.
 
     ``w`` has 3N entries (6N with angular terms, linear first); only its
-    positional part displaces the particles.  Returns (linear, angular).
+    positional part displaces the particles.  ``round_positions``, when
+    given, is applied to the two displaced configurations before M is
+    evaluated (to evaluate the sample on positions stored at a lower
+    precision).  ``mdot(x, forces, torques, a, eta) -> (U, Omega)`` replaces
+    the dense product (e.g. the C pair loop on selected rows).  Returns
+    (linear, angular).
     """
+    mdot = mdot_dense if mdot is None else mdot
     n = x.shape[0]
     wp = w[: 3 * n].reshape(n, 3)
     wt = w[3 * n:].reshape(n, 3) if angular else None
-    up, op = mdot_dense(x + 0.5 * delta * wp, wp, wt, a, eta)
-    um, om = mdot_dense(x - 0.5 * delta * wp, wp, wt, a, eta)
+    xp = x + 0.5 * delta * wp
+    xm = x - 0.5 * delta * wp
+    if round_positions is not None:
+        xp, xm = round_positions(xp), round_positions(xm)
+    up, op = mdot(xp, wp, wt, a, eta)
+    um, om = mdot(xm, wp, wt, a, eta)
     return (up - um) / delta, (None if not angular else (op - om) / delta)

@@ -10,8 +10,8 @@ from ._lib import NotConvergedError, RpyError, Status
 
 _lib.load()
 
-from .solver import Batch, Solver, mdot  # noqa: E402
+from .solver import AdamsBashforth, Batch, Solver, mdot  # noqa: E402
 
 NBody = Solver
 
-__all__ = ["Solver", "NBody", "Batch", "mdot", "RpyError", "NotConvergedError", "Status"]
+__all__ = ["Solver", "NBody", "Batch", "AdamsBashforth", "mdot", "RpyError", "NotConvergedError", "Status"]

@@ -76,6 +76,9 @@ def load() -> ctypes.CDLL:
         "rpy_mdot": ([vp, vp, vp, vp, vp, vp], i),
         "rpy_sqrt_mdot_w": ([vp, vp, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_div_m": ([vp, vp, vp, vp], i),
+        "rpy_div_m_rfd": ([vp, vp, d, vp, vp, vp], i),
+        "rpy_langevin_velocities": ([vp, vp, vp, vp, d, d, d, i, vp, vp, ctypes.POINTER(i), vp], i),
+        "rpy_ab2_step": ([vp, vp, vp, vp, d, d, d, i, vp, i, vp, vp, ctypes.POINTER(i), vp], i),
         "rpy_mdot_backward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i),
         "rpy_batch_create": ([ctypes.c_int32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d), i,
                               ctypes.POINTER(vp)], i),
@@ -178,6 +181,41 @@ def rpy_sqrt_mdot_w(h, w, prefactor, tol, max_iter, lin_out, ang_out, dtype, n, 
 def rpy_div_m(h, lin_out, ang_out, dtype, n):
     _check(h, load().rpy_div_m(h, _ptr(lin_out, dtype, 3 * n, "lin_out"),
                                _ptr(ang_out, dtype, 3 * n, "ang_out"), _stream(lin_out)))
+
+
+def rpy_div_m_rfd(h, w, delta, lin_out, ang_out, dtype, n, angular):
+    _check(h, load().rpy_div_m_rfd(h, _ptr(w, dtype, (6 if angular else 3) * n, "W"), float(delta),
+                                   _ptr(lin_out, dtype, 3 * n, "lin_out"), _ptr(ang_out, dtype, 3 * n, "ang_out"),
+                                   _stream(lin_out)))
+
+
+def _step_status(h, st, outs, iters):
+    if st == Status.NOT_CONVERGED:
+        raise NotConvergedError(st, load().rpy_last_error(h).decode(), outs, iters, float("nan"))
+    _check(h, st)
+    return iters
+
+
+def rpy_langevin_velocities(h, forces, torques, w, dt, kbt, tol, max_iter, lin_out, ang_out, dtype, n, angular):
+    iters = ctypes.c_int(0)
+    st = load().rpy_langevin_velocities(
+        h, _ptr(forces, dtype, 3 * n, "forces"), _ptr(torques, dtype, 3 * n, "torques"),
+        _ptr(w, dtype, (6 if angular else 3) * n, "W"), float(dt), float(kbt), float(tol), int(max_iter),
+        _ptr(lin_out, dtype, 3 * n, "lin_out"), _ptr(ang_out, dtype, 3 * n, "ang_out"), ctypes.byref(iters),
+        _stream(lin_out))
+    return _step_status(h, st, (lin_out, ang_out), iters.value)
+
+
+def rpy_ab2_step(h, forces, torques, w, dt, kbt, tol, max_iter, history, have_history, pos_out, ang_out, dtype, n,
+                 angular):
+    iters = ctypes.c_int(0)
+    st = load().rpy_ab2_step(
+        h, _ptr(forces, dtype, 3 * n, "forces"), _ptr(torques, dtype, 3 * n, "torques"),
+        _ptr(w, dtype, (6 if angular else 3) * n, "W"), float(dt), float(kbt), float(tol), int(max_iter),
+        _ptr(history, dtype, (6 if angular else 3) * n, "history"), int(bool(have_history)),
+        _ptr(pos_out, dtype, 3 * n, "pos_out"), _ptr(ang_out, dtype, 3 * n, "ang_out"), ctypes.byref(iters),
+        _stream(pos_out))
+    return _step_status(h, st, (pos_out, ang_out), iters.value)
 
 
 def rpy_mdot_backward(h, forces, torques, grad_lin, grad_ang, grad_pos, grad_forces, grad_torques, dtype, n):

@@ -15,11 +15,13 @@
 // kernels lies inside one system) with fixed-order two-stage reductions, and
 // converged systems drop out of all work.  Every iteration ends with the
 // stopping rule of the single-system solver, decided on the device per
-// system: the quadrature monitor estimates each system's increment, and only
-// systems whose estimate is near tol (or that broke down, or reached
-// max_iter) run the exact eigensolves of T_{k-1} and T_k and the increment
-// test; a system that stops writes its result at once.  The host only polls
-// the number of systems still active, every `check_every` iterations.
+// system: the quadrature monitor computes each system's s_{k-1}, s_k and
+// increment (to rounding, for safely positive definite T_k); only systems
+// whose estimate cannot decide (within 0.1 % of tol, spectrum outside the
+// quadrature's range, breakdown, max_iter) run the exact eigensolves of
+// T_{k-1} and T_k.  A system that stops writes its result at once.  The
+// host only polls the number of systems still active, every `check_every`
+// iterations.
 #include "rpy_device.hpp"
 #include "rpy_krylov.hpp"
 #include "rpy_internal.hpp"
@@ -44,8 +46,9 @@ constexpr int kSegThreads = 256;
 // per-system status (double): beta0, increment, not-SPD flag, running
 // max(|alpha|, beta), first breakdown iteration, iterations at stop
 // (0 while active), result code (0 ok, 1 not converged, 2 not SPD),
-// estimated increment (quadrature monitor)
-enum { BS_BETA0 = 0, BS_INCR, BS_NSPD, BS_TSCALE, BS_BREAK, BS_DONE, BS_CODE, BS_EST, BS_SIZE = 8 };
+// estimated increment (quadrature monitor), source of the final s (0 the
+// eigensolver, 1 the quadrature estimate), spare
+enum { BS_BETA0 = 0, BS_INCR, BS_NSPD, BS_TSCALE, BS_BREAK, BS_DONE, BS_CODE, BS_EST, BS_SRC, BS_SIZE = 10 };
 
 // ---------------------------------------------------------------------------
 // persistent batched pair kernel
@@ -355,7 +358,7 @@ batch_tridiag(const double *__restrict__ alpha, const double *__restrict__ beta,
               double *__restrict__ s_prev, double *__restrict__ s_cur, double *__restrict__ Q, int64_t qstride,
               double *__restrict__ status, const int *__restrict__ need, const int *__restrict__ kdev) {
     const int s = blockIdx.y;
-    if (need[s] == 0) return;
+    if (need[s] != 1) return;
     const int kc = kdev[0] - 1;
     const int kk = kc - 1 + (int)blockIdx.x;
     if (kk <= 0) return;
@@ -366,14 +369,14 @@ batch_tridiag(const double *__restrict__ alpha, const double *__restrict__ beta,
 }
 
 // status[slot] of system s = |b - [a; 0]| / |b| for the vectors a (length
-// k-1) and b (length k) of the system, k = kdev[0] - koff; systems with
-// gate[s] == 0 are skipped.
+// k-1) and b (length k) of the system, k = kdev[0] - koff, for the systems
+// with gate[s] == 1.
 __global__ void batch_increment(const double *__restrict__ s_prev, const double *__restrict__ s_cur, int64_t lstride,
                                 double *__restrict__ status, const int *__restrict__ gate,
                                 const int *__restrict__ kdev, int koff, int slot) {
     __shared__ double red[kSegThreads];
     const int s = blockIdx.x;
-    if (gate[s] == 0) return;
+    if (gate[s] != 1) return;
     const int k = kdev[0] - koff;
     const double *a = s_prev + (size_t)s * lstride, *b = s_cur + (size_t)s * lstride;
     double num = 0.0, den = 0.0;
@@ -404,9 +407,14 @@ batch_monitor(const double *__restrict__ alpha, const double *__restrict__ beta,
                   (blockIdx.x == 0 ? est_prev : est_cur) + (size_t)s * lstride);
 }
 
-// need[s] = 1 for the active systems that take the exact test after
-// iteration k = kdev[0]: estimated increment below 1.01 tol or not finite,
-// a recorded breakdown, the iteration cap, or every iteration (`every`)
+// Decision after iteration k = kdev[0] for every active system:
+//   need[s] = 1  take the exact test (eigensolves of T_{k-1}, T_k): a
+//                recorded breakdown, the iteration cap, an estimate that is
+//                NaN (spectrum outside the quadrature's range) or within
+//                0.1 % of tol, or every iteration (`every`);
+//   need[s] = 2  converged on the estimate (below tol, which is accurate to
+//                rounding), the result uses the quadrature s_k;
+//   need[s] = 0  continue.
 __global__ void batch_flag(const double *__restrict__ status, const int *__restrict__ active, int *__restrict__ need,
                            int nsys, int kcap, double tol, int every, const int *__restrict__ kdev) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -416,7 +424,11 @@ __global__ void batch_flag(const double *__restrict__ status, const int *__restr
     int f = 0;
     if (active[s] != 0) {
         const double est = st[BS_EST];
-        f = every || k >= kcap || st[BS_BREAK] > 0.0 || (k >= 2 && (!isfinite(est) || est < tol * 1.01));
+        if (every || k >= kcap || st[BS_BREAK] > 0.0 ||
+            (k >= 2 && (!isfinite(est) || fabs(est - tol) <= 1e-3 * tol)))
+            f = 1;
+        else if (k >= 2 && est < tol)
+            f = 2;
     }
     need[s] = f;
 }
@@ -437,6 +449,16 @@ __global__ void batch_converge(double *__restrict__ status, int *__restrict__ ac
             continue;
         }
         double *st = status + (size_t)s * BS_SIZE;
+        if (need[s] == 2) {   // converged on the quadrature estimate
+            st[BS_INCR] = st[BS_EST];
+            st[BS_DONE] = (double)kc;
+            st[BS_CODE] = 0.0;
+            st[BS_SRC] = 1.0;
+            active[s] = 0;
+            fresh[s] = 1;
+            continue;
+        }
+        st[BS_SRC] = 0.0;
         const int kb = (int)st[BS_BREAK];
         int done = 0;
         double code = 0.0;
@@ -472,15 +494,17 @@ __global__ void batch_converge(double *__restrict__ status, int *__restrict__ ac
 // y_s = prefactor beta0_s V_{k_s} s_s for every system that just stopped
 template <typename Tout>
 __global__ void batch_combine(const double *__restrict__ V, int64_t ld, const double *__restrict__ s_cur,
-                              int64_t lstride, const double *__restrict__ status, const int *__restrict__ fresh,
-                              const double *__restrict__ prefactor, SegMap m, Tout *__restrict__ out) {
+                              const double *__restrict__ s_est, int64_t lstride, const double *__restrict__ status,
+                              const int *__restrict__ fresh, const double *__restrict__ prefactor, SegMap m,
+                              Tout *__restrict__ out) {
     __shared__ double hs[kMaxK];
     const int s = m.sys[blockIdx.x];
     if (fresh[s] == 0) return;
     const int64_t lo = m.lo[blockIdx.x], hi = m.hi[blockIdx.x];
     const double *st = status + (size_t)s * BS_SIZE;
     const int kf = (int)st[BS_DONE];
-    for (int j = threadIdx.x; j < kf; j += blockDim.x) hs[j] = s_cur[(size_t)s * lstride + j];
+    const double *src = (st[BS_SRC] != 0.0 ? s_est : s_cur) + (size_t)s * lstride;
+    for (int j = threadIdx.x; j < kf; j += blockDim.x) hs[j] = src[j];
     __syncthreads();
     const double scale = prefactor[0] * st[BS_BETA0];
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
@@ -638,8 +662,8 @@ void enqueue_iteration(rpy_batch *b, int kcap, double tol, int every, Real *out,
                        b->status.as<double>(), need, kdev, 1, (int)BS_INCR);
     hipLaunchKernelGGL(batch_converge, dim3(1), dim3(kSegThreads), 0, st, b->status.as<double>(), active, fresh, need,
                        kcap, b->nsys, tol, kdev);
-    hipLaunchKernelGGL((batch_combine<Real>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, V, ld, s_cur, L,
-                       b->status.as<double>(), fresh, b->pref.as<double>(), m, out);
+    hipLaunchKernelGGL((batch_combine<Real>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, V, ld, s_cur, e_cur,
+                       L, b->status.as<double>(), fresh, b->pref.as<double>(), m, out);
     hipLaunchKernelGGL(clear_ints, dim3((unsigned)((b->nsys + 255) / 256)), dim3(256), 0, st, fresh, b->nsys);
 }
 

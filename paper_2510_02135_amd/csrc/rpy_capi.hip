@@ -36,13 +36,13 @@ int splits_for(const rpy_solver *s, bool ang) {
 // M [F; T] for the stored positions with F, T already staged in s->f / s->t.
 // Output type Tout: the caller's dtype, or double for Lanczos products.
 template <typename Real, typename Tout>
-rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *angout, hipStream_t st) {
+rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *angout, hipStream_t st, const void *pos_in) {
     const int64_t n = s->n;
     const int splits = splits_for(s, ang);
     const int nc = (ang ? 6 : 3) * (std::is_same<Real, float>::value ? 2 : 1);
     HIP_TRY(s, s->part.ensure((size_t)splits * nc * n * sizeof(Real)));
     const PairConst<Real> pc = make_pair_const<Real>(s->radius);
-    const auto *pos = s->pos.as<vec4_t<Real>>();
+    const auto *pos = pos_in ? static_cast<const vec4_t<Real> *>(pos_in) : s->pos.as<vec4_t<Real>>();
     const auto *f = s->f.as<vec4_t<Real>>();
     const auto *t = s->t.as<vec4_t<Real>>();
     hipEvent_t e0 = timing_begin(s, RPY_KERNEL_PAIR, (double)n * (double)n);
@@ -80,9 +80,10 @@ hipEvent_t timing_end(rpy_solver *s, int kind) {
     return s->ev[kind][s->ev_used[kind]++].second;
 }
 
-template rpy_status apply_staged<float, float>(rpy_solver *, bool, float *, float *, hipStream_t);
-template rpy_status apply_staged<float, double>(rpy_solver *, bool, double *, double *, hipStream_t);
-template rpy_status apply_staged<double, double>(rpy_solver *, bool, double *, double *, hipStream_t);
+template rpy_status apply_staged<float, float>(rpy_solver *, bool, float *, float *, hipStream_t, const void *);
+template rpy_status apply_staged<float, double>(rpy_solver *, bool, double *, double *, hipStream_t, const void *);
+template rpy_status apply_staged<double, double>(rpy_solver *, bool, double *, double *, hipStream_t,
+                                                 const void *);
 
 rpy_status ensure_vec_buffers(rpy_solver *s, bool ang) {
     const size_t elt = s->dtype == RPY_F64 ? sizeof(double4) : sizeof(float4);
@@ -247,7 +248,7 @@ const char *rpy_last_error(const rpy_solver *s) { return s ? s->err.c_str() : "n
 void rpy_destroy(rpy_solver *s) {
     if (!s) return;
     for (DevBuf *b : {&s->pos, &s->f, &s->t, &s->part, &s->flag, &s->lz_basis, &s->lz_w, &s->lz_scal, &s->lz_red,
-                      &s->lz_q, &s->lz_vec, &s->lz_mon})
+                      &s->lz_q, &s->lz_vec, &s->lz_mon, &s->drift})
         b->release();
     for (auto &v : s->ev)
         for (auto &pr : v) {

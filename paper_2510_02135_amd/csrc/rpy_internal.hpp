@@ -73,7 +73,7 @@ struct rpy_solver {
     rpy::TileConfig cfg[2];   // pair-kernel tiles for products without / with the angular blocks
     rpy::DevBuf pos, f, t, part, flag;
     // Lanczos workspace (float64): basis, scratch vectors, tridiagonal data
-    rpy::DevBuf lz_basis, lz_w, lz_scal, lz_red, lz_q, lz_vec, lz_mon;
+    rpy::DevBuf lz_basis, lz_w, lz_scal, lz_red, lz_q, lz_vec, lz_mon, drift;
     // launch timing (rpy_enable_timing): event pairs and pair counts per kernel class
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];

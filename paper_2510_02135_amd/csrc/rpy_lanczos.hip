@@ -15,11 +15,11 @@
 //   v_{k+1} = w / beta_k.
 // The host reads a small status block after each iteration to decide
 // whether to stop (first k >= 2 with increment < tol; a clearly negative
-// Ritz value; beta_k ~ 0 meaning the Krylov space is invariant).  The
-// eigensolver runs only at iterations where a cheap quadrature estimate of
-// the increment says the test may pass.  The final
-// y = prefactor * beta_0 V_k s_k is formed on the device and written in the
-// caller's dtype.
+// Ritz value; beta_k ~ 0 meaning the Krylov space is invariant).  s_{k-1}
+// and s_k come from a quadrature estimate of T^{1/2} e_1 that is exact to
+// rounding for safely positive definite T_k; the eigensolver runs only where
+// that estimate cannot decide.  The final y = prefactor * beta_0 V_k s_k is
+// formed on the device and written in the caller's dtype.
 //
 // Reductions are two-stage with a fixed block count and fixed order, so the
 // result does not depend on scheduling.
@@ -95,35 +95,61 @@ __global__ void sumsq_partial(const Tin *__restrict__ w, int64_t n, double *__re
 }
 
 // partial[b * k + j] = sum over block b's rows of V[j][i] w[i], j < k.
-// Block b owns one contiguous slab of rows; each wavefront takes groups of
-// kCols basis columns (every kWaves-th group), keeps the loads of all of
-// them in flight while it walks its slab with coalesced reads, and reduces
-// across lanes by shuffles, so no workgroup barrier is needed.
-constexpr int kGemvBlocks = 1024;
+// A block owns chunks of kGtRows * 256 consecutive rows (chunk b, b + grid,
+// ...); each thread keeps its kGtRows entries of w in registers and, per
+// tile of kGtCols basis columns, issues all kGtRows * kGtCols coalesced loads
+// before one LDS reduction of the tile, so many loads are in flight per wave.
+// Every sum has a fixed order (deterministic).
+constexpr int kGemvBlocks = 1024;   // upper bound of the grid (partials per column)
+constexpr int kGtRows = 4;
+constexpr int kGtCols = 8;
 __global__ void __launch_bounds__(kRedThreads)
 gemv_t_partial(const double *__restrict__ V, int64_t ld, int k, const double *__restrict__ w, int64_t n,
                double *__restrict__ partial) {
-    constexpr int kWaves = kRedThreads / 64, kCols = 4;
-    int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    chunk = (chunk + 63) / 64 * 64;
-    const int64_t i0 = (int64_t)blockIdx.x * chunk;
-    const int64_t i1 = std::min<int64_t>(n, i0 + chunk);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int j0 = wv * kCols; j0 < k; j0 += kWaves * kCols) {
-        const int nc = std::min(kCols, k - j0);
-        const double *col = V + (size_t)j0 * ld;
-        double acc[kCols] = {};
-        for (int64_t i = i0 + lane; i < i1; i += 64) {
-            const double wi = w[i];
+    static_assert(kRedThreads == 256 && kGtCols * 32 == kRedThreads, "tile reduction layout");
+    __shared__ double sh[kGtCols][kRedThreads];
+    const int tid = threadIdx.x;
+    const int gc = tid >> 5, gl = tid & 31;    // reduction: 32 threads per column of the tile
+    const int64_t chunk_rows = (int64_t)kGtRows * kRedThreads;
+    const int64_t nchunks = (n + chunk_rows - 1) / chunk_rows;
+    bool first = true;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t base = ch * chunk_rows + tid;
+        double wr[kGtRows];
 #pragma unroll
-            for (int c = 0; c < kCols; ++c)
-                if (c < nc) acc[c] = fma(col[(size_t)c * ld + i], wi, acc[c]);
+        for (int q = 0; q < kGtRows; ++q) {
+            const int64_t i = base + (int64_t)q * kRedThreads;
+            wr[q] = i < n ? w[i] : 0.0;
         }
+        for (int j0 = 0; j0 < k; j0 += kGtCols) {
+            double acc[kGtCols];
 #pragma unroll
-        for (int c = 0; c < kCols; ++c) {
-            const double r = wave_sum(acc[c]);
-            if (lane == 0 && c < nc) partial[(size_t)blockIdx.x * k + j0 + c] = r;
+            for (int c = 0; c < kGtCols; ++c) {
+                acc[c] = 0.0;
+                if (j0 + c < k) {
+                    const double *col = V + (size_t)(j0 + c) * ld;
+#pragma unroll
+                    for (int q = 0; q < kGtRows; ++q) {
+                        const int64_t i = base + (int64_t)q * kRedThreads;
+                        if (i < n) acc[c] = fma(col[i], wr[q], acc[c]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kGtCols; ++c) sh[c][tid] = acc[c];
+            __syncthreads();
+            double v = 0.0;
+#pragma unroll
+            for (int m = 0; m < kRedThreads / 32; ++m) v += sh[gc][gl + 32 * m];
+#pragma unroll
+            for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 32);
+            if (gl == 0 && j0 + gc < k) {
+                double *dst = partial + (size_t)blockIdx.x * k + j0 + gc;
+                *dst = first ? v : *dst + v;
+            }
+            __syncthreads();
         }
+        first = false;
     }
 }
 
@@ -150,12 +176,13 @@ __global__ void gemv_n_sub(const double *__restrict__ V, int64_t ld, int k, cons
     }
 }
 
-// out = scale * sum_j V[j][i] s[j], written as n_lin linear entries to lin and
-// the rest to ang (caller's dtype).
+// out = scale * sum_j V[j][i] s[j] (or out + that, with `accumulate`),
+// written as n_lin linear entries to lin and the rest to ang (caller's
+// dtype; the sum is formed in float64 and rounded once).
 template <typename Tout>
 __global__ void combine_out(const double *__restrict__ V, int64_t ld, int k, const double *__restrict__ s,
                             const double *__restrict__ status, double prefactor, int64_t n, int64_t n_lin,
-                            Tout *__restrict__ lin, Tout *__restrict__ ang) {
+                            int accumulate, Tout *__restrict__ lin, Tout *__restrict__ ang) {
     __shared__ double hs[kMaxK];
     for (int j = threadIdx.x; j < k; j += blockDim.x) hs[j] = s[j];
     __syncthreads();
@@ -163,11 +190,9 @@ __global__ void combine_out(const double *__restrict__ V, int64_t ld, int k, con
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double acc = 0.0;
         for (int j = 0; j < k; ++j) acc = fma(V[(size_t)j * ld + i], hs[j], acc);
-        const Tout v = (Tout)(scale * acc);
-        if (i < n_lin)
-            lin[i] = v;
-        else
-            ang[i - n_lin] = v;
+        Tout *dst = i < n_lin ? lin + i : ang + (i - n_lin);
+        const double base = accumulate ? (double)*dst : 0.0;
+        *dst = (Tout)(base + scale * acc);
     }
 }
 
@@ -246,7 +271,7 @@ int grid_for(int64_t n) { return (int)std::min<int64_t>(2048, std::max<int64_t>(
 
 template <typename Tio>
 rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double tol, int max_iter, Tio *lin,
-                       Tio *ang, int *iters_out, double *incr_out, hipStream_t st) {
+                       Tio *ang, int *iters_out, double *incr_out, hipStream_t st, bool accumulate) {
     const bool ang_mode = s->angular;
     const int64_t np = s->n;
     const int64_t n = (ang_mode ? 6 : 3) * np;
@@ -300,24 +325,31 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
     if (iters_out) *iters_out = 0;
     if (incr_out) *incr_out = 0.0;
     if (beta0 == 0.0) {
-        HIP_TRY(s, launch_fill_zero<Tio>(lin, 3 * np, st));
-        if (ang) HIP_TRY(s, launch_fill_zero<Tio>(ang, 3 * np, st));
+        if (!accumulate) {
+            HIP_TRY(s, launch_fill_zero<Tio>(lin, 3 * np, st));
+            if (ang) HIP_TRY(s, launch_fill_zero<Tio>(ang, 3 * np, st));
+        }
         return RPY_OK;
     }
     hipLaunchKernelGGL((init_basis<Tio>), dim3(grid_for(n)), dim3(256), 0, st, L.V, w_in, L.status + ST_BETA0, n);
     HIP_TRY(s, hipGetLastError());
 
-    // The increment test needs s_{k-1} and s_k from the eigensolver.  Each
-    // iteration k >= 2 runs the quadrature monitor instead, and the exact
-    // test runs only when the estimated increment is within 1% of tol (or is
-    // not finite, or at max_iter, or after a breakdown), so the loop stops
-    // at the same first k as testing every iteration.  RPY_LANCZOS_CHECK=every
-    // runs the exact test at every iteration.
+    // The increment test needs s_{k-1} and s_k.  Each iteration k >= 2
+    // computes both by the quadrature monitor, accurate to rounding while
+    // T_k's spectrum lies in [1e-10 g, g] (checked by an LDL^T factorisation;
+    // otherwise the estimate is NaN).  The eigensolver (exact test, and the
+    // exact s_k for the result) runs only when the estimate cannot decide:
+    // within 0.1 % of tol, NaN, after a breakdown, or at max_iter.  The loop
+    // therefore stops at the same first k as the exact test at every
+    // iteration.  RPY_LANCZOS_CHECK=every runs the exact test at every
+    // iteration and never uses the estimate.
     const char *check_env = std::getenv("RPY_LANCZOS_CHECK");
     const bool check_every = check_env && std::string(check_env) == "every";
     const int g = grid_for(n);
+    const int gt_blocks = (int)std::min<int64_t>(kGemvBlocks, (n + kGtRows * kRedThreads - 1) / (kGtRows * kRedThreads));
     int k = 0, kf = 0;
     double incr = INFINITY;
+    const double *s_final = L.s;   // exact s_k unless the estimate decided
     bool converged = false, not_spd = false;
     for (k = 1; k <= kmax; ++k) {
         const double *vk = L.V + (size_t)(k - 1) * ld;
@@ -343,8 +375,8 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
         hipEvent_t cgs0 = timing_begin(s, RPY_KERNEL_LANCZOS_CGS, 2.0 * (2.0 * k + 3.0) * (double)n * 8.0);
         if (cgs0) HIP_TRY(s, hipEventRecord(cgs0, st));
         for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(gemv_t_partial, dim3(kGemvBlocks), dim3(kRedThreads), 0, st, L.V, ld, k, L.w, n, L.red);
-            hipLaunchKernelGGL(gemv_t_final, dim3(k), dim3(kRedThreads), 0, st, L.red, kGemvBlocks, k, L.h);
+            hipLaunchKernelGGL(gemv_t_partial, dim3(gt_blocks), dim3(kRedThreads), 0, st, L.V, ld, k, L.w, n, L.red);
+            hipLaunchKernelGGL(gemv_t_final, dim3(k), dim3(kRedThreads), 0, st, L.red, gt_blocks, k, L.h);
             hipLaunchKernelGGL(gemv_n_sub, dim3(g), dim3(256), 0, st, L.V, ld, k, L.h, L.w, n);
         }
         if (hipEvent_t cgs1 = timing_end(s, RPY_KERNEL_LANCZOS_CGS)) HIP_TRY(s, hipEventRecord(cgs1, st));
@@ -364,7 +396,18 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
             HIP_TRY(s, hipMemcpyAsync(s->host_scal, L.status, sizeof(double) * ST_SIZE, hipMemcpyDeviceToHost, st));
             HIP_TRY(s, hipStreamSynchronize(st));
             const double est = s->host_scal[ST_EST];
-            exact = s->host_scal[ST_BREAK] > 0.0 || !std::isfinite(est) || est < tol * 1.01;
+            // the exact test only where the estimate cannot decide: a breakdown,
+            // an eigenvalue outside the quadrature's range (NaN), or an
+            // estimate within 0.1 % of tol
+            exact = s->host_scal[ST_BREAK] > 0.0 || !std::isfinite(est) || std::fabs(est - tol) <= 1e-3 * tol;
+            if (!exact && est < tol) {
+                // converged: the quadrature s_k is T_k^{1/2} e_1 to rounding
+                incr = est;
+                kf = k;
+                s_final = L.est1;
+                converged = true;
+                break;
+            }
         }
         if (exact) {
             hipLaunchKernelGGL(tridiag_sqrt_kernel, dim3(2), dim3(kEigThreads), 0, st, L.alpha, L.beta, k, L.s_prev,
@@ -396,8 +439,8 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
         hipLaunchKernelGGL(next_basis_kernel, dim3(g), dim3(256), 0, st, L.V + (size_t)k * ld, L.w, L.beta + (k - 1),
                            L.status, n);
     }
-    hipLaunchKernelGGL((combine_out<Tio>), dim3(g), dim3(256), 0, st, L.V, ld, kf, L.s, L.status, prefactor, n,
-                       3 * np, lin, ang);
+    hipLaunchKernelGGL((combine_out<Tio>), dim3(g), dim3(256), 0, st, L.V, ld, kf, s_final, L.status, prefactor, n,
+                       3 * np, accumulate ? 1 : 0, lin, ang);
     HIP_TRY(s, hipGetLastError());
     HIP_TRY(s, hipStreamSynchronize(st));
     if (iters_out) *iters_out = kf;
@@ -409,9 +452,9 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
 }
 
 template rpy_status lanczos_run<float>(rpy_solver *, const float *, double, double, int, float *, float *, int *,
-                                       double *, hipStream_t);
+                                       double *, hipStream_t, bool);
 template rpy_status lanczos_run<double>(rpy_solver *, const double *, double, double, int, double *, double *, int *,
-                                        double *, hipStream_t);
+                                        double *, hipStream_t, bool);
 
 }  // namespace rpy
 
@@ -431,7 +474,7 @@ extern "C" rpy_status rpy_sqrt_mdot_w(rpy_solver *s, const void *w, double prefa
     if (s->dtype == RPY_F64)
         return lanczos_run<double>(s, static_cast<const double *>(w), prefactor, tol, max_iter,
                                    static_cast<double *>(lin_out), static_cast<double *>(ang_out), iters_out,
-                                   incr_out, st);
+                                   incr_out, st, false);
     return lanczos_run<float>(s, static_cast<const float *>(w), prefactor, tol, max_iter, static_cast<float *>(lin_out),
-                              static_cast<float *>(ang_out), iters_out, incr_out, st);
+                              static_cast<float *>(ang_out), iters_out, incr_out, st, false);
 }

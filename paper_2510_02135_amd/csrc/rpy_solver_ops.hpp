@@ -20,9 +20,18 @@ hipEvent_t timing_begin(rpy_solver *s, int kind, double pairs);
 hipEvent_t timing_end(rpy_solver *s, int kind);
 
 // M [F; T] with F (and T) already staged in s->f (s->t); Real is the pair
-// precision, Tout the output element type.  ang_out may be NULL.
+// precision, Tout the output element type.  ang_out may be NULL.  `pos`
+// replaces the stored positions when not NULL (vec4_t<Real>, N entries).
 template <typename Real, typename Tout>
-rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *ang_out, hipStream_t st);
+rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *ang_out, hipStream_t st,
+                        const void *pos = nullptr);
+
+// prefactor * M^{1/2} W by Lanczos for the stored positions (W and the
+// outputs in the solver's dtype Tio); with `accumulate` the result is added
+// to lin/ang instead of overwriting them.  Synchronises `st`.
+template <typename Tio>
+rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double tol, int max_iter, Tio *lin,
+                       Tio *ang, int *iters_out, double *incr_out, hipStream_t st, bool accumulate);
 
 }  // namespace rpy
 

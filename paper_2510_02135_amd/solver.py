@@ -2,16 +2,19 @@
 
 ``Solver`` mirrors the libMobility solver classes: constructor with per-axis
 periodicity, ``setParameters``, ``initialize``, ``setPositions``, ``Mdot``,
-``sqrtMdotW`` and ``divM``, each returning (linear, angular).  Only torch
-device tensors are accepted; results are new tensors of the input dtype on
-the same device.  ``mdot`` is the differentiable form: a
-``torch.autograd.Function`` whose backward calls the library's adjoint.
+``sqrtMdotW``, ``divM`` and ``LangevinVelocities``, each returning (linear,
+angular), plus ``divM_rfd`` (one random finite difference of the drift,
+eq. (rfd)).  ``AdamsBashforth`` steps eq. (bdhi) with the scheme of
+Sec. 5.1.  Only torch device tensors are accepted; results are new tensors
+of the input dtype on the same device.  ``mdot`` is the differentiable form:
+a ``torch.autograd.Function`` whose backward calls the library's adjoint.
 """
 from __future__ import annotations
 
 import torch
 
 from . import _lib
+from ._lib import NotConvergedError
 
 
 class Solver:
@@ -111,6 +114,50 @@ class Solver:
         _lib.rpy_div_m(self._h, lin, ang, self._dtype, self._n)
         return lin, ang
 
+    def divM_rfd(self, W: torch.Tensor | None = None, delta: float | None = None,
+                 generator: torch.Generator | None = None):
+        """One random finite difference of the drift, eq. (rfd):
+        (M(X + delta/2 W_X) W - M(X - delta/2 W_X) W) / delta.  W ~ N(0, I)
+        is drawn when not given (3N, or 6N with angular terms); delta
+        defaults to 1e-3 a (float32) or 1e-4 a (float64)."""
+        self._require_positions()
+        dim = (6 if self._angular else 3) * self._n
+        if W is None:
+            W = torch.randn(dim, dtype=self._dtype, device=self._device, generator=generator)
+        w = W.reshape(-1)
+        if w.dtype != self._dtype:
+            raise ValueError(f"DTYPE_MISMATCH: W is {w.dtype}, positions are {self._dtype}")
+        if delta is None:
+            delta = (1e-3 if self._dtype == torch.float32 else 1e-4) * self.hydrodynamicRadius
+        lin = self._empty()
+        ang = self._empty() if self._angular else None
+        _lib.rpy_div_m_rfd(self._h, w.contiguous(), delta, lin, ang, self._dtype, self._n, self._angular)
+        return lin, ang
+
+    def LangevinVelocities(self, forces=None, torques=None, dt: float = 1.0, kBT: float = 0.0,
+                           W: torch.Tensor | None = None, tol: float = 1e-6, maxIter: int = 500,
+                           generator: torch.Generator | None = None):
+        """Euler-Maruyama velocities of eq. (bdhi):
+        M [F; T] + sqrt(2 kBT / dt) M^{1/2} W + kBT d_X . M (drift zero in
+        open space).  W ~ N(0, I) is drawn when kBT > 0 and W is not given."""
+        self._require_positions()
+        f, t = self._as(forces, "forces"), self._as(torques, "torques")
+        w = self._noise(W, generator) if kBT > 0 else None
+        lin = self._empty()
+        ang = self._empty() if self._angular else None
+        self.last_iterations = _lib.rpy_langevin_velocities(self._h, f, t, w, dt, kBT, tol, maxIter, lin, ang,
+                                                            self._dtype, self._n, self._angular)
+        return lin, ang
+
+    def _noise(self, W, generator):
+        dim = (6 if self._angular else 3) * self._n
+        if W is None:
+            W = torch.randn(dim, dtype=self._dtype, device=self._device, generator=generator)
+        w = W.reshape(-1)
+        if w.dtype != self._dtype:
+            raise ValueError(f"DTYPE_MISMATCH: W is {w.dtype}, positions are {self._dtype}")
+        return w.contiguous()
+
     def Mdot_backward(self, forces, torques, grad_lin, grad_ang=None, need_pos=True,
                       need_forces=True, need_torques=True):
         """(dL/dX, dL/dF, dL/dT) for cotangents of the Mdot outputs."""
@@ -192,6 +239,55 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class AdamsBashforth:
+    """The stochastic Adams-Bashforth scheme of Sec. 5.1 on a Solver:
+
+        X^{n+1} = X^n + dt (3/2 u^n - 1/2 u^{n-1}) + sqrt(2 kBT dt) (M^n)^{1/2} W^n,
+        u^n = M^n [F^n; T^n] + kBT (d_X . M)^n,
+
+    starting with one Euler-Maruyama step.  ``step`` uses the solver's
+    current positions, returns (X^{n+1}, rotation increment or None) and
+    stores X^{n+1} in the solver for the next step.  The scheme's history
+    u^{n-1} lives in a device buffer owned by this object."""
+
+    def __init__(self, solver: "Solver", dt: float, kBT: float = 0.0, tol: float = 1e-6, maxIter: int = 500):
+        self.solver, self.dt, self.kBT, self.tol, self.maxIter = solver, float(dt), float(kBT), tol, maxIter
+        self._hist = None
+        self._have = False
+        self.last_iterations = 0
+        self.positions = None     # X^{n+1} of the last step (also stored in the solver)
+
+    def reset(self):
+        """Forget the history: the next step is an Euler-Maruyama step."""
+        self._have = False
+
+    def step(self, forces=None, torques=None, W: torch.Tensor | None = None,
+             generator: torch.Generator | None = None):
+        s = self.solver
+        s._require_positions()
+        f, t = s._as(forces, "forces"), s._as(torques, "torques")
+        w = s._noise(W, generator) if self.kBT > 0 else None
+        dim = (6 if s._angular else 3) * s._n
+        if self._hist is None or self._hist.numel() != dim or self._hist.dtype != s._dtype:
+            self._hist = torch.empty(dim, dtype=s._dtype, device=s._device)
+            self._have = False
+        pos = s._empty()
+        ang = s._empty() if s._angular else None
+        try:
+            self.last_iterations = _lib.rpy_ab2_step(s._h, f, t, w, self.dt, self.kBT, self.tol, self.maxIter,
+                                                     self._hist, self._have, pos, ang, s._dtype, s._n, s._angular)
+        except NotConvergedError:
+            # the step was completed with the last Lanczos iterate
+            self._have = True
+            s.setPositions(pos)
+            self.positions = pos
+            raise
+        self._have = True
+        s.setPositions(pos)
+        self.positions = pos
+        return pos, ang
 
 
 class _MdotFunction(torch.autograd.Function):

@@ -63,8 +63,8 @@ def test_batched_lanczos_matched_iterations_and_eager_replay(dtype, monkeypatch)
     lies within rounding of tol), matches the oracle's Lanczos at the
     iteration count the batch reports, and the eager single-system solver
     stopped at that iteration (every replay of the captured graph
-    contributes).  The host poll interval and the exact test at every
-    iteration change nothing."""
+    contributes).  The host poll interval changes nothing; the exact test at
+    every iteration changes nothing but the rounding of s_k."""
     import paper_2510_02135_amd as rpy
     sizes = [1, 5, 40, 97, 200, 333]
     say(f"case batch lanczos sizes={sizes} {dtype}")
@@ -81,7 +81,10 @@ def test_batched_lanczos_matched_iterations_and_eager_replay(dtype, monkeypatch)
     Ye = host(b.sqrtMdotW(W, prefactor=0.7, tol=1e-6, checkEvery=5)).reshape(-1)
     monkeypatch.delenv("RPY_LANCZOS_CHECK")
     assert list(b.last_iterations) == iters
-    np.testing.assert_array_equal(Y, Ye)
+    # the default takes s_k from the quadrature estimate (exact to rounding),
+    # the every-iteration test from the eigensolver
+    scale = np.abs(Ye).max()
+    assert np.abs(Y - Ye).max() <= (1e-13 if dtype == torch.float64 else 4 * 2.0 ** -24) * scale
     a, eta = 1.0, 1 / (6 * math.pi)
     for k, (x, f, w) in enumerate(systems):
         xr, wr = rounded(x, dtype), rounded(w, dtype)

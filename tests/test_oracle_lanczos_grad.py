@@ -167,3 +167,25 @@ def test_random_finite_differences_average_to_zero():
     assert np.all(np.abs(mean) <= 5 * se)
     det = drift.divergence_fd(x, 1e-4, A, ETA)
     assert np.abs(det - 0).max() < 1e-8
+
+
+@pytest.mark.parametrize("angular", [False, True])
+def test_rfd_sample_is_the_directional_derivative(angular):
+    """One random finite difference [eq. (rfd)] equals (M'(X)[W_X]) W, the
+    derivative of M along the positional part of W applied to W, up to
+    O(delta^2): checked against the complex-step derivative of the oracle's
+    mobility along W_X (independent of the difference formula; a sign or
+    factor slip in either the displacement or the 1/delta fails)."""
+    x, rng = _system(30, 9.0, 28)          # overlapping and far pairs
+    w = rng.standard_normal(6 * 30 if angular else 3 * 30)
+    delta = 1e-5
+    lin, ang = drift.rfd_sample(x, w, delta, A, ETA, angular)
+    wp = w[:90].reshape(30, 3)
+    wt = w[90:].reshape(30, 3) if angular else None
+    h = 1e-30
+    u, om = mob.mdot_dense(x.astype(np.complex128) + 1j * h * wp, wp, wt, A, ETA)
+    du = np.imag(u) / h
+    assert np.abs(lin - du).max() <= 1e-7 * np.abs(du).max()
+    if angular:
+        dom = np.imag(om) / h
+        assert np.abs(ang - dom).max() <= 1e-7 * np.abs(dom).max()
