@@ -94,63 +94,63 @@ __global__ void sumsq_partial(const Tin *__restrict__ w, int64_t n, double *__re
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
-// partial[b * k + j] = sum over block b's rows of V[j][i] w[i], j < k.
-// A block owns chunks of kGtRows * 256 consecutive rows (chunk b, b + grid,
-// ...); each thread keeps its kGtRows entries of w in registers and, per
-// tile of kGtCols basis columns, issues all kGtRows * kGtCols coalesced loads
-// before one LDS reduction of the tile, so many loads are in flight per wave.
-// Every sum has a fixed order (deterministic).
-constexpr int kGemvBlocks = 1024;   // upper bound of the grid (partials per column)
+// partial[b * k + j] = sum over row chunk b of V[j][i] w[i], j < k.
+// Grid (row chunks of kGtRows * 256 rows) x (groups of kGtCols columns):
+// each thread keeps its kGtRows entries of w in registers and issues all
+// kGtRows * kGtCols coalesced loads of its tile at once (unguarded in the
+// interior), then the block reduces the tile's columns through LDS.  Every
+// sum has a fixed order (deterministic).
 constexpr int kGtRows = 4;
-constexpr int kGtCols = 8;
+constexpr int kGtCols = 16;
+constexpr int kGtChunk = kGtRows * kRedThreads;   // rows per chunk
+template <bool GUARD>
+__device__ __forceinline__ void gemv_t_tile(const double *__restrict__ V, int64_t ld, int j0, int k,
+                                            const double *__restrict__ w, int64_t n, int64_t base,
+                                            double (&acc)[kGtCols]) {
+    double wr[kGtRows];
+#pragma unroll
+    for (int q = 0; q < kGtRows; ++q) {
+        const int64_t i = base + (int64_t)q * kRedThreads;
+        wr[q] = (!GUARD || i < n) ? w[i] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < kGtCols; ++c) {
+        acc[c] = 0.0;
+        if (!GUARD || j0 + c < k) {
+            const double *col = V + (size_t)(j0 + c) * ld;
+#pragma unroll
+            for (int q = 0; q < kGtRows; ++q) {
+                const int64_t i = base + (int64_t)q * kRedThreads;
+                if (!GUARD || i < n) acc[c] = fma(col[i], wr[q], acc[c]);
+            }
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kRedThreads)
 gemv_t_partial(const double *__restrict__ V, int64_t ld, int k, const double *__restrict__ w, int64_t n,
                double *__restrict__ partial) {
-    static_assert(kRedThreads == 256 && kGtCols * 32 == kRedThreads, "tile reduction layout");
+    static_assert(kRedThreads == 256 && kGtCols * 16 == kRedThreads, "tile reduction layout");
     __shared__ double sh[kGtCols][kRedThreads];
     const int tid = threadIdx.x;
-    const int gc = tid >> 5, gl = tid & 31;    // reduction: 32 threads per column of the tile
-    const int64_t chunk_rows = (int64_t)kGtRows * kRedThreads;
-    const int64_t nchunks = (n + chunk_rows - 1) / chunk_rows;
-    bool first = true;
-    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const int64_t base = ch * chunk_rows + tid;
-        double wr[kGtRows];
+    const int64_t base = (int64_t)blockIdx.x * kGtChunk + tid;
+    const int j0 = (int)blockIdx.y * kGtCols;
+    double acc[kGtCols];
+    if ((int64_t)blockIdx.x * kGtChunk + kGtChunk <= n && j0 + kGtCols <= k)
+        gemv_t_tile<false>(V, ld, j0, k, w, n, base, acc);
+    else
+        gemv_t_tile<true>(V, ld, j0, k, w, n, base, acc);
 #pragma unroll
-        for (int q = 0; q < kGtRows; ++q) {
-            const int64_t i = base + (int64_t)q * kRedThreads;
-            wr[q] = i < n ? w[i] : 0.0;
-        }
-        for (int j0 = 0; j0 < k; j0 += kGtCols) {
-            double acc[kGtCols];
+    for (int c = 0; c < kGtCols; ++c) sh[c][tid] = acc[c];
+    __syncthreads();
+    // column gc = tid / 16 of the tile: 16 threads sum its 256 partials
+    const int gc = tid >> 4, gl = tid & 15;
+    double v = 0.0;
 #pragma unroll
-            for (int c = 0; c < kGtCols; ++c) {
-                acc[c] = 0.0;
-                if (j0 + c < k) {
-                    const double *col = V + (size_t)(j0 + c) * ld;
+    for (int m = 0; m < kRedThreads / 16; ++m) v += sh[gc][gl + 16 * m];
 #pragma unroll
-                    for (int q = 0; q < kGtRows; ++q) {
-                        const int64_t i = base + (int64_t)q * kRedThreads;
-                        if (i < n) acc[c] = fma(col[i], wr[q], acc[c]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < kGtCols; ++c) sh[c][tid] = acc[c];
-            __syncthreads();
-            double v = 0.0;
-#pragma unroll
-            for (int m = 0; m < kRedThreads / 32; ++m) v += sh[gc][gl + 32 * m];
-#pragma unroll
-            for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 32);
-            if (gl == 0 && j0 + gc < k) {
-                double *dst = partial + (size_t)blockIdx.x * k + j0 + gc;
-                *dst = first ? v : *dst + v;
-            }
-            __syncthreads();
-        }
-        first = false;
-    }
+    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 16);
+    if (gl == 0 && j0 + gc < k) partial[(size_t)blockIdx.x * k + j0 + gc] = v;
 }
 
 // h[j] = sum_b partial[b * k + j]   (one block per j)
@@ -285,7 +285,9 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
     HIP_TRY(s, s->lz_basis.ensure(basis_bytes));
     HIP_TRY(s, s->lz_w.ensure((size_t)ld * sizeof(double)));
     HIP_TRY(s, s->lz_scal.ensure(sizeof(double) * (ST_SIZE + 8 * (size_t)(kMaxK + 1))));
-    HIP_TRY(s, s->lz_red.ensure(sizeof(double) * (size_t)kGemvBlocks * (kMaxK + 1)));
+    // partial sums: the Gram-Schmidt projection keeps one per (row chunk, column)
+    const size_t red_rows = std::max<size_t>(kRedBlocks, (size_t)((n + kGtChunk - 1) / kGtChunk));
+    HIP_TRY(s, s->lz_red.ensure(sizeof(double) * red_rows * (kMaxK + 1)));
     HIP_TRY(s, s->lz_q.ensure(sizeof(double) * 2 * (size_t)kmax * kmax));
     // monitor scratch: per workgroup, one vector of kMonNodes systems
     const int64_t mon_stride = (int64_t)kmax * kMonNodes;
@@ -346,7 +348,7 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
     const char *check_env = std::getenv("RPY_LANCZOS_CHECK");
     const bool check_every = check_env && std::string(check_env) == "every";
     const int g = grid_for(n);
-    const int gt_blocks = (int)std::min<int64_t>(kGemvBlocks, (n + kGtRows * kRedThreads - 1) / (kGtRows * kRedThreads));
+    const int gt_blocks = (int)((n + kGtChunk - 1) / kGtChunk);
     int k = 0, kf = 0;
     double incr = INFINITY;
     const double *s_final = L.s;   // exact s_k unless the estimate decided
@@ -375,7 +377,8 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
         hipEvent_t cgs0 = timing_begin(s, RPY_KERNEL_LANCZOS_CGS, 2.0 * (2.0 * k + 3.0) * (double)n * 8.0);
         if (cgs0) HIP_TRY(s, hipEventRecord(cgs0, st));
         for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(gemv_t_partial, dim3(gt_blocks), dim3(kRedThreads), 0, st, L.V, ld, k, L.w, n, L.red);
+            hipLaunchKernelGGL(gemv_t_partial, dim3(gt_blocks, (k + kGtCols - 1) / kGtCols), dim3(kRedThreads), 0, st,
+                               L.V, ld, k, L.w, n, L.red);
             hipLaunchKernelGGL(gemv_t_final, dim3(k), dim3(kRedThreads), 0, st, L.red, gt_blocks, k, L.h);
             hipLaunchKernelGGL(gemv_n_sub, dim3(g), dim3(256), 0, st, L.V, ld, k, L.h, L.w, n);
         }
