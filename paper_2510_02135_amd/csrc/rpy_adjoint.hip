@@ -104,13 +104,15 @@ __device__ __forceinline__ void adj_interact(const Tgt<Real, ANG> &k, const vec4
     acc[4] = fma(A, sg.y, fma(b4, dy, acc[4]));
     acc[5] = fma(A, sg.z, fma(b4, dz, acc[5]));
     if constexpr (ANG) {
-        // cross products with d
-        const Real tjx = st.y * dz - st.z * dy, tjy = st.z * dx - st.x * dz, tjz = st.x * dy - st.y * dx;   // Tj x d
-        const Real fjx = sf.y * dz - sf.z * dy, fjy = sf.z * dx - sf.x * dz, fjz = sf.x * dy - sf.y * dx;   // Fj x d
-        const Real tkx = k.ty * dz - k.tz * dy, tky = k.tz * dx - k.tx * dz, tkz = k.tx * dy - k.ty * dx;   // Tk x d
-        const Real fkx = k.fy * dz - k.fz * dy, fky = k.fz * dx - k.fx * dz, fkz = k.fx * dy - k.fy * dx;   // Fk x d
-        const Real gsum = dot3(k.gx, k.gy, k.gz, tjx, tjy, tjz) + dot3(k.hx, k.hy, k.hz, fjx, fjy, fjz) -
-                          dot3(sg.x, sg.y, sg.z, tkx, tky, tkz) - dot3(sh.x, sh.y, sh.z, fkx, fky, fkz);
+        // C = gUk x Tj + gWk x Fj - gUj x Tk - gWj x Fk, one fused chain per component
+        const Real cx = fma(k.gy, st.z, fma(-k.gz, st.y, fma(k.hy, sf.z, fma(-k.hz, sf.y,
+                        fma(-sg.y, k.tz, fma(sg.z, k.ty, fma(-sh.y, k.fz, sh.z * k.fy)))))));
+        const Real cy = fma(k.gz, st.x, fma(-k.gx, st.z, fma(k.hz, sf.x, fma(-k.hx, sf.z,
+                        fma(-sg.z, k.tx, fma(sg.x, k.tz, fma(-sh.z, k.fx, sh.x * k.fz)))))));
+        const Real cz = fma(k.gx, st.y, fma(-k.gy, st.x, fma(k.hx, sf.y, fma(-k.hy, sf.x,
+                        fma(-sg.x, k.ty, fma(sg.y, k.tx, fma(-sh.x, k.fy, sh.y * k.fx)))))));
+        // gUk.(Tj x d) + gWk.(Fj x d) - gUj.(Tk x d) - gWj.(Fk x d) = d.C (cyclic triple products)
+        const Real gsum = dot3(dx, dy, dz, cx, cy, cz);
         const Real dTj = dot3(dx, dy, dz, st.x, st.y, st.z);
         const Real dhj = dot3(dx, dy, dz, sh.x, sh.y, sh.z);
         const Real dTk = dot3(dx, dy, dz, k.tx, k.ty, k.tz);
@@ -118,13 +120,7 @@ __device__ __forceinline__ void adj_interact(const Tgt<Real, ANG> &k, const vec4
         const Real hkTj = dot3(k.hx, k.hy, k.hz, st.x, st.y, st.z);
         const Real hjTk = dot3(sh.x, sh.y, sh.z, k.tx, k.ty, k.tz);
         S = fma(Gr, gsum, fma(Dr, hkTj + hjTk, fma(Er, fma(dhk, dTj, dhj * dTk), S)));
-        // G [gUk x Tj + gWk x Fj - gUj x Tk - gWj x Fk]
-        const Real cx = (k.gy * st.z - k.gz * st.y) + (k.hy * sf.z - k.hz * sf.y) - (sg.y * k.tz - sg.z * k.ty) -
-                        (sh.y * k.fz - sh.z * k.fy);
-        const Real cy = (k.gz * st.x - k.gx * st.z) + (k.hz * sf.x - k.hx * sf.z) - (sg.z * k.tx - sg.x * k.tz) -
-                        (sh.z * k.fx - sh.x * k.fz);
-        const Real cz = (k.gx * st.y - k.gy * st.x) + (k.hx * sf.y - k.hy * sf.x) - (sg.x * k.ty - sg.y * k.tx) -
-                        (sh.x * k.fy - sh.y * k.fx);
+        // G C
         const Real e1 = E * dTj, e2 = E * dhk, e3 = E * dTk, e4 = E * dhj;
         ox = fma(Gg, cx, fma(e1, k.hx, fma(e2, st.x, fma(e3, sh.x, fma(e4, k.tx, ox)))));
         oy = fma(Gg, cy, fma(e1, k.hy, fma(e2, st.y, fma(e3, sh.y, fma(e4, k.ty, oy)))));

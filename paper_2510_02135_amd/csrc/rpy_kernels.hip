@@ -80,6 +80,7 @@ pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__restrict
     __shared__ R4 sp[kTile];
     __shared__ R4 sf[kTile];
     __shared__ R4 st[ANG ? kTile : 1];
+    __shared__ R4 sh[ANG ? kTile : 1];
 
     const int tid = threadIdx.x;
     const int tbase = blockIdx.x * (kBlock * TM);
@@ -110,9 +111,23 @@ pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__restrict
     for (int t0 = s_begin; t0 < s_end; t0 += kTile) {
         const int j = t0 + tid;
         if (j < s_end) {
-            sp[tid] = pos[j];
-            sf[tid] = frc[j];
-            if constexpr (ANG) st[tid] = trq[j];
+            R4 p = pos[j], f = frc[j];
+            if constexpr (ANG) {
+                // per-source vectors of the regrouped angular pair (interact_ang)
+                R4 t = trq[j];
+                p.w = c.two_a2_3 * f.x;
+                f.w = c.two_a2_3 * f.y;
+                t.w = c.two_a2_3 * f.z;
+                R4 h;
+                h.x = Real(-0.5) * t.x;
+                h.y = Real(-0.5) * t.y;
+                h.z = Real(-0.5) * t.z;
+                h.w = Real(0);
+                st[tid] = t;
+                sh[tid] = h;
+            }
+            sp[tid] = p;
+            sf[tid] = f;
         }
         __syncthreads();
         const int cnt = min(kTile, s_end - t0);
@@ -120,11 +135,17 @@ pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__restrict
         for (int q = 0; q < cnt; ++q) {
             const R4 a = sp[q];
             const R4 b = sf[q];
-            R4 d = zero4;
-            if constexpr (ANG) d = st[q];
+            if constexpr (ANG) {
+                const R4 d = st[q];
+                const R4 e = sh[q];
 #pragma unroll
-            for (int m = 0; m < TM; ++m)
-                interact<Real, ANG>(xi[m], yi[m], zi[m], a, b, d, c, acc[m], acc[m] + 3);
+                for (int m = 0; m < TM; ++m)
+                    interact_ang<Real>(xi[m], yi[m], zi[m], a, b, d, e, c, acc[m], acc[m] + 3);
+            } else {
+#pragma unroll
+                for (int m = 0; m < TM; ++m)
+                    interact<Real, false>(xi[m], yi[m], zi[m], a, b, zero4, c, acc[m], nullptr);
+            }
         }
         __syncthreads();
         if constexpr (COMP) {
