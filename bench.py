@@ -69,17 +69,16 @@ def emax(got, ref):
 
 
 def hbm_traffic(kernel: str, n: int, tile):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE passes scaled by a plain copy), or None when
-    the summary is missing, was taken at another N, or the kernel sources
-    have changed since."""
+    """HBM bytes per launch of `kernel` at tile configuration `tile` from the
+    committed counter summary (FETCH_SIZE and WRITE_SIZE passes scaled by a
+    plain copy), or None when the summary has no entry for that kernel, N
+    and tile, or the kernel sources have changed since the counters were
+    taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "pair_kernel_f32_angular_n65536_hbm.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
-        return None
-    if d.get("kernel") != kernel or d.get("n") != n or list(d.get("tile", [])) != list(tile):
         return None
     h = hashlib.sha256()
     for f in d.get("kernel_sources", []):
@@ -89,7 +88,10 @@ def hbm_traffic(kernel: str, n: int, tile):
             return None
     if h.hexdigest() != d.get("kernel_source_sha256"):
         return None
-    return d.get("traffic_bytes_per_dispatch")
+    for e in d.get("entries", []):
+        if e.get("kernel") == kernel and e.get("n") == n and list(e.get("tile", [])) == list(tile):
+            return e.get("traffic_bytes_per_dispatch")
+    return None
 
 
 def bench_batched(rpy, workloads, dev, stream, timed):

@@ -4,11 +4,15 @@
 // (targets per lane in {1, 2, 4}) x (source splits around the default
 // choice) with HIP events on the caller's stream, for translational-only
 // products and, with include_angular, for angular ones: a screen of single
-// products, then the three fastest in interleaved rounds of back-to-back
-// bursts, whose median decides (single products run at boost clocks; the
-// sustained rate under load is what the solver sees).
-// The forces used for timing are zeros: the pair kernel's work does not
-// depend on the values (only on positions, through the overlap branch).
+// products, then the fastest split of each targets-per-lane value in
+// interleaved rounds of back-to-back bursts of about 100 ms, whose median
+// decides (single products and short
+// bursts run at boost clocks; the sustained rate under load is what the
+// solver sees).
+// The forces and torques used for timing are a fixed pseudo-random pattern
+// in [-1, 1): the pair kernel's instruction count does not depend on the
+// values, but its power draw, and so the clock it holds, does (zeros run
+// about 20 % faster than data like a real product's).
 // Choices can be cached in a text file, one line per
 // (arch, dtype, mode, log2 N bucket).
 #include "rpy_internal.hpp"
@@ -17,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <fstream>
 #include <map>
 #include <sstream>
@@ -26,6 +31,35 @@
 using namespace rpy;
 
 namespace {
+
+// v[i] = (h(i, 0), h(i, 1), h(i, 2), 0) with h a 32-bit integer hash mapped to [-1, 1)
+template <typename Real>
+__global__ void fill_pattern_kernel(vec4_t<Real> *__restrict__ v, int64_t n, unsigned salt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Real c[3];
+    for (int k = 0; k < 3; ++k) {
+        unsigned x = (unsigned)(i * 3 + k) * 2654435761u ^ salt;
+        x ^= x >> 16;
+        x *= 0x7feb352du;
+        x ^= x >> 15;
+        x *= 0x846ca68bu;
+        x ^= x >> 16;
+        c[k] = Real((double)x * (2.0 / 4294967296.0) - 1.0);
+    }
+    vec4_t<Real> o;
+    o.x = c[0];
+    o.y = c[1];
+    o.z = c[2];
+    o.w = Real(0);
+    v[i] = o;
+}
+
+template <typename Real>
+hipError_t fill_pattern(vec4_t<Real> *v, int64_t n, unsigned salt, hipStream_t st) {
+    hipLaunchKernelGGL((fill_pattern_kernel<Real>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, v, n, salt);
+    return hipGetLastError();
+}
 
 struct Entry {
     int tm = 2, split = 0;
@@ -166,19 +200,28 @@ rpy_status tune_mode(rpy_solver *s, bool ang, hipStream_t st, Entry *best) {
         }
         if (r != RPY_OK) break;
     }
-    // stage 2: the three fastest, re-timed in interleaved rounds of bursts of
-    // back-to-back products (so clock and thermal drift affect them alike and
-    // the sustained rate decides); the median round time picks the winner
+    // stage 2: the fastest screened split of each targets-per-lane value,
+    // re-timed in interleaved rounds of bursts of back-to-back products (so
+    // clock and thermal drift affect them alike and the sustained rate
+    // decides); the median round time picks the winner
     best->ms = 1e300;
     if (r == RPY_OK) {
         std::sort(screened.begin(), screened.end(),
                   [](const std::pair<double, TileConfig> &x, const std::pair<double, TileConfig> &y) {
                       return x.first < y.first;
                   });
-        const size_t nfin = std::min<size_t>(3, screened.size());
+        std::vector<std::pair<double, TileConfig>> fin;
+        for (const auto &e : screened) {
+            bool seen = false;
+            for (const auto &f : fin) seen = seen || f.second.tm == e.second.tm;
+            if (!seen) fin.push_back(e);
+        }
+        screened.swap(fin);
+        const size_t nfin = screened.size();
         const int rounds = 5;
-        // bursts of about 25 ms (2 to 32 products)
-        const int burst = std::max(2, (int)std::min(32.0, 25.0 / std::max(screened[0].first, 1e-3)));
+        // bursts of about 100 ms (2 to 64 products): long enough for the
+        // clock to settle where it sits under sustained load
+        const int burst = std::max(2, (int)std::min(64.0, 100.0 / std::max(screened[0].first, 1e-3)));
         std::vector<std::vector<double>> t(nfin);
         for (int q = 0; q < rounds && r == RPY_OK; ++q)
             for (size_t i = 0; i < nfin && r == RPY_OK; ++i) {
@@ -186,9 +229,14 @@ rpy_status tune_mode(rpy_solver *s, bool ang, hipStream_t st, Entry *best) {
                 r = time_burst<Real>(s, ang, screened[i].second, burst, st, a, b, out.as<Real>(), &ms);
                 t[i].push_back(ms);
             }
+        const char *verbose = std::getenv("RPY_AUTOTUNE_VERBOSE");
         for (size_t i = 0; i < nfin && r == RPY_OK; ++i) {
             std::sort(t[i].begin(), t[i].end());
             const double med = t[i][t[i].size() / 2];
+            if (verbose && verbose[0] == '1')
+                std::fprintf(stderr, "rpy_autotune: %s N=%lld tm=%d splits=%d screen %.4f ms sustained %.4f ms\n",
+                             ang ? "angular" : "linear", (long long)n, screened[i].second.tm,
+                             screened[i].second.n_split, screened[i].first, med);
             if (med < best->ms) {
                 best->ms = med;
                 best->tm = screened[i].second.tm;
@@ -244,11 +292,11 @@ rpy_status rpy_autotune(rpy_solver *s, const char *cache_path, void *hip_stream)
         r = ensure_vec_buffers(s, true);
         if (r != RPY_OK) return r;
         if (s->dtype == RPY_F64) {
-            HIP_TRY(s, (launch_stage_vec<double, double>(nullptr, s->n, s->f.as<double4>(), st)));
-            HIP_TRY(s, (launch_stage_vec<double, double>(nullptr, s->n, s->t.as<double4>(), st)));
+            HIP_TRY(s, fill_pattern<double>(s->f.as<double4>(), s->n, 0x9e3779b9u, st));
+            HIP_TRY(s, fill_pattern<double>(s->t.as<double4>(), s->n, 0x85ebca6bu, st));
         } else {
-            HIP_TRY(s, (launch_stage_vec<float, float>(nullptr, s->n, s->f.as<float4>(), st)));
-            HIP_TRY(s, (launch_stage_vec<float, float>(nullptr, s->n, s->t.as<float4>(), st)));
+            HIP_TRY(s, fill_pattern<float>(s->f.as<float4>(), s->n, 0x9e3779b9u, st));
+            HIP_TRY(s, fill_pattern<float>(s->t.as<float4>(), s->n, 0x85ebca6bu, st));
         }
         Entry best;
         r = s->dtype == RPY_F64 ? tune_mode<double>(s, ang, st, &best) : tune_mode<float>(s, ang, st, &best);
