@@ -109,8 +109,9 @@ def bench_batched(rpy, workloads, dev, stream, timed):
     W = torch.tensor(np.concatenate([s.w for s in syss]), dtype=f32, device=dev)
     b = rpy.Batch(off, workloads.VISCOSITY, workloads.RADIUS, f32)
     b.setPositions(X)
+    batch_tiles = b.autotune()
     b.Mdot(F)
-    t_mdot = timed(lambda: b.Mdot(F), 5, stream)
+    t_mdot = timed(lambda: b.Mdot(F), 10, stream, warmup=3)
     b.sqrtMdotW(W, tol=1e-6)
     t0 = time.perf_counter()
     b.sqrtMdotW(W, tol=1e-6)
@@ -144,6 +145,7 @@ def bench_batched(rpy, workloads, dev, stream, timed):
     b.close()
     pairs = float((ns.astype(np.float64) ** 2).sum())
     return {"systems": len(syss), "total_particles": int(off[-1]), "sum_n2": pairs,
+            "tile_config": {"targets_per_lane": batch_tiles[0], "workgroups_per_cu": batch_tiles[1]},
             "mdot_ms": round(t_mdot, 4), "mdot_pairs_per_s": pairs / (t_mdot * 1e-3),
             "mdot_per_system_launches_ms": round(t_mdot_ps, 3),
             "sqrt_ms": round(t_sqrt, 3), "sqrt_per_system_launches_ms": round(t_sqrt_ps, 3),

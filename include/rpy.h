@@ -268,6 +268,26 @@ rpy_status rpy_batch_mdot(rpy_batch *b, const void *forces, void *lin_out, void 
 rpy_status rpy_batch_sqrt_mdot_w(rpy_batch *b, const void *w, double prefactor, double tol, int max_iter,
                                  int check_every, void *lin_out, int *iters_out, void *hip_stream);
 
+/*
+ * Configuration of the batched pair kernel: targets_per_lane in {1, 2}
+ * (each task covers 64 x targets_per_lane targets of one system) and
+ * workgroups_per_cu in [1, 32] (size of the persistent grid).  Defaults 1
+ * and 8.  Setting it rebuilds the task list (synchronous host-to-device
+ * copy).  RPY_ERR_INVALID_ARG outside those ranges.
+ */
+rpy_status rpy_batch_set_tile_config(rpy_batch *b, int targets_per_lane, int workgroups_per_cu);
+rpy_status rpy_batch_get_tile_config(const rpy_batch *b, int *targets_per_lane, int *workgroups_per_cu);
+
+/*
+ * Autotuner of the batched pair kernel for the current systems and
+ * positions: times every (targets per lane, workgroups per CU) in
+ * {1, 2} x {4, 8, 16} on a fixed pseudo-random force vector, screens them
+ * with single products, re-times the best of each tile width in interleaved
+ * rounds of ~100 ms bursts, and keeps the fastest.  Synchronises
+ * hip_stream.  RPY_ERR_NO_POSITIONS before rpy_batch_set_positions.
+ */
+rpy_status rpy_batch_autotune(rpy_batch *b, void *hip_stream);
+
 /* Message describing the last failure of `b`; owned by `b`. */
 const char *rpy_batch_last_error(const rpy_batch *b);
 

@@ -86,6 +86,9 @@ def load() -> ctypes.CDLL:
         "rpy_batch_mdot": ([vp, vp, vp, vp], i),
         "rpy_batch_sqrt_mdot_w": ([vp, vp, d, d, i, i, vp, ctypes.POINTER(i), vp], i),
         "rpy_batch_last_error": ([vp], ctypes.c_char_p),
+        "rpy_batch_set_tile_config": ([vp, i, i], i),
+        "rpy_batch_get_tile_config": ([vp, ctypes.POINTER(i), ctypes.POINTER(i)], i),
+        "rpy_batch_autotune": ([vp, vp], i),
         "rpy_batch_destroy": ([vp], None),
         "rpy_set_tile_config": ([vp, i, i, i], i),
         "rpy_get_tile_config": ([vp, i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
@@ -225,6 +228,20 @@ def rpy_mdot_backward(h, forces, torques, grad_lin, grad_ang, grad_pos, grad_for
         _ptr(grad_lin, dtype, 3 * n, "grad_lin"), _ptr(grad_ang, dtype, 3 * n, "grad_ang"),
         _ptr(grad_pos, dtype, 3 * n, "grad_pos"), _ptr(grad_forces, dtype, 3 * n, "grad_forces"),
         _ptr(grad_torques, dtype, 3 * n, "grad_torques"), _stream(ref)))
+
+
+def rpy_batch_set_tile_config(h, targets_per_lane: int, workgroups_per_cu: int):
+    _bcheck(h, load().rpy_batch_set_tile_config(h, int(targets_per_lane), int(workgroups_per_cu)))
+
+
+def rpy_batch_get_tile_config(h):
+    tm, wg = ctypes.c_int(0), ctypes.c_int(0)
+    _bcheck(h, load().rpy_batch_get_tile_config(h, ctypes.byref(tm), ctypes.byref(wg)))
+    return tm.value, wg.value
+
+
+def rpy_batch_autotune(h):
+    _bcheck(h, load().rpy_batch_autotune(h, _stream()))
 
 
 def _bcheck(h, status: int):

@@ -53,7 +53,9 @@ enum { BS_BETA0 = 0, BS_INCR, BS_NSPD, BS_TSCALE, BS_BREAK, BS_DONE, BS_CODE, BS
 // ---------------------------------------------------------------------------
 // persistent batched pair kernel
 // ---------------------------------------------------------------------------
-template <typename Real, typename Tout>
+// A task is (system, tile of 64 TM targets); lane l of the wave owns targets
+// tile * 64 TM + m * 64 + l, m < TM.
+template <typename Real, typename Tout, int TM>
 __global__ void __launch_bounds__(kBatchBlock)
 batch_pair_kernel(const vec4_t<Real> *__restrict__ rec, const int64_t *__restrict__ off,
                   const int2 *__restrict__ tasks, int ntasks, unsigned *__restrict__ counter,
@@ -73,12 +75,16 @@ batch_pair_kernel(const vec4_t<Real> *__restrict__ rec, const int64_t *__restric
         if (active && active[s] == 0) continue;
         const int64_t o = off[s];
         const int ns = (int)(off[s + 1] - o);
-        const int i = task.y * 64 + lane;
         const R4 *src = rec + 2 * o;
-        const R4 p = src[2 * min(i, ns - 1)];
+        R4 p[TM];
+#pragma unroll
+        for (int m = 0; m < TM; ++m) p[m] = src[2 * min(task.y * 64 * TM + m * 64 + lane, ns - 1)];
         const PairConst<Real> c = pcs[s];
-        Real acc[3] = {Real(0), Real(0), Real(0)};
-        Real sum[3] = {Real(0), Real(0), Real(0)}, cmp[3] = {Real(0), Real(0), Real(0)};
+        Real acc[TM][3], sum[TM][3], cmp[TM][3];
+#pragma unroll
+        for (int m = 0; m < TM; ++m)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) acc[m][d] = sum[m][d] = cmp[m][d] = Real(0);
         // the next source record is loaded before the current one is used
         R4 sp = src[0], sf = src[1];
         for (int j0 = 0; j0 < ns; j0 += kSrcChunk) {
@@ -88,24 +94,31 @@ batch_pair_kernel(const vec4_t<Real> *__restrict__ rec, const int64_t *__restric
                 const int jn = min(j0 + q + 1, ns - 1);
                 const R4 np = src[2 * jn];
                 const R4 nf = src[2 * jn + 1];
-                interact<Real, false>(p.x, p.y, p.z, sp, sf, zero4, c, acc, nullptr);
+#pragma unroll
+                for (int m = 0; m < TM; ++m) interact<Real, false>(p[m].x, p[m].y, p[m].z, sp, sf, zero4, c, acc[m], nullptr);
                 sp = np;
                 sf = nf;
             }
             if constexpr (COMP) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    neumaier(sum[d], cmp[d], acc[d]);
-                    acc[d] = Real(0);
-                }
+                for (int m = 0; m < TM; ++m)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        neumaier(sum[m][d], cmp[m][d], acc[m][d]);
+                        acc[m][d] = Real(0);
+                    }
             }
         }
-        if (i < ns) {
-            const double kk = kfac[s];
+        const double kk = kfac[s];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const double v = COMP ? ((double)sum[d] + (double)cmp[d]) : (double)acc[d];
-                out[3 * (o + i) + d] = (Tout)(kk * v);
+        for (int m = 0; m < TM; ++m) {
+            const int i = task.y * 64 * TM + m * 64 + lane;
+            if (i < ns) {
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double v = COMP ? ((double)sum[m][d] + (double)cmp[m][d]) : (double)acc[m][d];
+                    out[3 * (o + i) + d] = (Tout)(kk * v);
+                }
             }
         }
     }
@@ -555,6 +568,10 @@ struct rpy_batch {
     bool have_pos = false;
     int ntasks = 0, nblk = 0;
     int max_sys_n = 0;
+    // pair-kernel configuration: targets per lane (tasks of 64 tm targets)
+    // and persistent workgroups per CU; systems longest first
+    int tm = 1, wg_per_cu = 8;
+    std::vector<int> order;
     DevBuf d_off, d_kfac, d_pc, d_tasks, d_counter, d_rec, d_flag;
     DevBuf d_blk_sys, d_blk_lo, d_blk_hi, d_sys_b0, d_sys_b1, d_kmax;
     DevBuf V, w, lanc, red, Q, status, ints, pref, mon;
@@ -585,9 +602,37 @@ SegMap seg_map(const rpy_batch *b) {
     return SegMap{b->d_blk_sys.as<int>(), b->d_blk_lo.as<int64_t>(), b->d_blk_hi.as<int64_t>()};
 }
 
-unsigned persistent_blocks(int ntasks) {
-    const int waves = std::max(1, ntasks);
-    return (unsigned)std::min((waves + 3) / 4, 256 * 8);
+// persistent grid: one wave per task at most, wg_per_cu workgroups per CU
+unsigned persistent_blocks(const rpy_batch *b) {
+    const int waves = std::max(1, b->ntasks);
+    return (unsigned)std::min((waves + 3) / 4, 256 * b->wg_per_cu);
+}
+
+// task list (system, tile of 64 tm targets) in b->order, uploaded to d_tasks
+hipError_t build_tasks(rpy_batch *b) {
+    std::vector<int2> tasks;
+    const int tile = 64 * b->tm;
+    for (int s : b->order) {
+        const int64_t ns = b->off[s + 1] - b->off[s];
+        for (int64_t t = 0; t < (ns + tile - 1) / tile; ++t) tasks.push_back(make_int2(s, (int)t));
+    }
+    b->ntasks = (int)tasks.size();
+    hipError_t e = b->d_tasks.ensure(sizeof(int2) * tasks.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(b->d_tasks.p, tasks.data(), sizeof(int2) * tasks.size(), hipMemcpyHostToDevice);
+}
+
+template <typename Real, typename Tout>
+void launch_batch_pair(rpy_batch *b, const int *active, Tout *out, hipStream_t st) {
+    const dim3 grid(persistent_blocks(b)), block(kBatchBlock);
+    if (b->tm == 2)
+        hipLaunchKernelGGL((batch_pair_kernel<Real, Tout, 2>), grid, block, 0, st, b->d_rec.as<vec4_t<Real>>(),
+                           b->d_off.as<int64_t>(), b->d_tasks.as<int2>(), b->ntasks, b->d_counter.as<unsigned>(),
+                           b->d_pc.as<PairConst<Real>>(), b->d_kfac.as<double>(), active, out);
+    else
+        hipLaunchKernelGGL((batch_pair_kernel<Real, Tout, 1>), grid, block, 0, st, b->d_rec.as<vec4_t<Real>>(),
+                           b->d_off.as<int64_t>(), b->d_tasks.as<int2>(), b->ntasks, b->d_counter.as<unsigned>(),
+                           b->d_pc.as<PairConst<Real>>(), b->d_kfac.as<double>(), active, out);
 }
 
 template <typename Real>
@@ -595,10 +640,7 @@ rpy_status batch_mdot_typed(rpy_batch *b, const Real *F, Real *out, hipStream_t 
     hipLaunchKernelGGL((batch_stage_vec<Real, Real>), dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0, st, F,
                        (const int *)nullptr, (int64_t)0, b->ntot, b->d_rec.as<vec4_t<Real>>());
     BHIP(b, launch_fill_zero<unsigned>(b->d_counter.as<unsigned>(), 1, st));
-    hipLaunchKernelGGL((batch_pair_kernel<Real, Real>), dim3(persistent_blocks(b->ntasks)), dim3(kBatchBlock), 0, st,
-                       b->d_rec.as<vec4_t<Real>>(), b->d_off.as<int64_t>(), b->d_tasks.as<int2>(), b->ntasks,
-                       b->d_counter.as<unsigned>(), b->d_pc.as<PairConst<Real>>(), b->d_kfac.as<double>(),
-                       (const int *)nullptr, out);
+    launch_batch_pair<Real, Real>(b, nullptr, out, st);
     BHIP(b, hipGetLastError());
     return RPY_OK;
 }
@@ -622,9 +664,7 @@ void enqueue_iteration(rpy_batch *b, int kcap, double tol, int every, Real *out,
     hipLaunchKernelGGL((batch_stage_vec<double, Real>), dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0, st, V,
                        kdev, ld, b->ntot, b->d_rec.as<vec4_t<Real>>());
     hipLaunchKernelGGL(clear_ints, dim3(1), dim3(64), 0, st, (int *)b->d_counter.p, 1);
-    hipLaunchKernelGGL((batch_pair_kernel<Real, double>), dim3(persistent_blocks(b->ntasks)), dim3(kBatchBlock), 0, st,
-                       b->d_rec.as<vec4_t<Real>>(), b->d_off.as<int64_t>(), b->d_tasks.as<int2>(), b->ntasks,
-                       b->d_counter.as<unsigned>(), b->d_pc.as<PairConst<Real>>(), b->d_kfac.as<double>(), active, w);
+    launch_batch_pair<Real, double>(b, active, w, st);
     // recurrence
     hipLaunchKernelGGL(seg_recur_dot, gb, tb, 0, st, w, V, ld, beta, L, m, active, kdev, red);
     hipLaunchKernelGGL(seg_sys_reduce, gs, dim3(256), 0, st, red, b->d_sys_b0.as<int>(), b->d_sys_b1.as<int>(),
@@ -765,6 +805,117 @@ rpy_status batch_sqrt_typed(rpy_batch *b, const Real *w_in, double prefactor, do
     return RPY_OK;
 }
 
+// out[i] = a fixed pseudo-random value in [-1, 1) (timing data for the tuner)
+template <typename Real>
+__global__ void batch_fill_pattern(Real *__restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned x = (unsigned)i * 2654435761u ^ 0x9e3779b9u;
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    out[i] = Real((double)x * (2.0 / 4294967296.0) - 1.0);
+}
+
+// milliseconds per batched product over `burst` back-to-back products
+template <typename Real>
+rpy_status batch_time(rpy_batch *b, const Real *F, Real *out, int burst, hipStream_t st, hipEvent_t e0,
+                      hipEvent_t e1, double *ms) {
+    BHIP(b, hipEventRecord(e0, st));
+    for (int r = 0; r < burst; ++r) {
+        rpy_status q = batch_mdot_typed<Real>(b, F, out, st);
+        if (q != RPY_OK) return q;
+    }
+    BHIP(b, hipEventRecord(e1, st));
+    BHIP(b, hipEventSynchronize(e1));
+    float f = 0.f;
+    BHIP(b, hipEventElapsedTime(&f, e0, e1));
+    *ms = f / burst;
+    return RPY_OK;
+}
+
+// Screen every (targets per lane, workgroups per CU) with single products,
+// then re-time the best of each tile width in interleaved rounds of ~100 ms
+// bursts and keep the fastest (as the single-system tuner does).
+template <typename Real>
+rpy_status batch_tune(rpy_batch *b, hipStream_t st) {
+    DevBuf data;
+    const int64_t n3 = 3 * b->ntot;
+    BHIP(b, data.ensure(2 * sizeof(Real) * (size_t)n3));
+    Real *F = data.as<Real>(), *out = F + n3;
+    hipLaunchKernelGGL((batch_fill_pattern<Real>), dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, F, n3);
+    BHIP(b, hipGetLastError());
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BHIP(b, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return bfail(b, RPY_ERR_HIP, "hipEventCreate failed");
+    }
+    struct Cand {
+        int tm, wg;
+        double ms;
+    };
+    std::vector<Cand> screen;
+    rpy_status r = RPY_OK;
+    for (int tm : {1, 2})
+        for (int wg : {4, 8, 16}) {
+            if (r != RPY_OK) break;
+            b->tm = tm;
+            b->wg_per_cu = wg;
+            if (build_tasks(b) != hipSuccess) {
+                r = bfail(b, RPY_ERR_HIP, "task list upload failed");
+                break;
+            }
+            std::vector<double> t;
+            for (int q = 0; q < 4 && r == RPY_OK; ++q) {
+                double ms = 0.0;
+                r = batch_time<Real>(b, F, out, 1, st, e0, e1, &ms);
+                if (q > 0) t.push_back(ms);   // the first product is a warm-up
+            }
+            if (r == RPY_OK) {
+                std::sort(t.begin(), t.end());
+                screen.push_back({tm, wg, t[t.size() / 2]});
+            }
+        }
+    Cand best{1, 8, 1e300};
+    if (r == RPY_OK) {
+        std::vector<Cand> fin;
+        for (int tm : {1, 2}) {
+            Cand c{tm, 8, 1e300};
+            for (const Cand &x : screen)
+                if (x.tm == tm && x.ms < c.ms) c = x;
+            fin.push_back(c);
+        }
+        const int burst = std::max(2, (int)std::min(64.0, 100.0 / std::max(fin[0].ms, 1e-3)));
+        std::vector<std::vector<double>> t(fin.size());
+        for (int round = 0; round < 5 && r == RPY_OK; ++round)
+            for (size_t i = 0; i < fin.size() && r == RPY_OK; ++i) {
+                b->tm = fin[i].tm;
+                b->wg_per_cu = fin[i].wg;
+                if (build_tasks(b) != hipSuccess) {
+                    r = bfail(b, RPY_ERR_HIP, "task list upload failed");
+                    break;
+                }
+                double ms = 0.0;
+                r = batch_time<Real>(b, F, out, burst, st, e0, e1, &ms);
+                t[i].push_back(ms);
+            }
+        for (size_t i = 0; i < fin.size() && r == RPY_OK; ++i) {
+            std::sort(t[i].begin(), t[i].end());
+            const double med = t[i][t[i].size() / 2];
+            if (med < best.ms) best = {fin[i].tm, fin[i].wg, med};
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->tm = best.tm;
+    b->wg_per_cu = best.wg;
+    if (build_tasks(b) != hipSuccess && r == RPY_OK) r = bfail(b, RPY_ERR_HIP, "task list upload failed");
+    return r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -791,19 +942,13 @@ rpy_status rpy_batch_create(int32_t n_systems, const int64_t *offsets, const dou
     b->eta.assign(viscosity, viscosity + n_systems);
     b->radius.assign(radius, radius + n_systems);
     b->ntot = offsets[n_systems];
-    // task list: (system, 64-target tile), longest systems first
-    std::vector<int> order(n_systems);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    // systems longest first (the task list is built from this order)
+    b->order.resize(n_systems);
+    std::iota(b->order.begin(), b->order.end(), 0);
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
         return (b->off[x + 1] - b->off[x]) > (b->off[y + 1] - b->off[y]);
     });
-    std::vector<int2> tasks;
-    for (int s : order) {
-        const int64_t ns = b->off[s + 1] - b->off[s];
-        b->max_sys_n = std::max<int>(b->max_sys_n, (int)ns);
-        for (int64_t t = 0; t < (ns + 63) / 64; ++t) tasks.push_back(make_int2(s, (int)t));
-    }
-    b->ntasks = (int)tasks.size();
+    for (int s = 0; s < n_systems; ++s) b->max_sys_n = std::max<int>(b->max_sys_n, (int)(b->off[s + 1] - b->off[s]));
     // segmented blocks over the 3N-entry vectors
     std::vector<int> bsys, b0(n_systems), b1(n_systems);
     std::vector<int64_t> blo, bhi;
@@ -835,7 +980,7 @@ rpy_status rpy_batch_create(int32_t n_systems, const int64_t *offsets, const dou
     if (e == hipSuccess)
         e = dtype == RPY_F64 ? up(b->d_pc, pcd.data(), sizeof(PairConst<double>) * n_systems)
                              : up(b->d_pc, pcf.data(), sizeof(PairConst<float>) * n_systems);
-    if (e == hipSuccess) e = up(b->d_tasks, tasks.data(), sizeof(int2) * tasks.size());
+    if (e == hipSuccess) e = build_tasks(b);
     if (e == hipSuccess) e = up(b->d_blk_sys, bsys.data(), sizeof(int) * bsys.size());
     if (e == hipSuccess) e = up(b->d_blk_lo, blo.data(), sizeof(int64_t) * blo.size());
     if (e == hipSuccess) e = up(b->d_blk_hi, bhi.data(), sizeof(int64_t) * bhi.size());
@@ -906,6 +1051,32 @@ rpy_status rpy_batch_sqrt_mdot_w(rpy_batch *b, const void *w, double prefactor, 
 }
 
 const char *rpy_batch_last_error(const rpy_batch *b) { return b ? b->err.c_str() : "null batch handle"; }
+
+rpy_status rpy_batch_set_tile_config(rpy_batch *b, int targets_per_lane, int workgroups_per_cu) {
+    if (!b) return RPY_ERR_INVALID_ARG;
+    if (targets_per_lane != 1 && targets_per_lane != 2)
+        return bfail(b, RPY_ERR_INVALID_ARG, "targets per lane must be 1 or 2");
+    if (workgroups_per_cu < 1 || workgroups_per_cu > 32)
+        return bfail(b, RPY_ERR_INVALID_ARG, "workgroups per CU must be in [1, 32]");
+    b->tm = targets_per_lane;
+    b->wg_per_cu = workgroups_per_cu;
+    BHIP(b, build_tasks(b));
+    return RPY_OK;
+}
+
+rpy_status rpy_batch_get_tile_config(const rpy_batch *b, int *targets_per_lane, int *workgroups_per_cu) {
+    if (!b) return RPY_ERR_INVALID_ARG;
+    if (targets_per_lane) *targets_per_lane = b->tm;
+    if (workgroups_per_cu) *workgroups_per_cu = b->wg_per_cu;
+    return RPY_OK;
+}
+
+rpy_status rpy_batch_autotune(rpy_batch *b, void *hip_stream) {
+    if (!b) return RPY_ERR_INVALID_ARG;
+    if (!b->have_pos) return bfail(b, RPY_ERR_NO_POSITIONS, "rpy_batch_set_positions has not been called");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    return b->dtype == RPY_F64 ? batch_tune<double>(b, st) : batch_tune<float>(b, st);
+}
 
 void rpy_batch_destroy(rpy_batch *b) {
     if (!b) return;

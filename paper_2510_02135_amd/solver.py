@@ -221,6 +221,19 @@ class Batch:
         _lib.rpy_batch_mdot(self._h, forces.reshape(-1, 3).contiguous(), out, self._dtype, self.total)
         return out
 
+    def autotune(self):
+        """Time the batched pair kernel's configurations on the current
+        systems and keep the fastest; returns (targets per lane, workgroups
+        per CU)."""
+        _lib.rpy_batch_autotune(self._h)
+        return self.tileConfig()
+
+    def tileConfig(self):
+        return _lib.rpy_batch_get_tile_config(self._h)
+
+    def setTileConfig(self, targets_per_lane: int, workgroups_per_cu: int = 8):
+        _lib.rpy_batch_set_tile_config(self._h, targets_per_lane, workgroups_per_cu)
+
     def sqrtMdotW(self, W: torch.Tensor, prefactor: float = 1.0, tol: float = 1e-6, maxIter: int = 500,
                   checkEvery: int = 4):
         out = torch.empty((self.total, 3), dtype=self._dtype, device=self._device)

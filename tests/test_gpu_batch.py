@@ -57,6 +57,40 @@ def test_batched_mdot_per_system(dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
+def test_batched_mdot_every_tile_config_and_autotune(dtype):
+    """Every (targets per lane, workgroups per CU) of the batched pair kernel,
+    and the autotuner's choice, against the oracle per system; bad
+    configurations are rejected."""
+    import paper_2510_02135_amd as rpy
+    sizes = [1, 63, 64, 65, 127, 128, 129, 300, 2, 511]
+    say(f"case batch tile configs sizes={sizes} {dtype}")
+    systems = _systems(sizes, 14)
+    b, off = _batch(systems, dtype)
+    F = torch.tensor(np.concatenate([s[1] for s in systems]), dtype=dtype, device="cuda")
+    refs = [mobility.mdot_dense(rounded(x, dtype), rounded(f, dtype), None, 1.0, 1 / (6 * math.pi))[0]
+            for x, f, _ in systems]
+
+    def check(tag):
+        U = host(b.Mdot(F))
+        worst = max(emax(U[off[k]:off[k + 1]], refs[k]) for k in range(len(systems)))
+        say(f"  {tag}: worst system e_max {worst:.3e}")
+        assert worst <= tol_for(dtype)
+
+    for tm in (1, 2):
+        for wg in (1, 4, 16, 32):
+            b.setTileConfig(tm, wg)
+            assert b.tileConfig() == (tm, wg)
+            check(f"tm={tm} wg={wg}")
+    chosen = b.autotune()
+    assert chosen[0] in (1, 2) and chosen[1] in (4, 8, 16)
+    check(f"autotuned {chosen}")
+    for bad in ((0, 8), (3, 8), (1, 0), (1, 33)):
+        with pytest.raises(rpy.RpyError):
+            b.setTileConfig(*bad)
+    assert b.tileConfig() == chosen
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
 def test_batched_lanczos_matched_iterations_and_eager_replay(dtype, monkeypatch):
     """Each system stops where the oracle's Lanczos stops (float64; float32
     within one iteration, since float32 products can move an increment that
