@@ -21,8 +21,9 @@ backward/forward time ratio, the roofline position of the dominant kernel
 inside the timed steps), the HBM rate of the Lanczos vector operations (the
 Gram-Schmidt passes, timed the same way, algorithmic bytes), the max
 relative error of each result against the float64 CPU oracle on sampled
-particles, and the oracle's own rate on a bounded sample of the same
-workload on the host cores.
+particles, the oracle's own rate on a bounded sample of the same workload on
+the host cores, the 512-system batch (one persistent launch vs one launch
+per system) and one angular product of 4096 bead chains x 256 beads.
 """
 from __future__ import annotations
 
@@ -53,7 +54,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle sample")
     p.add_argument("--no-breakdown", action="store_true", help="skip the per-precision breakdown and oracle check")
-    p.add_argument("--no-batch", action="store_true", help="skip the batched-systems measurement")
+    p.add_argument("--no-batch", action="store_true",
+                   help="skip the batched-systems and bead-chain measurements")
     p.add_argument("--tile-cache", default=None,
                    help="autotune cache file (read if it has an entry, else written)")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -300,6 +302,22 @@ def main():
                             gp.double().cpu().numpy(), gf.double().cpu().numpy())
             so.close()
 
+    # ---- bead chains, N = 1,048,576: one angular float32 product ----------
+    chains = None
+    if not args.no_batch:
+        print("bench: bead chains N=1048576", file=sys.stderr, flush=True)
+        c5 = workloads.c5_chains()
+        sc = rpy.Solver()
+        sc.initialize(viscosity=c5.viscosity, hydrodynamicRadius=c5.radius, includeAngular=True)
+        sc.setPositions(dev_t(c5.pos, torch.float32))
+        Fc, Tc = dev_t(c5.forces, torch.float32), dev_t(c5.torques, torch.float32)
+        tc = timed(lambda: sc.Mdot(forces=Fc, torques=Tc), 2, stream, warmup=1)
+        chains = {"n": c5.n, "workload": "4096 random-walk chains x 256 beads, bond 2.1a, phi 0.05, seed 1005",
+                  "mdot_angular_fp32_ms": round(tc, 3), "pairs_per_s": float(c5.n) ** 2 / (tc * 1e-3),
+                  "tiles": sc.tileConfig(True)}
+        sc.close()
+        del Fc, Tc
+
     # ---- batched systems: one persistent launch vs one launch per system ----
     batched = None
     if not args.no_batch:
@@ -399,6 +417,7 @@ def main():
         "breakdown": breakdown,
         "accuracy_vs_fp64_oracle": acc,
         "batched": batched,
+        "chains": chains,
         "tiles": {"linear": tiles[0], "angular": tiles[1]},
         "adjoint_kernel_avg_ms": round(adj_ms / max(adj_launches, 1), 4),
     }

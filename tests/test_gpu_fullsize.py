@@ -11,7 +11,8 @@ that hold at any size:
 * 4096 chains x 256 beads (N = 1,048,576), float32 with torques: Mdot and
   the backward pass on sampled particles against the C oracle; Lanczos
   basis orthonormality through the norm identity after a bounded number of
-  iterations.
+  iterations, and agreement of the float32 and float64 Lanczos iterates at
+  that matched iteration count.
 """
 import math
 
@@ -122,3 +123,16 @@ def test_c5_chains_sampled_rows_and_lanczos_orthonormality():
     wmw = float(wr @ _flat(ml, ma))
     say(f"  |y_12|^2 / W^T M W = {y @ y / wmw:.9f}")
     assert abs(y @ y / wmw - 1) <= 1e-5
+    # the same 12 iterations with float64 pairs on the float32-rounded inputs:
+    # the float32 and float64 Lanczos iterates agree to the float32 bar
+    del sol, ml, ma
+    sol64 = _solver(True)
+    sol64.setPositions(torch.tensor(xr, dtype=torch.float64, device="cuda"))
+    try:
+        yl64, ya64 = sol64.sqrtMdotW(torch.tensor(wr, dtype=torch.float64, device="cuda"), tol=1e-15, maxIter=12)
+    except rpy.NotConvergedError as err:
+        yl64, ya64 = err.result
+    y64 = _flat(yl64, ya64)
+    e = float(np.abs(y - y64).max() / np.abs(y64).max())
+    say(f"  float32 vs float64 Lanczos at k = 12: max rel {e:.3e}")
+    assert e <= 1e-5
