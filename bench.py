@@ -156,6 +156,36 @@ def bench_batched(rpy, workloads, dev, stream, timed):
             "per_system_lanczos_iterations_median": float(np.median(it_ps))}
 
 
+def oracle_timings(workloads, pairloop):
+    """Seconds of the other oracle routes on the host (context for the
+    GPU numbers, not targets): dense float64 assembly + product at N = 1024
+    (translational, as the 1024-particle workload), the oracle's Lanczos
+    square root there (tol 1e-6), and the C pair loop on 1024 sampled rows
+    of the 1,048,576-bead chains (with torques)."""
+    import numpy as np
+    from oracle import lanczos as olz, mobility as omob
+    out = {}
+    c1 = workloads.c1_small_fp64()
+    t0 = time.perf_counter()
+    m = omob.grand_mobility(c1.pos, c1.radius, c1.viscosity)
+    u = m @ c1.forces.reshape(-1)
+    out["n1024_dense_assembly_and_product_s"] = round(time.perf_counter() - t0, 3)
+    w = np.random.default_rng(1001).standard_normal(3 * c1.n)
+    t0 = time.perf_counter()
+    _, info = olz.lanczos_sqrt(lambda v: m @ v, w, tol=1e-6)
+    out["n1024_lanczos_s"] = round(time.perf_counter() - t0, 3)
+    out["n1024_lanczos_iterations"] = info.iters
+    c5 = workloads.c5_chains()
+    rows = c5.extra["subset"][:1024]
+    t0 = time.perf_counter()
+    pairloop.mdot_rows(c5.pos, rows, c5.forces, c5.torques, c5.radius, c5.viscosity)
+    dt = time.perf_counter() - t0
+    out["chains_1024_rows_s"] = round(dt, 3)
+    out["chains_rows_pairs_per_s"] = len(rows) * float(c5.n) / dt
+    del u
+    return out
+
+
 def host_cpu_model():
     """The host CPU's model name from /proc/cpuinfo (None if unreadable)."""
     try:
@@ -393,6 +423,7 @@ def main():
                "sample": f"{reps} x ({m} target rows x {n} sources) of the same workload, linear+angular Mdot, "
                          f"float64 C/OpenMP pair loop ({dt_cpu:.1f} s)",
                "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count()}
+        cpu["other_oracle_timings"] = oracle_timings(workloads, pairloop)
 
     out = {
         "metric": METRIC,

@@ -85,7 +85,7 @@ def test_lanczos_stopping_iteration_against_oracle(monkeypatch, angular, tol):
         e = float(np.abs(y - y_ref).max() / np.abs(y_ref).max())
         say(f"  oracle stops at {info.iters}, {mode} schedule at {sol.last_iterations}, max rel {e:.3e}")
         assert sol.last_iterations == info.iters
-        assert e <= 1e-12
+        assert e <= (1e-7 if case == "coincident" else 1e-12)
 
 
 def test_lanczos_zero_noise_and_not_converged():
@@ -103,6 +103,48 @@ def test_lanczos_zero_noise_and_not_converged():
     bad[5] = float("nan")
     with pytest.raises(rpy.RpyError):
         sol.sqrtMdotW(bad)
+
+
+@pytest.mark.parametrize("case", ["coincident", "single", "two_far"])
+def test_lanczos_degenerate_configurations(monkeypatch, case):
+    """Configurations that leave the quadrature estimate's safe range or end
+    the Krylov space early: coincident particles (M only semi-definite, a
+    Ritz value near 0, so the estimate reports NaN and the eigensolver
+    decides), one particle (Krylov space of dimension 3: breakdown), two
+    distant particles (M nearly diagonal).  The solver stops where the
+    oracle's Lanczos stops and matches its y, with the default schedule and
+    with the exact test at every iteration.  With coincident particles the
+    bar is sqrt(eps)-sized: T_k then has a Ritz value of order eps |M|, and
+    since sqrt is not Lipschitz at 0 two correct float64 eigensolvers give
+    that term's sqrt(lambda) to about sqrt(eps) |M|^(1/2) only (1.5e-8
+    relative); the other configurations keep the float64 bar."""
+    say(f"case lanczos degenerate {case}")
+    rng = np.random.default_rng(77)
+    if case == "coincident":
+        x = (rng.random((40, 3)) - 0.5) * 6.0
+        x[7] = x[3]                          # two coincident particles
+        x[20] = x[3]                         # and a third
+    elif case == "single":
+        x = np.array([[0.3, -0.2, 0.1]])
+    else:
+        x = np.array([[0.0, 0.0, 0.0], [300.0, 10.0, -5.0]])
+    n = x.shape[0]
+    w = rng.standard_normal(3 * n)
+    m = mobility.grand_mobility(x, workloads.RADIUS, workloads.VISCOSITY)
+    y_ref, info = lanczos.lanczos_sqrt(lambda v: m @ v, w, tol=1e-6)
+    sol = _solver(False)
+    sol.setPositions(to_dev(x, torch.float64))
+    for mode in ("default", "every"):
+        if mode == "every":
+            monkeypatch.setenv("RPY_LANCZOS_CHECK", "every")
+        else:
+            monkeypatch.delenv("RPY_LANCZOS_CHECK", raising=False)
+        lin, _ = sol.sqrtMdotW(to_dev(w, torch.float64), tol=1e-6)
+        y = host(lin).reshape(-1)
+        e = float(np.abs(y - y_ref).max() / np.abs(y_ref).max())
+        say(f"  {mode}: oracle stops at {info.iters}, solver at {sol.last_iterations}, max rel {e:.3e}")
+        assert sol.last_iterations == info.iters
+        assert e <= (1e-7 if case == "coincident" else 1e-12)
 
 
 def test_fluctuation_dissipation_ks():
