@@ -115,6 +115,29 @@ rpy_status rpy_mdot(rpy_solver *s, const void *forces, const void *torques,
                     void *lin_out, void *ang_out, void *hip_stream);
 
 /*
+ * Several deterministic products with one geometry (an addition beside the
+ * paper's method, which applies M to one vector per call; Sec. 3.3 notes
+ * that a Krylov method may need several products at the same positions):
+ * for r = 0 .. nrhs-1,
+ *   lin_out[r] = M_uF F[r] + M_uT T[r],  ang_out[r] = M_wF F[r] + M_wT T[r].
+ * forces, torques, lin_out and ang_out hold nrhs consecutive n x 3 arrays
+ * (element (r, i, k) at offset 3*n*r + 3*i + k); either of forces / torques
+ * may be NULL (zero), not both; torques or ang_out need include_angular.
+ * 1 <= nrhs <= 1024 and nrhs * n < 2^31.  The pair geometry (separation,
+ * 1/r, the tensor coefficients) is evaluated once per pair for up to four
+ * vectors, and every vector's result is bit-identical to rpy_mdot of that
+ * vector with the same tile configuration.  Asynchronous.
+ */
+rpy_status rpy_mdot_multi(rpy_solver *s, const void *forces, const void *torques, int nrhs,
+                          void *lin_out, void *ang_out, void *hip_stream);
+
+/* Targets per lane of the multi-vector pair kernel: 1, 2, or 0 (default)
+ * for the measured choice (1 for the float32 product with angular blocks,
+ * 2 otherwise); results do not depend on it.  RPY_ERR_INVALID_ARG
+ * otherwise. */
+rpy_status rpy_set_multi_config(rpy_solver *s, int targets_per_lane);
+
+/*
  * Fluctuating displacements (Sec. 3.2, sqrtMdotW; second term of eq.
  * (bdhi)) by the Lanczos iteration of Sec. 3.3:
  * y = prefactor * M^{1/2} w, converging to the symmetric square root.
@@ -134,6 +157,27 @@ rpy_status rpy_mdot(rpy_solver *s, const void *forces, const void *torques,
 rpy_status rpy_sqrt_mdot_w(rpy_solver *s, const void *w, double prefactor, double tol,
                            int max_iter, void *lin_out, void *ang_out, int *iters_out,
                            double *incr_out, void *hip_stream);
+
+/*
+ * Fluctuating displacements for several noise vectors with one geometry (an
+ * addition beside the paper's method): y_r = prefactor * M^{1/2} w_r for
+ * r = 0 .. nrhs-1 by nrhs Lanczos recurrences advanced together, each
+ * iteration applying M to all unconverged recurrences in one multi-vector
+ * product (rpy_mdot_multi).  w holds nrhs consecutive vectors of 3N (6N with
+ * include_angular) entries; lin_out / ang_out hold nrhs consecutive n x 3
+ * arrays.  Each recurrence stops at the iteration, and with the result,
+ * that rpy_sqrt_mdot_w gives for its vector alone (bit-identical with the
+ * same tile configuration).  iters_out and incr_out (host, nrhs entries,
+ * may be NULL) receive each recurrence's iteration count and last relative
+ * increment.  1 <= nrhs <= 1024 and nrhs * n < 2^31; the float64 workspace
+ * holds nrhs bases of min(max_iter, 1024) + 1 vectors.  Synchronises
+ * hip_stream.  Returns RPY_ERR_NOT_SPD if any recurrence found M
+ * indefinite, else RPY_ERR_NOT_CONVERGED if any reached max_iter (all
+ * results written), RPY_ERR_NONFINITE for a non-finite w_r.
+ */
+rpy_status rpy_sqrt_mdot_w_multi(rpy_solver *s, const void *w, int nrhs, double prefactor, double tol,
+                                 int max_iter, void *lin_out, void *ang_out, int *iters_out,
+                                 double *incr_out, void *hip_stream);
 
 /*
  * Thermal drift d_X . M (Sec. 3.2, divM; third term of eq. (bdhi)).  In an
@@ -321,13 +365,19 @@ rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_pe
 rpy_status rpy_autotune(rpy_solver *s, const char *cache_path, void *hip_stream);
 
 /* Kernel classes reported by rpy_kernel_time. */
-typedef enum { RPY_KERNEL_PAIR = 0, RPY_KERNEL_ADJOINT = 1, RPY_KERNEL_LANCZOS_CGS = 2 } rpy_kernel;
+typedef enum {
+    RPY_KERNEL_PAIR = 0,
+    RPY_KERNEL_ADJOINT = 1,
+    RPY_KERNEL_LANCZOS_CGS = 2,
+    RPY_KERNEL_PAIR_MULTI = 3
+} rpy_kernel;
 
 /*
  * Instrumentation, not part of the method: with `enable` != 0 the solver
  * records a HIP event pair, on the stream of the call, around every launch
  * of its pair kernel (forward products, including those inside sqrtMdotW),
- * of its adjoint kernel, and around the two classical Gram-Schmidt passes of
+ * of its adjoint kernel, of the multi-vector pair kernels (one record per
+ * rpy_mdot_multi call), and around the two classical Gram-Schmidt passes of
  * every Lanczos iteration (four launches: two projections V^T w and two
  * updates w -= V h).  Enabling (or re-enabling) clears the records.
  */
@@ -336,7 +386,8 @@ rpy_status rpy_enable_timing(rpy_solver *s, int enable);
 /*
  * Sum of the recorded durations of one kernel class in milliseconds, the
  * number of records and the work they did: ordered particle pairs for
- * RPY_KERNEL_PAIR and RPY_KERNEL_ADJOINT; algorithmic HBM bytes for
+ * RPY_KERNEL_PAIR and RPY_KERNEL_ADJOINT, pairs times vectors for
+ * RPY_KERNEL_PAIR_MULTI; algorithmic HBM bytes for
  * RPY_KERNEL_LANCZOS_CGS (per pass at iteration k with basis vectors of n
  * doubles: (k + 1) n reads for V^T w, (k + 1) n reads and n writes for the
  * update, times 8 bytes).  Waits for the recorded events (host blocking).

@@ -74,7 +74,10 @@ def load() -> ctypes.CDLL:
         "rpy_initialize": ([vp, d, d, i], i),
         "rpy_set_positions": ([vp, vp, i64, i, vp], i),
         "rpy_mdot": ([vp, vp, vp, vp, vp, vp], i),
+        "rpy_mdot_multi": ([vp, vp, vp, i, vp, vp, vp], i),
+        "rpy_set_multi_config": ([vp, i], i),
         "rpy_sqrt_mdot_w": ([vp, vp, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
+        "rpy_sqrt_mdot_w_multi": ([vp, vp, i, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_div_m": ([vp, vp, vp, vp], i),
         "rpy_div_m_rfd": ([vp, vp, d, vp, vp, vp], i),
         "rpy_langevin_velocities": ([vp, vp, vp, vp, d, d, d, i, vp, vp, ctypes.POINTER(i), vp], i),
@@ -167,6 +170,17 @@ def rpy_mdot(h, forces, torques, lin_out, ang_out, dtype, n):
                               _stream(lin_out)))
 
 
+def rpy_mdot_multi(h, forces, torques, nrhs, lin_out, ang_out, dtype, n):
+    m = 3 * n * nrhs
+    _check(h, load().rpy_mdot_multi(h, _ptr(forces, dtype, m, "forces"), _ptr(torques, dtype, m, "torques"),
+                                    int(nrhs), _ptr(lin_out, dtype, m, "lin_out"), _ptr(ang_out, dtype, m, "ang_out"),
+                                    _stream(lin_out)))
+
+
+def rpy_set_multi_config(h, targets_per_lane):
+    _check(h, load().rpy_set_multi_config(h, int(targets_per_lane)))
+
+
 def rpy_sqrt_mdot_w(h, w, prefactor, tol, max_iter, lin_out, ang_out, dtype, n, angular):
     iters = ctypes.c_int(0)
     incr = ctypes.c_double(0.0)
@@ -179,6 +193,21 @@ def rpy_sqrt_mdot_w(h, w, prefactor, tol, max_iter, lin_out, ang_out, dtype, n, 
                                 iters.value, incr.value)
     _check(h, st)
     return iters.value, incr.value
+
+
+def rpy_sqrt_mdot_w_multi(h, w, nrhs, prefactor, tol, max_iter, lin_out, ang_out, dtype, n, angular):
+    """Per-vector (iterations, increments) lists; NotConvergedError carries them too."""
+    iters = (ctypes.c_int * nrhs)()
+    incr = (ctypes.c_double * nrhs)()
+    m = 3 * n * nrhs
+    st = load().rpy_sqrt_mdot_w_multi(h, _ptr(w, dtype, (2 if angular else 1) * m, "W"), int(nrhs),
+                                      float(prefactor), float(tol), int(max_iter), _ptr(lin_out, dtype, m, "lin_out"),
+                                      _ptr(ang_out, dtype, m, "ang_out"), iters, incr, _stream(lin_out))
+    its, incs = list(iters), list(incr)
+    if st == Status.NOT_CONVERGED:
+        raise NotConvergedError(st, load().rpy_last_error(h).decode(), (lin_out, ang_out), its, incs)
+    _check(h, st)
+    return its, incs
 
 
 def rpy_div_m(h, lin_out, ang_out, dtype, n):
@@ -316,13 +345,13 @@ def rpy_enable_timing(h, enable: bool = True):
     _check(h, load().rpy_enable_timing(h, int(bool(enable))))
 
 
-KERNEL = {"pair": 0, "adjoint": 1, "lanczos_cgs": 2}
+KERNEL = {"pair": 0, "adjoint": 1, "lanczos_cgs": 2, "pair_multi": 3}
 
 
 def rpy_kernel_time(h, kernel: str = "pair"):
     """(total milliseconds, records, work) recorded for a kernel class; work
-    is ordered pairs for "pair" and "adjoint", algorithmic HBM bytes for
-    "lanczos_cgs"."""
+    is ordered pairs for "pair" and "adjoint", pairs times vectors for
+    "pair_multi", algorithmic HBM bytes for "lanczos_cgs"."""
     ms = ctypes.c_double(0.0)
     n = ctypes.c_int64(0)
     work = ctypes.c_double(0.0)

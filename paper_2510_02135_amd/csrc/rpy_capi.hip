@@ -219,7 +219,7 @@ rpy_status rpy_div_m(rpy_solver *s, void *lin_out, void *ang_out, void *hip_stre
 rpy_status rpy_enable_timing(rpy_solver *s, int enable) {
     if (!s) return RPY_ERR_INVALID_ARG;
     s->timing = enable != 0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kKernelClasses; ++k) {
         s->ev_used[k] = 0;
         s->ev_pairs[k] = 0.0;
     }
@@ -228,7 +228,7 @@ rpy_status rpy_enable_timing(rpy_solver *s, int enable) {
 
 rpy_status rpy_kernel_time(rpy_solver *s, rpy_kernel kernel, double *ms_total, int64_t *launches, double *work) {
     if (!s) return RPY_ERR_INVALID_ARG;
-    if ((int)kernel < 0 || (int)kernel > 2) return fail(s, RPY_ERR_INVALID_ARG, "unknown kernel class");
+    if ((int)kernel < 0 || (int)kernel >= kKernelClasses) return fail(s, RPY_ERR_INVALID_ARG, "unknown kernel class");
     const int k = (int)kernel;
     double total = 0.0;
     for (size_t i = 0; i < s->ev_used[k]; ++i) {
@@ -256,7 +256,7 @@ void rpy_destroy(rpy_solver *s) {
             (void)hipEventDestroy(pr.second);
         }
     if (s->host_flag) (void)hipHostFree(s->host_flag);
-    if (s->host_scal) (void)hipHostFree(s->host_scal);
+    if (s->host_stat) (void)hipHostFree(s->host_stat);
     delete s;
 }
 

@@ -13,6 +13,9 @@
 
 namespace rpy {
 
+constexpr int kKernelClasses = 4;   // rpy_kernel values
+constexpr int kMaxRhs = 1024;       // vectors per multi-vector product
+
 // Tile configuration of the pair kernels.
 struct TileConfig {
     int tm = 2;          // targets per lane (1, 2 or 4)
@@ -71,15 +74,17 @@ struct rpy_solver {
     int64_t n = 0;
     rpy_dtype dtype = RPY_F32;
     rpy::TileConfig cfg[2];   // pair-kernel tiles for products without / with the angular blocks
+    int multi_tm = 0;         // targets per lane of the multi-vector pair kernel (0 = automatic, 1, 2)
     rpy::DevBuf pos, f, t, part, flag;
     // Lanczos workspace (float64): basis, scratch vectors, tridiagonal data
     rpy::DevBuf lz_basis, lz_w, lz_scal, lz_red, lz_q, lz_vec, lz_mon, drift;
     // launch timing (rpy_enable_timing): event pairs and pair counts per kernel class
     bool timing = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];
-    size_t ev_used[3] = {0, 0, 0};
-    double ev_pairs[3] = {0.0, 0.0, 0.0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[rpy::kKernelClasses];
+    size_t ev_used[rpy::kKernelClasses] = {};
+    double ev_pairs[rpy::kKernelClasses] = {};
     unsigned *host_flag = nullptr;   // pinned host word for flags
-    double *host_scal = nullptr;     // pinned host scalars for Lanczos polling
+    double *host_stat = nullptr;     // pinned host copy of the Lanczos status blocks
+    size_t host_stat_cap = 0;        // doubles in host_stat
     std::string err;
 };

@@ -255,85 +255,145 @@ __global__ void next_basis_kernel(double *__restrict__ dst, const double *__rest
         dst[i] = broken ? 0.0 : src[i] * inv;
 }
 
-struct LanczosWork {
-    double *V = nullptr;
-    int64_t ld = 0;
-    int cap = 0;
-    double *w = nullptr, *alpha = nullptr, *beta = nullptr, *h = nullptr, *red = nullptr;
-    double *s = nullptr, *s_prev = nullptr, *Q = nullptr, *status = nullptr;
-    double *est0 = nullptr, *est1 = nullptr, *mon = nullptr;
-    int64_t mon_stride = 0;
+// Device state of one recurrence inside the shared workspace, and the
+// host's view of its progress.
+struct LzRec {
+    double *V = nullptr;   // basis, cap + 1 columns of ld doubles
+    double *status = nullptr, *alpha = nullptr, *beta = nullptr, *h = nullptr;
+    double *s = nullptr, *s_prev = nullptr, *est0 = nullptr, *est1 = nullptr;
+    int kf = 0;
+    double incr = INFINITY;
+    const double *s_final = nullptr;   // exact s_k unless the estimate decided
+    bool done = false, converged = false, not_spd = false, exact = false;
 };
 
 int grid_for(int64_t n) { return (int)std::min<int64_t>(2048, std::max<int64_t>(1, (n + 255) / 256)); }
 
+// w (slots of ld doubles, linear then angular rows) = M v for the basis
+// column `col` of every listed recurrence: one single-vector product, or
+// one multi-vector product for several.
+template <typename Real>
+rpy_status lanczos_products(rpy_solver *s, const std::vector<LzRec *> &act, int64_t ld, int col, double *W,
+                            hipStream_t st) {
+    const int64_t np = s->n;
+    const bool am = s->angular;
+    const int m = (int)act.size();
+    const size_t elt = sizeof(vec4_t<Real>);
+    HIP_TRY(s, s->f.ensure(elt * (size_t)m * np));
+    if (am) HIP_TRY(s, s->t.ensure(elt * (size_t)m * np));
+    for (int j = 0; j < m; ++j) {
+        const double *v = act[j]->V + (size_t)col * ld;
+        HIP_TRY(s, (launch_stage_vec<double, Real>(v, np, s->f.as<vec4_t<Real>>() + (size_t)j * np, st)));
+        if (am) HIP_TRY(s, (launch_stage_vec<double, Real>(v + 3 * np, np, s->t.as<vec4_t<Real>>() + (size_t)j * np, st)));
+    }
+    if (m == 1) return apply_staged<Real, double>(s, am, W, am ? W + 3 * np : nullptr, st);
+    return apply_staged_multi<Real, double>(s, am, m, W, am ? W + 3 * np : nullptr, ld, st);
+}
+
 }  // namespace
 
+// nrhs Lanczos recurrences for prefactor * M^{1/2} W_r with one geometry,
+// advanced in lockstep: each iteration applies M to the current basis
+// vector of every recurrence still running (one multi-vector product), then
+// runs each recurrence's vector operations and stopping test exactly as for
+// a single vector, so every recurrence stops at the iteration, and with the
+// result, that it would reach alone (the products are bit-identical).
+// W_r at w_in + r * wstride; outputs at lin / ang + r * ostride.
 template <typename Tio>
-rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double tol, int max_iter, Tio *lin,
-                       Tio *ang, int *iters_out, double *incr_out, hipStream_t st, bool accumulate) {
+rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t wstride, double prefactor,
+                             double tol, int max_iter, Tio *lin, Tio *ang, int64_t ostride, int *iters_out,
+                             double *incr_out, hipStream_t st, bool accumulate) {
     const bool ang_mode = s->angular;
     const int64_t np = s->n;
     const int64_t n = (ang_mode ? 6 : 3) * np;
-    const int kmax = (int)std::min<int64_t>({(int64_t)max_iter, (int64_t)kMaxK, n});
     if (max_iter > kMaxK)
         return fail(s, RPY_ERR_INVALID_ARG, "max_iter exceeds the largest supported Krylov dimension (1024)");
+    const int kmax = (int)std::min<int64_t>({(int64_t)max_iter, (int64_t)kMaxK, n});
 
-    // workspace: basis of kmax+1 columns, scalars, Q (kmax x kmax)
+    // workspace: per recurrence a basis of kmax+1 columns, a product slot and
+    // scalar arrays; shared partial sums, eigensolver and monitor scratch
     const int64_t ld = (n + 63) / 64 * 64;
-    const size_t basis_bytes = (size_t)(kmax + 1) * ld * sizeof(double);
-    HIP_TRY(s, s->lz_basis.ensure(basis_bytes));
-    HIP_TRY(s, s->lz_w.ensure((size_t)ld * sizeof(double)));
-    HIP_TRY(s, s->lz_scal.ensure(sizeof(double) * (ST_SIZE + 8 * (size_t)(kMaxK + 1))));
-    // partial sums: the Gram-Schmidt projection keeps one per (row chunk, column)
+    const size_t per_rec = 8 * (size_t)(kMaxK + 1);   // alpha, beta, h, s, s_prev, est0, est1 (+1 spare)
+    HIP_TRY(s, s->lz_basis.ensure((size_t)nrhs * (kmax + 1) * ld * sizeof(double)));
+    HIP_TRY(s, s->lz_w.ensure((size_t)nrhs * ld * sizeof(double)));
+    HIP_TRY(s, s->lz_scal.ensure(sizeof(double) * (size_t)nrhs * (ST_SIZE + per_rec)));
     const size_t red_rows = std::max<size_t>(kRedBlocks, (size_t)((n + kGtChunk - 1) / kGtChunk));
     HIP_TRY(s, s->lz_red.ensure(sizeof(double) * red_rows * (kMaxK + 1)));
     HIP_TRY(s, s->lz_q.ensure(sizeof(double) * 2 * (size_t)kmax * kmax));
-    // monitor scratch: per workgroup, one vector of kMonNodes systems
     const int64_t mon_stride = (int64_t)kmax * kMonNodes;
     HIP_TRY(s, s->lz_mon.ensure(sizeof(double) * 2 * (size_t)mon_stride));
-    if (!s->host_scal) HIP_TRY(s, hipHostMalloc((void **)&s->host_scal, sizeof(double) * 8, hipHostMallocDefault));
-    LanczosWork L;
-    L.V = s->lz_basis.as<double>();
-    L.ld = ld;
-    L.cap = kmax;
-    L.w = s->lz_w.as<double>();
-    L.status = s->lz_scal.as<double>();
-    L.alpha = L.status + ST_SIZE;
-    L.beta = L.alpha + (kMaxK + 1);
-    L.h = L.beta + (kMaxK + 1);
-    L.s = L.h + (kMaxK + 1);
-    L.s_prev = L.s + (kMaxK + 1);
-    L.est0 = L.s_prev + (kMaxK + 1);
-    L.est1 = L.est0 + (kMaxK + 1);
-    L.mon = s->lz_mon.as<double>();
-    L.mon_stride = mon_stride;
-    L.red = s->lz_red.as<double>();
-    L.Q = s->lz_q.as<double>();
-
+    if (s->host_stat_cap < (size_t)nrhs * ST_SIZE) {
+        if (s->host_stat) (void)hipHostFree(s->host_stat);
+        s->host_stat = nullptr;
+        s->host_stat_cap = 0;
+        HIP_TRY(s, hipHostMalloc((void **)&s->host_stat, sizeof(double) * (size_t)nrhs * ST_SIZE,
+                                 hipHostMallocDefault));
+        s->host_stat_cap = (size_t)nrhs * ST_SIZE;
+    }
+    double *const hstat = s->host_stat;
+    double *const status_all = s->lz_scal.as<double>();   // [nrhs][ST_SIZE], contiguous for one copy
+    double *const W = s->lz_w.as<double>();
+    double *const red = s->lz_red.as<double>();
+    double *const Q = s->lz_q.as<double>();
+    double *const mon = s->lz_mon.as<double>();
+    std::vector<LzRec> rec(nrhs);
+    for (int r = 0; r < nrhs; ++r) {
+        LzRec &R = rec[r];
+        R.V = s->lz_basis.as<double>() + (size_t)r * (kmax + 1) * ld;
+        R.status = status_all + (size_t)r * ST_SIZE;
+        R.alpha = status_all + (size_t)nrhs * ST_SIZE + (size_t)r * per_rec;
+        R.beta = R.alpha + (kMaxK + 1);
+        R.h = R.beta + (kMaxK + 1);
+        R.s = R.h + (kMaxK + 1);
+        R.s_prev = R.s + (kMaxK + 1);
+        R.est0 = R.s_prev + (kMaxK + 1);
+        R.est1 = R.est0 + (kMaxK + 1);
+        R.s_final = R.s;
+    }
     const bool fp32 = s->dtype == RPY_F32;
     rpy_status r = ensure_vec_buffers(s, ang_mode);
     if (r != RPY_OK) return r;
-
-    // beta0 = |W|, v1 = W / beta0; the status block starts cleared
-    HIP_TRY(s, launch_fill_zero<double>(L.status, ST_SIZE, st));
-    hipLaunchKernelGGL((sumsq_partial<Tio>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, w_in, n, L.red);
-    hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, L.red, kRedBlocks, L.status + ST_BETA0, 1);
-    HIP_TRY(s, hipGetLastError());
-    HIP_TRY(s, hipMemcpyAsync(s->host_scal, L.status, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(s, hipStreamSynchronize(st));
-    const double beta0 = s->host_scal[0];
-    if (!std::isfinite(beta0)) return fail(s, RPY_ERR_NONFINITE, "the noise vector W is not finite");
-    if (iters_out) *iters_out = 0;
-    if (incr_out) *incr_out = 0.0;
-    if (beta0 == 0.0) {
-        if (!accumulate) {
-            HIP_TRY(s, launch_fill_zero<Tio>(lin, 3 * np, st));
-            if (ang) HIP_TRY(s, launch_fill_zero<Tio>(ang, 3 * np, st));
-        }
+    auto copy_status = [&]() -> rpy_status {
+        HIP_TRY(s, hipMemcpyAsync(hstat, status_all, sizeof(double) * (size_t)nrhs * ST_SIZE, hipMemcpyDeviceToHost,
+                                  st));
+        HIP_TRY(s, hipStreamSynchronize(st));
         return RPY_OK;
+    };
+
+    // beta0 = |W_r|, v1 = W_r / beta0; status blocks start cleared
+    HIP_TRY(s, launch_fill_zero<double>(status_all, (int64_t)nrhs * ST_SIZE, st));
+    for (int q = 0; q < nrhs; ++q) {
+        hipLaunchKernelGGL((sumsq_partial<Tio>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, w_in + q * wstride, n,
+                           red);
+        hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, red, kRedBlocks,
+                           rec[q].status + ST_BETA0, 1);
     }
-    hipLaunchKernelGGL((init_basis<Tio>), dim3(grid_for(n)), dim3(256), 0, st, L.V, w_in, L.status + ST_BETA0, n);
+    HIP_TRY(s, hipGetLastError());
+    if ((r = copy_status()) != RPY_OK) return r;
+    for (int q = 0; q < nrhs; ++q) {
+        if (iters_out) iters_out[q] = 0;
+        if (incr_out) incr_out[q] = 0.0;
+        const double beta0 = hstat[(size_t)q * ST_SIZE + ST_BETA0];
+        if (!std::isfinite(beta0))
+            return fail(s, RPY_ERR_NONFINITE,
+                        nrhs == 1 ? std::string("the noise vector W is not finite")
+                                  : "noise vector " + std::to_string(q) + " is not finite");
+    }
+    const int g = grid_for(n);
+    for (int q = 0; q < nrhs; ++q) {
+        if (hstat[(size_t)q * ST_SIZE + ST_BETA0] == 0.0) {
+            // zero W: zero result, nothing to iterate
+            rec[q].done = rec[q].converged = true;
+            rec[q].incr = 0.0;
+            if (!accumulate) {
+                HIP_TRY(s, launch_fill_zero<Tio>(lin + q * ostride, 3 * np, st));
+                if (ang) HIP_TRY(s, launch_fill_zero<Tio>(ang + q * ostride, 3 * np, st));
+            }
+            continue;
+        }
+        hipLaunchKernelGGL((init_basis<Tio>), dim3(g), dim3(256), 0, st, rec[q].V, w_in + q * wstride,
+                           rec[q].status + ST_BETA0, n);
+    }
     HIP_TRY(s, hipGetLastError());
 
     // The increment test needs s_{k-1} and s_k.  Each iteration k >= 2
@@ -347,117 +407,147 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
     // iteration and never uses the estimate.
     const char *check_env = std::getenv("RPY_LANCZOS_CHECK");
     const bool check_every = check_env && std::string(check_env) == "every";
-    const int g = grid_for(n);
     const int gt_blocks = (int)((n + kGtChunk - 1) / kGtChunk);
-    int k = 0, kf = 0;
-    double incr = INFINITY;
-    const double *s_final = L.s;   // exact s_k unless the estimate decided
-    bool converged = false, not_spd = false;
-    for (k = 1; k <= kmax; ++k) {
-        const double *vk = L.V + (size_t)(k - 1) * ld;
-        // w = M v_k
-        if (fp32) {
-            HIP_TRY(s, (launch_stage_vec<double, float>(vk, np, s->f.as<float4>(), st)));
-            if (ang_mode) HIP_TRY(s, (launch_stage_vec<double, float>(vk + 3 * np, np, s->t.as<float4>(), st)));
-            r = apply_staged<float, double>(s, ang_mode, L.w, ang_mode ? L.w + 3 * np : nullptr, st);
-        } else {
-            HIP_TRY(s, (launch_stage_vec<double, double>(vk, np, s->f.as<double4>(), st)));
-            if (ang_mode) HIP_TRY(s, (launch_stage_vec<double, double>(vk + 3 * np, np, s->t.as<double4>(), st)));
-            r = apply_staged<double, double>(s, ang_mode, L.w, ang_mode ? L.w + 3 * np : nullptr, st);
-        }
+    std::vector<LzRec *> act;
+    for (int k = 1; k <= kmax; ++k) {
+        act.clear();
+        for (auto &R : rec)
+            if (!R.done) act.push_back(&R);
+        if (act.empty()) break;
+        // w_j = M v_k for every running recurrence (slot j)
+        r = fp32 ? lanczos_products<float>(s, act, ld, k - 1, W, st)
+                 : lanczos_products<double>(s, act, ld, k - 1, W, st);
         if (r != RPY_OK) return r;
-        // three-term recurrence
-        if (k > 1)
-            hipLaunchKernelGGL(axpy_dev, dim3(g), dim3(256), 0, st, L.w, L.V + (size_t)(k - 2) * ld, L.beta + (k - 2),
-                               -1.0, n);
-        hipLaunchKernelGGL(dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, vk, L.w, n, L.red);
-        hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, L.red, kRedBlocks, L.alpha + (k - 1), 0);
-        hipLaunchKernelGGL(axpy_dev, dim3(g), dim3(256), 0, st, L.w, vk, L.alpha + (k - 1), -1.0, n);
-        // classical Gram-Schmidt against V_k, twice
-        hipEvent_t cgs0 = timing_begin(s, RPY_KERNEL_LANCZOS_CGS, 2.0 * (2.0 * k + 3.0) * (double)n * 8.0);
-        if (cgs0) HIP_TRY(s, hipEventRecord(cgs0, st));
-        for (int pass = 0; pass < 2; ++pass) {
-            hipLaunchKernelGGL(gemv_t_partial, dim3(gt_blocks, (k + kGtCols - 1) / kGtCols), dim3(kRedThreads), 0, st,
-                               L.V, ld, k, L.w, n, L.red);
-            hipLaunchKernelGGL(gemv_t_final, dim3(k), dim3(kRedThreads), 0, st, L.red, gt_blocks, k, L.h);
-            hipLaunchKernelGGL(gemv_n_sub, dim3(g), dim3(256), 0, st, L.V, ld, k, L.h, L.w, n);
-        }
-        if (hipEvent_t cgs1 = timing_end(s, RPY_KERNEL_LANCZOS_CGS)) HIP_TRY(s, hipEventRecord(cgs1, st));
-        // beta_k = |w|, breakdown bookkeeping, v_{k+1}
-        hipLaunchKernelGGL(dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, L.w, L.w, n, L.red);
-        hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, L.red, kRedBlocks, L.beta + (k - 1), 1);
-        hipLaunchKernelGGL(finish_iter_kernel, dim3(1), dim3(64), 0, st, L.alpha, L.beta, k, L.status);
-        HIP_TRY(s, hipGetLastError());
-        const bool last = (k == kmax);
-        bool exact = last || check_every;
-        if (!exact && k >= 2) {
-            hipLaunchKernelGGL(lanczos_monitor_kernel, dim3(2), dim3(kMonThreads), 0, st, L.alpha, L.beta, k, L.mon,
-                               L.mon_stride, L.est0, L.est1);
-            hipLaunchKernelGGL(increment_kernel, dim3(1), dim3(kRedThreads), 0, st, L.est0, L.est1, k, L.status,
-                               (int)ST_EST);
+        for (size_t j = 0; j < act.size(); ++j) {
+            LzRec &R = *act[j];
+            double *w = W + j * ld;
+            const double *vk = R.V + (size_t)(k - 1) * ld;
+            // three-term recurrence
+            if (k > 1)
+                hipLaunchKernelGGL(axpy_dev, dim3(g), dim3(256), 0, st, w, R.V + (size_t)(k - 2) * ld, R.beta + (k - 2),
+                                   -1.0, n);
+            hipLaunchKernelGGL(dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, vk, w, n, red);
+            hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, red, kRedBlocks, R.alpha + (k - 1), 0);
+            hipLaunchKernelGGL(axpy_dev, dim3(g), dim3(256), 0, st, w, vk, R.alpha + (k - 1), -1.0, n);
+            // classical Gram-Schmidt against V_k, twice
+            hipEvent_t cgs0 = timing_begin(s, RPY_KERNEL_LANCZOS_CGS, 2.0 * (2.0 * k + 3.0) * (double)n * 8.0);
+            if (cgs0) HIP_TRY(s, hipEventRecord(cgs0, st));
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(gemv_t_partial, dim3(gt_blocks, (k + kGtCols - 1) / kGtCols), dim3(kRedThreads), 0,
+                                   st, R.V, ld, k, w, n, red);
+                hipLaunchKernelGGL(gemv_t_final, dim3(k), dim3(kRedThreads), 0, st, red, gt_blocks, k, R.h);
+                hipLaunchKernelGGL(gemv_n_sub, dim3(g), dim3(256), 0, st, R.V, ld, k, R.h, w, n);
+            }
+            if (hipEvent_t cgs1 = timing_end(s, RPY_KERNEL_LANCZOS_CGS)) HIP_TRY(s, hipEventRecord(cgs1, st));
+            // beta_k = |w|, breakdown bookkeeping
+            hipLaunchKernelGGL(dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, w, n, red);
+            hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, red, kRedBlocks, R.beta + (k - 1), 1);
+            hipLaunchKernelGGL(finish_iter_kernel, dim3(1), dim3(64), 0, st, R.alpha, R.beta, k, R.status);
             HIP_TRY(s, hipGetLastError());
-            HIP_TRY(s, hipMemcpyAsync(s->host_scal, L.status, sizeof(double) * ST_SIZE, hipMemcpyDeviceToHost, st));
-            HIP_TRY(s, hipStreamSynchronize(st));
-            const double est = s->host_scal[ST_EST];
-            // the exact test only where the estimate cannot decide: a breakdown,
-            // an eigenvalue outside the quadrature's range (NaN), or an
-            // estimate within 0.1 % of tol
-            exact = s->host_scal[ST_BREAK] > 0.0 || !std::isfinite(est) || std::fabs(est - tol) <= 1e-3 * tol;
-            if (!exact && est < tol) {
-                // converged: the quadrature s_k is T_k^{1/2} e_1 to rounding
-                incr = est;
-                kf = k;
-                s_final = L.est1;
-                converged = true;
-                break;
+            R.exact = (k == kmax) || check_every;
+        }
+        // stopping test by the quadrature estimate, all running recurrences at once
+        if (!check_every && k >= 2 && k < kmax) {
+            for (LzRec *R : act) {
+                hipLaunchKernelGGL(lanczos_monitor_kernel, dim3(2), dim3(kMonThreads), 0, st, R->alpha, R->beta, k,
+                                   mon, mon_stride, R->est0, R->est1);
+                hipLaunchKernelGGL(increment_kernel, dim3(1), dim3(kRedThreads), 0, st, R->est0, R->est1, k,
+                                   R->status, (int)ST_EST);
+            }
+            HIP_TRY(s, hipGetLastError());
+            if ((r = copy_status()) != RPY_OK) return r;
+            for (LzRec *R : act) {
+                const double *hs = hstat + (R->status - status_all);
+                const double est = hs[ST_EST];
+                // the exact test only where the estimate cannot decide: a
+                // breakdown, an eigenvalue outside the quadrature's range
+                // (NaN), or an estimate within 0.1 % of tol
+                R->exact = hs[ST_BREAK] > 0.0 || !std::isfinite(est) || std::fabs(est - tol) <= 1e-3 * tol;
+                if (!R->exact && est < tol) {
+                    // converged: the quadrature s_k is T_k^{1/2} e_1 to rounding
+                    R->incr = est;
+                    R->kf = k;
+                    R->s_final = R->est1;
+                    R->converged = R->done = true;
+                }
             }
         }
-        if (exact) {
-            hipLaunchKernelGGL(tridiag_sqrt_kernel, dim3(2), dim3(kEigThreads), 0, st, L.alpha, L.beta, k, L.s_prev,
-                               L.s, L.Q, (int64_t)kmax * kmax, L.status);
-            hipLaunchKernelGGL(increment_kernel, dim3(1), dim3(kRedThreads), 0, st, L.s_prev, L.s, k, L.status,
+        bool any_exact = false;
+        for (LzRec *R : act) {
+            if (R->done || !R->exact) continue;
+            any_exact = true;
+            hipLaunchKernelGGL(tridiag_sqrt_kernel, dim3(2), dim3(kEigThreads), 0, st, R->alpha, R->beta, k, R->s_prev,
+                               R->s, Q, (int64_t)kmax * kmax, R->status);
+            hipLaunchKernelGGL(increment_kernel, dim3(1), dim3(kRedThreads), 0, st, R->s_prev, R->s, k, R->status,
                                (int)ST_INCR);
-            HIP_TRY(s, hipGetLastError());
-            HIP_TRY(s, hipMemcpyAsync(s->host_scal, L.status, sizeof(double) * ST_SIZE, hipMemcpyDeviceToHost, st));
-            HIP_TRY(s, hipStreamSynchronize(st));
-            incr = s->host_scal[ST_INCR];
-            const int kb = (int)s->host_scal[ST_BREAK];
-            kf = k;
-            if (kb > 0) {
-                // invariant Krylov space at kb: T_k = diag(T_kb, 0), so s_k = [s_kb; 0]
-                kf = kb;
-                converged = true;
-                break;
-            }
-            if (((int)s->host_scal[ST_FLAGS]) & FLAG_NOT_SPD) {
-                not_spd = true;
-                break;
-            }
-            if (k >= 2 && incr < tol) {
-                converged = true;
-                break;
-            }
-            if (last) break;
         }
-        hipLaunchKernelGGL(next_basis_kernel, dim3(g), dim3(256), 0, st, L.V + (size_t)k * ld, L.w, L.beta + (k - 1),
-                           L.status, n);
+        if (any_exact) {
+            HIP_TRY(s, hipGetLastError());
+            if ((r = copy_status()) != RPY_OK) return r;
+            for (LzRec *R : act) {
+                if (R->done || !R->exact) continue;
+                const double *hs = hstat + (R->status - status_all);
+                R->incr = hs[ST_INCR];
+                const int kb = (int)hs[ST_BREAK];
+                R->kf = k;
+                if (kb > 0) {
+                    // invariant Krylov space at kb: T_k = diag(T_kb, 0), so s_k = [s_kb; 0]
+                    R->kf = kb;
+                    R->converged = R->done = true;
+                } else if (((int)hs[ST_FLAGS]) & FLAG_NOT_SPD) {
+                    R->not_spd = R->done = true;
+                } else if (k >= 2 && R->incr < tol) {
+                    R->converged = R->done = true;
+                } else if (k == kmax) {
+                    R->done = true;
+                }
+            }
+        }
+        // v_{k+1} = w / beta_k for the recurrences that go on
+        for (size_t j = 0; j < act.size(); ++j) {
+            LzRec &R = *act[j];
+            if (R.done) continue;
+            hipLaunchKernelGGL(next_basis_kernel, dim3(g), dim3(256), 0, st, R.V + (size_t)k * ld, W + j * ld,
+                               R.beta + (k - 1), R.status, n);
+        }
+        HIP_TRY(s, hipGetLastError());
     }
-    hipLaunchKernelGGL((combine_out<Tio>), dim3(g), dim3(256), 0, st, L.V, ld, kf, s_final, L.status, prefactor, n,
-                       3 * np, accumulate ? 1 : 0, lin, ang);
+    bool any_not_spd = false, any_not_conv = false;
+    for (int q = 0; q < nrhs; ++q) {
+        LzRec &R = rec[q];
+        if (R.kf > 0)
+            hipLaunchKernelGGL((combine_out<Tio>), dim3(g), dim3(256), 0, st, R.V, ld, R.kf, R.s_final, R.status,
+                               prefactor, n, 3 * np, accumulate ? 1 : 0, lin + q * ostride,
+                               ang ? ang + q * ostride : nullptr);
+        if (iters_out) iters_out[q] = R.kf;
+        if (incr_out) incr_out[q] = R.incr;
+        any_not_spd |= R.not_spd;
+        any_not_conv |= !R.converged && !R.not_spd;
+    }
     HIP_TRY(s, hipGetLastError());
     HIP_TRY(s, hipStreamSynchronize(st));
-    if (iters_out) *iters_out = kf;
-    if (incr_out) *incr_out = incr;
-    if (not_spd) return fail(s, RPY_ERR_NOT_SPD, "the mobility matrix is not positive definite (negative Ritz value)");
-    if (!converged)
+    if (any_not_spd)
+        return fail(s, RPY_ERR_NOT_SPD, "the mobility matrix is not positive definite (negative Ritz value)");
+    if (any_not_conv)
         return fail(s, RPY_ERR_NOT_CONVERGED, "Lanczos did not reach the tolerance within max_iter iterations");
     return RPY_OK;
+}
+
+template <typename Tio>
+rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double tol, int max_iter, Tio *lin,
+                       Tio *ang, int *iters_out, double *incr_out, hipStream_t st, bool accumulate) {
+    return lanczos_run_multi<Tio>(s, w_in, 1, 0, prefactor, tol, max_iter, lin, ang, 0, iters_out, incr_out, st,
+                                  accumulate);
 }
 
 template rpy_status lanczos_run<float>(rpy_solver *, const float *, double, double, int, float *, float *, int *,
                                        double *, hipStream_t, bool);
 template rpy_status lanczos_run<double>(rpy_solver *, const double *, double, double, int, double *, double *, int *,
                                         double *, hipStream_t, bool);
+template rpy_status lanczos_run_multi<float>(rpy_solver *, const float *, int, int64_t, double, double, int, float *,
+                                             float *, int64_t, int *, double *, hipStream_t, bool);
+template rpy_status lanczos_run_multi<double>(rpy_solver *, const double *, int, int64_t, double, double, int,
+                                              double *, double *, int64_t, int *, double *, hipStream_t, bool);
 
 }  // namespace rpy
 
@@ -480,4 +570,30 @@ extern "C" rpy_status rpy_sqrt_mdot_w(rpy_solver *s, const void *w, double prefa
                                    incr_out, st, false);
     return lanczos_run<float>(s, static_cast<const float *>(w), prefactor, tol, max_iter, static_cast<float *>(lin_out),
                               static_cast<float *>(ang_out), iters_out, incr_out, st, false);
+}
+
+extern "C" rpy_status rpy_sqrt_mdot_w_multi(rpy_solver *s, const void *w, int nrhs, double prefactor, double tol,
+                                            int max_iter, void *lin_out, void *ang_out, int *iters_out,
+                                            double *incr_out, void *hip_stream) {
+    using namespace rpy;
+    rpy_status r = check_ready(s);
+    if (r != RPY_OK) return r;
+    if (nrhs < 1 || nrhs > kMaxRhs) return fail(s, RPY_ERR_INVALID_ARG, "nrhs must be in [1, 1024]");
+    if (!w || !lin_out) return fail(s, RPY_ERR_INVALID_ARG, "W and the linear output must not be NULL");
+    if (s->angular && !ang_out) return fail(s, RPY_ERR_INVALID_ARG, "include_angular needs the angular output");
+    if (!s->angular && ang_out) return fail(s, RPY_ERR_ANGULAR_DISABLED, "angular output needs include_angular");
+    if (!(tol > 0.0 && tol < 1.0)) return fail(s, RPY_ERR_INVALID_ARG, "tol must be in (0, 1)");
+    if (max_iter < 1) return fail(s, RPY_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if (!std::isfinite(prefactor)) return fail(s, RPY_ERR_INVALID_ARG, "prefactor must be finite");
+    if ((int64_t)nrhs * s->n > (int64_t)INT32_MAX)
+        return fail(s, RPY_ERR_INVALID_ARG, "nrhs * n must stay below 2^31");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t wstride = (s->angular ? 6 : 3) * s->n, ostride = 3 * s->n;
+    if (s->dtype == RPY_F64)
+        return lanczos_run_multi<double>(s, static_cast<const double *>(w), nrhs, wstride, prefactor, tol, max_iter,
+                                         static_cast<double *>(lin_out), static_cast<double *>(ang_out), ostride,
+                                         iters_out, incr_out, st, false);
+    return lanczos_run_multi<float>(s, static_cast<const float *>(w), nrhs, wstride, prefactor, tol, max_iter,
+                                    static_cast<float *>(lin_out), static_cast<float *>(ang_out), ostride, iters_out,
+                                    incr_out, st, false);
 }

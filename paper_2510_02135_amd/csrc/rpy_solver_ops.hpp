@@ -26,12 +26,31 @@ template <typename Real, typename Tout>
 rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *ang_out, hipStream_t st,
                         const void *pos = nullptr);
 
+// nrhs products M [F_r; T_r] with the vectors staged in s->f (s->t) as
+// [vector][n] vec4 arrays (stage_multi); vector r's outputs are the n x 3
+// arrays at lin + r * ostride and ang_out + r * ostride.  Defined in
+// rpy_multi.hip.
+template <typename Real, typename Tout>
+rpy_status apply_staged_multi(rpy_solver *s, bool ang, int nrhs, Tout *lin, Tout *ang_out, int64_t ostride,
+                              hipStream_t st);
+template <typename Real>
+rpy_status stage_multi(rpy_solver *s, const Real *F, const Real *T, int nrhs, bool ang, hipStream_t st);
+
 // prefactor * M^{1/2} W by Lanczos for the stored positions (W and the
 // outputs in the solver's dtype Tio); with `accumulate` the result is added
 // to lin/ang instead of overwriting them.  Synchronises `st`.
 template <typename Tio>
 rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double tol, int max_iter, Tio *lin,
                        Tio *ang, int *iters_out, double *incr_out, hipStream_t st, bool accumulate);
+
+// nrhs recurrences of lanczos_run with one geometry, in lockstep: W_r at
+// w_in + r * wstride, outputs at lin / ang + r * ostride, iters_out and
+// incr_out (host, nrhs entries, may be NULL).  Every recurrence stops and
+// ends as it would alone.
+template <typename Tio>
+rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t wstride, double prefactor,
+                             double tol, int max_iter, Tio *lin, Tio *ang, int64_t ostride, int *iters_out,
+                             double *incr_out, hipStream_t st, bool accumulate);
 
 }  // namespace rpy
 

@@ -88,6 +88,33 @@ class Solver:
         _lib.rpy_mdot(self._h, f, t, lin, ang, self._dtype, self._n)
         return lin, ang
 
+    def MdotMulti(self, forces: torch.Tensor | None = None, torques: torch.Tensor | None = None):
+        """Mdot for several vectors at the stored positions: forces / torques
+        of shape (nrhs, N, 3); returns outputs of the same shape (angular
+        None without includeAngular).  Each vector's result equals Mdot's."""
+        self._require_positions()
+        ref = forces if forces is not None else torques
+        if ref is None:
+            _lib.rpy_mdot_multi(self._h, None, None, 1, self._empty(), None, self._dtype, self._n)
+        nrhs = ref.numel() // (3 * self._n) if ref.numel() % (3 * self._n) == 0 else -1
+        if nrhs < 1:
+            raise ValueError(f"vectors must have shape (nrhs, {self._n}, 3)")
+        f = self._as_multi(forces, "forces", nrhs)
+        t = self._as_multi(torques, "torques", nrhs)
+        lin = torch.empty((nrhs, self._n, 3), dtype=self._dtype, device=self._device)
+        ang = torch.empty_like(lin) if self._angular else None
+        _lib.rpy_mdot_multi(self._h, f, t, nrhs, lin, ang, self._dtype, self._n)
+        return lin, ang
+
+    def _as_multi(self, t, name, nrhs):
+        if t is None:
+            return None
+        if t.numel() != 3 * self._n * nrhs:
+            raise ValueError(f"{name} must have shape ({nrhs}, {self._n}, 3)")
+        if t.dtype != self._dtype:
+            raise ValueError(f"DTYPE_MISMATCH: {name} is {t.dtype}, positions are {self._dtype}")
+        return t.reshape(nrhs, self._n, 3).contiguous()
+
     def sqrtMdotW(self, W: torch.Tensor | None = None, prefactor: float = 1.0,
                   tol: float = 1e-6, maxIter: int = 500, generator: torch.Generator | None = None):
         """prefactor * M^{1/2} W by Lanczos; W ~ N(0, I) is drawn when not given."""
@@ -103,6 +130,27 @@ class Solver:
         ang = self._empty() if self._angular else None
         it, inc = _lib.rpy_sqrt_mdot_w(self._h, w, prefactor, tol, maxIter, lin, ang, self._dtype,
                                        self._n, self._angular)
+        self.last_iterations, self.last_increment = it, inc
+        return lin, ang
+
+    def sqrtMdotWMulti(self, W: torch.Tensor, prefactor: float = 1.0, tol: float = 1e-6, maxIter: int = 500):
+        """prefactor * M^{1/2} W_r for the rows of W (shape (nrhs, 3N), or
+        (nrhs, 6N) with angular terms), one Lanczos recurrence per row
+        advanced together; each row's result and iteration count equal
+        sqrtMdotW's.  Returns outputs of shape (nrhs, N, 3);
+        last_iterations becomes the list of iteration counts."""
+        self._require_positions()
+        dim = (6 if self._angular else 3) * self._n
+        if W.numel() % dim != 0 or W.numel() == 0:
+            raise ValueError(f"W must have shape (nrhs, {dim})")
+        if W.dtype != self._dtype:
+            raise ValueError(f"DTYPE_MISMATCH: W is {W.dtype}, positions are {self._dtype}")
+        nrhs = W.numel() // dim
+        w = W.reshape(nrhs, dim).contiguous()
+        lin = torch.empty((nrhs, self._n, 3), dtype=self._dtype, device=self._device)
+        ang = torch.empty_like(lin) if self._angular else None
+        it, inc = _lib.rpy_sqrt_mdot_w_multi(self._h, w, nrhs, prefactor, tol, maxIter, lin, ang, self._dtype,
+                                             self._n, self._angular)
         self.last_iterations, self.last_increment = it, inc
         return lin, ang
 
@@ -181,6 +229,10 @@ class Solver:
 
     def setTileConfig(self, angular: bool, targets_per_lane: int, source_splits: int = 0):
         _lib.rpy_set_tile_config(self._h, angular, targets_per_lane, source_splits)
+
+    def setMultiConfig(self, targets_per_lane: int):
+        """Targets per lane (0 = automatic, 1 or 2) of the multi-vector pair kernel."""
+        _lib.rpy_set_multi_config(self._h, targets_per_lane)
 
     def close(self):
         if getattr(self, "_h", None):

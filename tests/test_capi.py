@@ -84,14 +84,20 @@ def test_parameter_and_initialize_checks(lib):
 def test_call_order_checks(lib):
     h = _solver(lib)
     buf = ctypes.c_void_p(16)   # never dereferenced: every call below fails validation first
+    lib.rpy_mdot_multi.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     try:
         assert lib.rpy_set_positions(h, buf, 4, 0, None) == NOT_INIT
         assert lib.rpy_mdot(h, buf, None, buf, None, None) == NOT_INIT
+        assert lib.rpy_mdot_multi(h, buf, None, 2, buf, None, None) == NOT_INIT
         assert lib.rpy_initialize(h, 1.0, 1.0, 0) == OK
         assert lib.rpy_mdot(h, buf, None, buf, None, None) == NO_POS
         assert lib.rpy_div_m(h, buf, None, None) == NO_POS
         assert lib.rpy_mdot_backward(h, buf, None, buf, None, buf, None, None, None) == NO_POS
         assert lib.rpy_sqrt_mdot_w(h, buf, 1.0, 1e-6, 10, buf, None, None, None, None) == NO_POS
+        assert lib.rpy_mdot_multi(h, buf, None, 2, buf, None, None) == NO_POS
+        assert lib.rpy_set_multi_config(h, 3) == INVALID and lib.rpy_set_multi_config(h, -1) == INVALID
+        assert lib.rpy_set_multi_config(h, 2) == OK
         assert lib.rpy_set_positions(h, None, 4, 0, None) == INVALID
         assert lib.rpy_set_positions(h, buf, 0, 0, None) == INVALID
         assert lib.rpy_set_positions(h, buf, -3, 1, None) == INVALID
@@ -122,17 +128,18 @@ def test_tile_config_accessors(lib):
 
 
 def test_timing_accessors(lib):
-    """Instrumentation classes 0..2 (pair, adjoint, Lanczos Gram-Schmidt)
-    report nothing before any launch; other classes are rejected."""
+    """Instrumentation classes 0..3 (pair, adjoint, Lanczos Gram-Schmidt,
+    multi-vector pair) report nothing before any launch; other classes are
+    rejected."""
     h = _solver(lib)
     lib.rpy_kernel_time.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
     assert lib.rpy_enable_timing(h, 1) == OK
-    for kind in (0, 1, 2):
+    for kind in (0, 1, 2, 3):
         ms, n, work = ctypes.c_double(-1), ctypes.c_int64(-1), ctypes.c_double(-1)
         assert lib.rpy_kernel_time(h, kind, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(work)) == OK
         assert (ms.value, n.value, work.value) == (0.0, 0, 0.0)
-    for kind in (-1, 3):
+    for kind in (-1, 4):
         assert lib.rpy_kernel_time(h, kind, None, None, None) == INVALID
     assert lib.rpy_enable_timing(h, 0) == OK
     lib.rpy_destroy(h)

@@ -85,7 +85,7 @@ def test_lanczos_stopping_iteration_against_oracle(monkeypatch, angular, tol):
         e = float(np.abs(y - y_ref).max() / np.abs(y_ref).max())
         say(f"  oracle stops at {info.iters}, {mode} schedule at {sol.last_iterations}, max rel {e:.3e}")
         assert sol.last_iterations == info.iters
-        assert e <= (1e-7 if case == "coincident" else 1e-12)
+        assert e <= 1e-12
 
 
 def test_lanczos_zero_noise_and_not_converged():
