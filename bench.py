@@ -23,7 +23,9 @@ Gram-Schmidt passes, timed the same way, algorithmic bytes), the max
 relative error of each result against the float64 CPU oracle on sampled
 particles, the oracle's own rate on a bounded sample of the same workload on
 the host cores, the 512-system batch (one persistent launch vs one launch
-per system) and one angular product of 4096 bead chains x 256 beads.
+per system), one angular product of 4096 bead chains x 256 beads, and the
+multi-vector calls (eight force sets in one product; four noise vectors in
+one lockstep Lanczos) against one call per vector.
 """
 from __future__ import annotations
 
@@ -332,6 +334,45 @@ def main():
                             gp.double().cpu().numpy(), gf.double().cpu().numpy())
             so.close()
 
+    # ---- several vectors at one geometry (float32, 8 force sets; 4 noise
+    # vectors) against one call per vector --------------------------------
+    multi = None
+    if not args.no_breakdown:
+        print("bench: multi-vector products", file=sys.stderr, flush=True)
+        multi = {"nrhs_mdot": 8, "nrhs_sqrt": 4}
+        rng = np.random.default_rng(1006)
+        Xd = dev_t(s.pos, torch.float32)
+        for ang in (False, True):
+            so = rpy.Solver()
+            so.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius, includeAngular=ang)
+            so.setPositions(Xd)
+            so.autotune(args.tile_cache)
+            Fm = dev_t(rng.standard_normal((8, n, 3)), torch.float32)
+            Tm = dev_t(rng.standard_normal((8, n, 3)), torch.float32) if ang else None
+            tm = timed(lambda: so.MdotMulti(Fm, Tm), 5, stream, warmup=2) / 8
+            single = breakdown["fp32_" + ("angular" if ang else "linear")]["mdot_ms"]
+            key = "angular" if ang else "linear"
+            multi[f"mdot_{key}_ms_per_vector"] = round(tm, 4)
+            multi[f"mdot_{key}_pair_vectors_per_s"] = float(n) * n / (tm * 1e-3)
+            multi[f"mdot_{key}_speedup_vs_single"] = round(single / tm, 3)
+            if ang:
+                Wm = dev_t(rng.standard_normal((4, 6 * n)), torch.float32)
+                t0 = time.perf_counter()
+                its_single = []
+                for r in range(4):
+                    so.sqrtMdotW(Wm[r], tol=1e-6)
+                    its_single.append(so.last_iterations)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                so.sqrtMdotWMulti(Wm, tol=1e-6)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                multi.update({"sqrt_angular_singles_ms": round(1e3 * (t1 - t0), 1),
+                              "sqrt_angular_multi_ms": round(1e3 * (t2 - t1), 1),
+                              "sqrt_iterations": so.last_iterations, "sqrt_iterations_single": its_single})
+            so.close()
+            del Fm, Tm
+
     # ---- bead chains, N = 1,048,576: one angular float32 product ----------
     chains = None
     if not args.no_batch:
@@ -449,6 +490,7 @@ def main():
         "accuracy_vs_fp64_oracle": acc,
         "batched": batched,
         "chains": chains,
+        "multi_vector": multi,
         "tiles": {"linear": tiles[0], "angular": tiles[1]},
         "adjoint_kernel_avg_ms": round(adj_ms / max(adj_launches, 1), 4),
     }
