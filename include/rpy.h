@@ -125,8 +125,10 @@ rpy_status rpy_mdot(rpy_solver *s, const void *forces, const void *torques,
  * may be NULL (zero), not both; torques or ang_out need include_angular.
  * 1 <= nrhs <= 1024 and nrhs * n < 2^31.  The pair geometry (separation,
  * 1/r, the tensor coefficients) is evaluated once per pair for up to four
- * vectors, and every vector's result is bit-identical to rpy_mdot of that
- * vector with the same tile configuration.  Asynchronous.
+ * vectors.  With the same tile configuration, translational results are
+ * bit-identical to rpy_mdot of each vector; with the angular blocks the
+ * pair is evaluated in a form that is cheaper per vector, and results agree
+ * with rpy_mdot's to rounding.  Asynchronous.
  */
 rpy_status rpy_mdot_multi(rpy_solver *s, const void *forces, const void *torques, int nrhs,
                           void *lin_out, void *ang_out, void *hip_stream);
@@ -165,9 +167,11 @@ rpy_status rpy_sqrt_mdot_w(rpy_solver *s, const void *w, double prefactor, doubl
  * iteration applying M to all unconverged recurrences in one multi-vector
  * product (rpy_mdot_multi).  w holds nrhs consecutive vectors of 3N (6N with
  * include_angular) entries; lin_out / ang_out hold nrhs consecutive n x 3
- * arrays.  Each recurrence stops at the iteration, and with the result,
- * that rpy_sqrt_mdot_w gives for its vector alone (bit-identical with the
- * same tile configuration).  iters_out and incr_out (host, nrhs entries,
+ * arrays.  Each recurrence runs rpy_sqrt_mdot_w's iteration and stopping
+ * rule: without include_angular it reproduces rpy_sqrt_mdot_w of its vector
+ * bit for bit (same tile configuration); with it the products agree to
+ * rounding, and so do the results (the stopping iteration can differ only
+ * where an increment lies within rounding of tol).  iters_out and incr_out (host, nrhs entries,
  * may be NULL) receive each recurrence's iteration count and last relative
  * increment.  1 <= nrhs <= 1024 and nrhs * n < 2^31; the float64 workspace
  * holds nrhs bases of min(max_iter, 1024) + 1 vectors.  Synchronises

@@ -296,8 +296,9 @@ rpy_status lanczos_products(rpy_solver *s, const std::vector<LzRec *> &act, int6
 // advanced in lockstep: each iteration applies M to the current basis
 // vector of every recurrence still running (one multi-vector product), then
 // runs each recurrence's vector operations and stopping test exactly as for
-// a single vector, so every recurrence stops at the iteration, and with the
-// result, that it would reach alone (the products are bit-identical).
+// a single vector.  Translational products are bit-identical to single ones,
+// so each recurrence then reproduces its single call exactly; angular
+// products agree to rounding.
 // W_r at w_in + r * wstride; outputs at lin / ang + r * ostride.
 template <typename Tio>
 rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t wstride, double prefactor,

@@ -4,21 +4,21 @@
 // sets at the same positions.  Everything about a pair that does not depend
 // on the vectors (separation, 1/r, the coefficient functions, the overlap
 // branch) is computed once and applied to NV vectors, so the rsqrt and the
-// geometry are shared: about 12 of the 48 instructions of an angular pair
-// and 12 of the 23 of a translational one.
+// geometry are shared.
 //
 // Work decomposition (as the single-vector pair kernel, one grid dimension
 // more)
 //   grid.x : target blocks of 256*TM targets (TM per lane, strided by 256);
-//   grid.y : source splits;
+//   grid.y : source splits (those of the single-vector product);
 //   grid.z : groups of NV vectors.
-//   A tile stages up to 256 source positions and, per vector, the records of
-//   the regrouped angular pair (F, T, T~ = -T/2 and F' = (2a^2/3) F spread
-//   over the three .w slots) or the forces alone.
-// The per-vector arithmetic, the order of the sum over sources and the
-// Neumaier folding after every tile of 256 sources are those of the
-// single-vector kernel, so with equal source splits every vector's result is
-// bit-identical to a single product of that vector.
+//   A tile stages up to 256 source positions and, per vector, the force (and
+//   torque) records.
+// The order of the sum over sources and the Neumaier folding after every 256
+// sources are those of the single-vector kernel.  The translational pair
+// arithmetic is too, so translational results are bit-identical to single
+// products of the same vectors; the angular pair uses a form that is
+// cheaper per vector (ang_apply), so angular results agree with single
+// products to rounding.
 #include "rpy_device.hpp"
 #include "rpy_internal.hpp"
 #include "rpy_solver_ops.hpp"
@@ -45,17 +45,22 @@ constexpr int tile_sources() {
 // ---------------------------------------------------------------------------
 // pair geometry and its application to one vector
 // ---------------------------------------------------------------------------
+// The angular pair in the direct form of the blocks, with the separation
+// prescaled by G (e = G d) so that the coupling terms G (T x d) and
+// G (F x d) are plain cross products with e:
+//   U += A F + B (d.F) d + T x e,   W += D T + E (d.T) d + F x e.
+// Per vector that is 32 instructions (two dot products, two scalings, four
+// multiply-adds per output component) against 35 for the regrouped form of
+// the single-vector kernel, whose savings are per pair (the coefficients
+// B, D, E, A and e cost 6 more per pair here); from two vectors on, this form
+// is the cheaper one.  The overlap branch only changes the coefficients.
 template <typename Real>
 struct AngGeom {
-    Real dx, dy, dz;
-    Real a1, g;    // U += a1 F + g (F' + s1 d + T x d),  W += g (T~ + s2 d + F x d)
-    Real f1, f2;   // s1 = f1 (d.F), s2 = f2 (d.T)
-    Real dd;       // overlap branch: W += dd T
+    Real dx, dy, dz;   // d = X_i - X_j
+    Real ex, ey, ez;   // e = G d
+    Real A, B, D, E;
 };
 
-// Coefficients as in interact_ang: far field a1 = 1/r, g = 1/r^3,
-// f1 = 1 - 2a^2/r^2, f2 = 3/(2r^2); overlap branch a1 = A - (2a^2/3) G,
-// f1 = B/G, f2 = E/G, g = G, dd = D + G/2.
 template <typename Real>
 __device__ __forceinline__ AngGeom<Real> ang_geom(Real xi, Real yi, Real zi, const vec4_t<Real> &p,
                                                   const PairConst<Real> &c) {
@@ -66,53 +71,44 @@ __device__ __forceinline__ AngGeom<Real> ang_geom(Real xi, Real yi, Real zi, con
     const Real r2 = fma(q.dx, q.dx, fma(q.dy, q.dy, q.dz * q.dz));
     const Real ri = rsq(r2);
     const Real ri2 = ri * ri;
-    q.g = ri * ri2;
-    q.a1 = ri;
-    q.f1 = fma(c.m_two_a2, ri2, Real(1));
-    q.f2 = Real(1.5) * ri2;
-    q.dd = Real(0);
+    Real G = ri * ri2;
+    const Real ri5 = G * ri2;
+    q.A = fma(c.two_a2_3, G, ri);
+    q.B = fma(c.m_two_a2, ri5, G);
+    q.D = Real(-0.5) * G;
+    q.E = Real(1.5) * ri5;
     if (__builtin_expect(r2 < c.four_a2, 0)) {
+        // overlap branch; at r = 0 (self pair) it gives the Stokes drag
         const Real rs = sel_pos(r2, ri);
         const Real r = r2 * rs;
-        const Real An = fma(c.nA1, r, c.nA0);
-        const Real Bn = c.nB * rs;
-        const Real Gn = fma(c.nG1, r, c.nG0);
-        const Real Dn = fma(fma(c.nD3, r * r, c.nD1), r, c.nD0);
-        const Real En = fma(c.nE_1, rs, c.nE1 * r);
-        const Real inv = Real(1) / Gn;
-        q.a1 = fma(-c.two_a2_3, Gn, An);
-        q.f1 = Bn * inv;
-        q.f2 = En * inv;
-        q.g = Gn;
-        q.dd = fma(Real(0.5), Gn, Dn);
+        q.A = fma(c.nA1, r, c.nA0);
+        q.B = c.nB * rs;
+        G = fma(c.nG1, r, c.nG0);
+        q.D = fma(fma(c.nD3, r * r, c.nD1), r, c.nD0);
+        q.E = fma(c.nE_1, rs, c.nE1 * r);
     }
+    q.ex = G * q.dx;
+    q.ey = G * q.dy;
+    q.ez = G * q.dz;
     return q;
 }
 
-// Records of one vector: f = (F, F'y), t = (T, F'z), h = (T~, F'x).  The
-// overlap branch's W += dd T is added by the caller before this (dd = 0
-// without overlap, where that addition is exact): a branch or select per
-// vector would cost more than the three multiply-adds.
+// One vector's force f and torque t (the .w slots unused).
 template <typename Real>
 __device__ __forceinline__ void ang_apply(const AngGeom<Real> &q, const vec4_t<Real> &f, const vec4_t<Real> &t,
-                                          const vec4_t<Real> &h, Real *u, Real *w) {
-    const Real dx = q.dx, dy = q.dy, dz = q.dz;
-    const Real dF = fma(dx, f.x, fma(dy, f.y, dz * f.z));
-    const Real dT = fma(dx, t.x, fma(dy, t.y, dz * t.z));
-    const Real s1 = q.f1 * dF;
-    const Real s2 = q.f2 * dT;
-    const Real vux = fma(-t.z, dy, fma(t.y, dz, fma(s1, dx, h.w)));
-    const Real vuy = fma(-t.x, dz, fma(t.z, dx, fma(s1, dy, f.w)));
-    const Real vuz = fma(-t.y, dx, fma(t.x, dy, fma(s1, dz, t.w)));
-    u[0] = fma(q.a1, f.x, fma(q.g, vux, u[0]));
-    u[1] = fma(q.a1, f.y, fma(q.g, vuy, u[1]));
-    u[2] = fma(q.a1, f.z, fma(q.g, vuz, u[2]));
-    const Real vwx = fma(-f.z, dy, fma(f.y, dz, fma(s2, dx, h.x)));
-    const Real vwy = fma(-f.x, dz, fma(f.z, dx, fma(s2, dy, h.y)));
-    const Real vwz = fma(-f.y, dx, fma(f.x, dy, fma(s2, dz, h.z)));
-    w[0] = fma(q.g, vwx, w[0]);
-    w[1] = fma(q.g, vwy, w[1]);
-    w[2] = fma(q.g, vwz, w[2]);
+                                          Real *u, Real *w) {
+    const Real dF = fma(q.dx, f.x, fma(q.dy, f.y, q.dz * f.z));
+    const Real dT = fma(q.dx, t.x, fma(q.dy, t.y, q.dz * t.z));
+    const Real sB = q.B * dF;
+    const Real sE = q.E * dT;
+    // U += A F + B (d.F) d + T x e
+    u[0] = fma(q.A, f.x, fma(sB, q.dx, fma(t.y, q.ez, fma(-t.z, q.ey, u[0]))));
+    u[1] = fma(q.A, f.y, fma(sB, q.dy, fma(t.z, q.ex, fma(-t.x, q.ez, u[1]))));
+    u[2] = fma(q.A, f.z, fma(sB, q.dz, fma(t.x, q.ey, fma(-t.y, q.ex, u[2]))));
+    // W += D T + E (d.T) d + F x e
+    w[0] = fma(q.D, t.x, fma(sE, q.dx, fma(f.y, q.ez, fma(-f.z, q.ey, w[0]))));
+    w[1] = fma(q.D, t.y, fma(sE, q.dy, fma(f.z, q.ex, fma(-f.x, q.ez, w[1]))));
+    w[2] = fma(q.D, t.z, fma(sE, q.dz, fma(f.x, q.ey, fma(-f.y, q.ex, w[2]))));
 }
 
 template <typename Real>
@@ -165,7 +161,7 @@ multi_pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__re
     using R4 = vec4_t<Real>;
     constexpr int NC = ANG ? 6 : 3;
     constexpr bool COMP = std::is_same<Real, float>::value;
-    constexpr int NR = ANG ? 3 : 1;          // records per vector and source
+    constexpr int NR = ANG ? 2 : 1;          // records per vector and source (F, T or F)
     constexpr int TS = tile_sources<Real, NV, NR>();
     static_assert(kFold % TS == 0, "fold points must fall on tile ends");
     __shared__ R4 sp[TS];
@@ -205,20 +201,8 @@ multi_pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__re
             sp[tid] = pos[src];
 #pragma unroll
             for (int j = 0; j < NV; ++j) {
-                R4 f = frc[(size_t)(vb + j) * nn + src];
-                if constexpr (ANG) {
-                    R4 t = trq[(size_t)(vb + j) * nn + src];
-                    R4 h;
-                    h.x = Real(-0.5) * t.x;
-                    h.y = Real(-0.5) * t.y;
-                    h.z = Real(-0.5) * t.z;
-                    h.w = c.two_a2_3 * f.x;
-                    f.w = c.two_a2_3 * f.y;
-                    t.w = c.two_a2_3 * f.z;
-                    sv[j][1][tid] = t;
-                    sv[j][2][tid] = h;
-                }
-                sv[j][0][tid] = f;
+                sv[j][0][tid] = frc[(size_t)(vb + j) * nn + src];
+                if constexpr (ANG) sv[j][1][tid] = trq[(size_t)(vb + j) * nn + src];
             }
         }
         __syncthreads();
@@ -231,16 +215,9 @@ multi_pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__re
                 for (int m = 0; m < TM; ++m) g[m] = ang_geom<Real>(xi[m], yi[m], zi[m], p, c);
 #pragma unroll
                 for (int j = 0; j < NV; ++j) {
-                    const R4 f = sv[j][0][q], t = sv[j][1][q], h = sv[j][2][q];
+                    const R4 f = sv[j][0][q], t = sv[j][1][q];
 #pragma unroll
-                    for (int m = 0; m < TM; ++m) {
-                        // W += dd T first, as interact_ang orders the terms
-                        // (exact no-op where dd = 0: no overlap)
-                        acc[m][j][3] = fma(g[m].dd, t.x, acc[m][j][3]);
-                        acc[m][j][4] = fma(g[m].dd, t.y, acc[m][j][4]);
-                        acc[m][j][5] = fma(g[m].dd, t.z, acc[m][j][5]);
-                        ang_apply<Real>(g[m], f, t, h, acc[m][j], acc[m][j] + 3);
-                    }
+                    for (int m = 0; m < TM; ++m) ang_apply<Real>(g[m], f, t, acc[m][j], acc[m][j] + 3);
                 }
             } else {
                 LinGeom<Real> g[TM];
@@ -421,9 +398,8 @@ int multi_targets_per_lane(const rpy_solver *s, bool ang) {
 }
 
 // nrhs products M [F_r; T_r] with the vectors already staged in s->f (and
-// s->t) as [vector][n] vec4 arrays.  The source splits are those of the
-// single-vector product, so every vector's result matches rpy_mdot's bit
-// for bit.
+// s->t) as [vector][n] vec4 arrays, with the source splits of the
+// single-vector product.
 template <typename Real, typename Tout>
 rpy_status apply_staged_multi(rpy_solver *s, bool ang, int nrhs, Tout *lin, Tout *ang_out, int64_t ostride,
                               hipStream_t st) {

@@ -91,7 +91,8 @@ class Solver:
     def MdotMulti(self, forces: torch.Tensor | None = None, torques: torch.Tensor | None = None):
         """Mdot for several vectors at the stored positions: forces / torques
         of shape (nrhs, N, 3); returns outputs of the same shape (angular
-        None without includeAngular).  Each vector's result equals Mdot's."""
+        None without includeAngular).  Each vector's result equals Mdot's
+        (bit for bit without angular terms, to rounding with them)."""
         self._require_positions()
         ref = forces if forces is not None else torques
         if ref is None:
@@ -137,7 +138,8 @@ class Solver:
         """prefactor * M^{1/2} W_r for the rows of W (shape (nrhs, 3N), or
         (nrhs, 6N) with angular terms), one Lanczos recurrence per row
         advanced together; each row's result and iteration count equal
-        sqrtMdotW's.  Returns outputs of shape (nrhs, N, 3);
+        sqrtMdotW's (exactly without angular terms, to rounding with them).
+        Returns outputs of shape (nrhs, N, 3);
         last_iterations becomes the list of iteration counts."""
         self._require_positions()
         dim = (6 if self._angular else 3) * self._n

@@ -1,16 +1,21 @@
-"""GPU parity of the multi-vector product rpy_mdot_multi (several force /
-torque sets at one geometry) through the C interface:
+"""GPU parity of the multi-vector calls (several force / torque sets, or
+several noise vectors, at one geometry) through the C interface:
 
-* against the float64 oracle for every vector (bars 1e-12 / 1e-5 in e_max,
-  float32 runs against the oracle on float32-rounded inputs), at sizes that
-  span several tiles with ragged tails and vector counts that leave every
-  remainder of the groups of four;
-* bit-identical to rpy_mdot of each vector with the same tile configuration
-  (the arithmetic, the order of the source sum and the fold points are the
-  single-vector kernel's), for both targets-per-lane settings and several
-  single-vector tile configurations;
-* at the full 65,536-sphere suspension, bit-identity with rpy_mdot (whose
-  full-size parity is tested on sampled rows) and sampled oracle rows.
+* rpy_mdot_multi against the float64 oracle for every vector (bars 1e-12 /
+  1e-5 in e_max, float32 runs against the oracle on float32-rounded
+  inputs), at sizes that span several tiles with ragged tails and vector
+  counts that leave every remainder of the groups of four;
+* against rpy_mdot of each vector with the same tile configuration:
+  translational results bit-identical (same pair arithmetic, source order
+  and fold points), angular ones within rounding (the multi-vector kernel
+  evaluates the angular pair in another algebraic form): e_max <= 1e-13 in
+  float64 and 2e-6 in float32;
+* at the full 65,536-sphere suspension, agreement with rpy_mdot and sampled
+  oracle rows;
+* rpy_sqrt_mdot_w_multi against single rpy_sqrt_mdot_w calls (iteration
+  counts equal; results bit-identical without angular terms, within the
+  parity bars with them) and against the oracle's Lanczos at matched
+  iterations and the exact root.
 """
 import math
 
@@ -63,10 +68,17 @@ def test_multi_against_oracle(dtype, angular, n, nrhs):
     assert e <= tol_for(dtype)
 
 
+def _same(got, ref, dtype, angular):
+    """Bitwise for translational products; rounding-level e_max otherwise."""
+    if not angular:
+        return torch.equal(got, ref)
+    return emax(host(got), host(ref)) <= (1e-13 if dtype == torch.float64 else 2e-6)
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("angular", [False, True])
-def test_multi_bit_identical_to_single_products(dtype, angular):
-    say(f"case multi vs single bitwise angular={angular} {dtype}")
+def test_multi_matches_single_products(dtype, angular):
+    say(f"case multi vs single products angular={angular} {dtype}")
     rng = np.random.default_rng(41)
     n, nrhs = 2300, 6
     x = (rng.random((n, 3)) - 0.5) * workloads.cube_side(n, 0.3)
@@ -81,10 +93,11 @@ def test_multi_bit_identical_to_single_products(dtype, angular):
             sol.setMultiConfig(mtm)
             lin, ang = sol.MdotMulti(Fd, Td)
             for r in range(nrhs):
-                assert torch.equal(lin[r], singles[r][0]), (tm, splits, mtm, r)
+                assert _same(lin[r], singles[r][0], dtype, angular), (tm, splits, mtm, r)
                 if angular:
-                    assert torch.equal(ang[r], singles[r][1]), (tm, splits, mtm, r)
-    say("  identical for 4 tile configurations x 2 targets-per-lane settings")
+                    assert _same(ang[r], singles[r][1], dtype, angular), (tm, splits, mtm, r)
+    sol.setMultiConfig(0)
+    say(f"  {'identical' if not angular else 'within rounding'} for 4 tile configurations x 2 targets-per-lane settings")
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -129,8 +142,8 @@ def test_multi_argument_checks():
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_multi_full_size_suspension(dtype):
     """N = 65,536 (the suspension of the headline product), six vectors with
-    angular blocks: every vector equals the single product bit for bit, and
-    64 sampled rows of two vectors match the oracle."""
+    angular blocks: every vector agrees with the single product to rounding,
+    and 64 sampled rows of two vectors match the oracle."""
     say(f"case multi full size N=65536 nrhs=6 angular {dtype}")
     s = workloads.c2_suspension()
     n, nrhs = s.n, 6
@@ -142,14 +155,14 @@ def test_multi_full_size_suspension(dtype):
     lin, ang = sol.MdotMulti(Fd, Td)
     for r in range(nrhs):
         l1, a1 = sol.Mdot(Fd[r], Td[r])
-        assert torch.equal(lin[r], l1) and torch.equal(ang[r], a1), r
+        assert _same(lin[r], l1, dtype, True) and _same(ang[r], a1, dtype, True), r
     rows = np.sort(rng.choice(n, 64, replace=False))
     xr = rounded(s.pos, dtype)
     e = 0.0
     for r in (0, nrhs - 1):
         u, w = pairloop.mdot_rows(xr, rows, rounded(F[r], dtype), rounded(T[r], dtype), s.radius, s.viscosity)
         e = max(e, emax(host(lin[r])[rows], u), emax(host(ang[r])[rows], w))
-    say(f"  bit-identical to single products; sampled e_max {e:.3e}")
+    say(f"  agrees with single products; sampled e_max {e:.3e}")
     assert e <= tol_for(dtype)
 
 
@@ -185,9 +198,13 @@ def test_sqrt_multi_equals_single_calls(dtype, angular):
     for r in range(W.shape[0]):
         l1, a1 = sol.sqrtMdotW(Wd[r], prefactor=0.7, tol=1e-6)
         singles.append(sol.last_iterations)
-        assert torch.equal(lin[r], l1), r
-        if angular:
-            assert torch.equal(ang[r], a1), r
+        if angular and l1.any():
+            bar = 1e-12 if dtype == torch.float64 else 1e-5
+            assert emax(host(lin[r]), host(l1)) <= bar and emax(host(ang[r]), host(a1)) <= bar, r
+        elif angular:
+            assert not lin[r].any() and not ang[r].any(), r
+        else:
+            assert torch.equal(lin[r], l1), r
     say(f"  iterations {its} (single calls {singles})")
     assert its == singles
     assert its[1] == 0 and not lin[1].any()
