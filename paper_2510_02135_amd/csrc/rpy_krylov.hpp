@@ -219,6 +219,17 @@ __device__ __noinline__ void tridiag_sqrt_block(const double *__restrict__ alpha
 // workgroup; `scratch` holds kk * kMonNodes doubles.
 constexpr int kMonNodes = 128;
 constexpr int kMonThreads = kMonNodes + 64;
+constexpr int kMonChunk = 16;  // scratch rows fetched together in the forward pass
+
+// 1/x from the hardware estimate and two Newton steps y <- y + y (1 - x y)
+// (within an ulp or two; the serial recurrences below run on its latency).
+__device__ __forceinline__ double recip(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
 
 __device__ __noinline__ void monitor_block(const double *__restrict__ alpha, const double *__restrict__ beta, int k,
                                            int kk, double *__restrict__ scratch, double *__restrict__ est) {
@@ -245,11 +256,18 @@ __device__ __noinline__ void monitor_block(const double *__restrict__ alpha, con
     if (!(bound > 0.0)) bound = 1.0;
     if (tid >= kMonNodes) {
         if (tid == kMonNodes) {
+            // only the pivots' signs matter: reciprocal instead of division
             const double shift = 1e-10 * bound;
             double piv = a[0] - shift;
             bool pd = piv > 0.0;
+            double bn = kk > 1 ? b[0] : 0.0, an = kk > 1 ? a[1] : 0.0;
             for (int i = 1; i < kk && pd; ++i) {
-                piv = a[i] - shift - b[i - 1] * (b[i - 1] / piv);
+                const double bi = bn, ai = an;
+                if (i + 1 < kk) {   // next row's operands, loaded ahead of the chain
+                    bn = b[i];
+                    an = a[i + 1];
+                }
+                piv = (ai - shift) - bi * (bi * recip(piv));
                 pd = piv > 0.0;
             }
             if (!pd) indefinite = 1;
@@ -261,13 +279,32 @@ __device__ __noinline__ void monitor_block(const double *__restrict__ alpha, con
         const double ul = u_lo + h * l;
         const double c = exp(ul), wl = h / M_PI * exp(0.5 * ul);
         double gp = a[kk - 1] + c;
+        double bn = kk > 1 ? b[kk - 2] : 0.0, an = kk > 1 ? a[kk - 2] : 0.0;
         for (int i = kk - 2; i >= 0; --i) {
-            const double r = -b[i] / gp;
+            const double bi = bn, ai = an;
+            if (i > 0) {   // next row's operands, loaded ahead of the chain
+                bn = b[i - 1];
+                an = a[i - 1];
+            }
+            const double r = -bi * recip(gp);
             scratch[(size_t)i * kMonNodes + l] = r;
-            gp = fma(b[i], r, a[i] + c);
+            gp = fma(bi, r, ai + c);
         }
-        double y = 1.0 / gp;
-        for (int i = 0; i + 1 < kk; ++i) {   // w_l y_i replaces r_i
+        double y = recip(gp);
+        // w_l y_i replaces r_i; the ratios of kMonChunk rows are fetched
+        // together so that the product chain waits once per chunk
+        int i = 0;
+        for (; i + kMonChunk < kk; i += kMonChunk) {
+            double rr[kMonChunk];
+#pragma unroll
+            for (int u = 0; u < kMonChunk; ++u) rr[u] = scratch[(size_t)(i + u) * kMonNodes + l];
+#pragma unroll
+            for (int u = 0; u < kMonChunk; ++u) {
+                scratch[(size_t)(i + u) * kMonNodes + l] = wl * y;
+                y *= rr[u];
+            }
+        }
+        for (; i + 1 < kk; ++i) {
             const double r = scratch[(size_t)i * kMonNodes + l];
             scratch[(size_t)i * kMonNodes + l] = wl * y;
             y *= r;
