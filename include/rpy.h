@@ -184,6 +184,29 @@ rpy_status rpy_sqrt_mdot_w_multi(rpy_solver *s, const void *w, int nrhs, double 
                                  double *incr_out, void *hip_stream);
 
 /*
+ * Mobility solve by conjugate gradients (an addition beside the paper's
+ * method: a Krylov consumer of the product): for r = 0 .. nrhs-1 finds
+ * [F_r; T_r] with M [F_r; T_r] = [U_r; Omega_r], the forces (and torques)
+ * that give prescribed linear (and angular) velocities at the stored
+ * positions.  u_lin / f_out (and, with include_angular, u_ang / t_out, both
+ * required then) hold nrhs consecutive n x 3 arrays in the solver's dtype.
+ * The iteration runs in float64 on the device, one multi-vector product per
+ * iteration for the right-hand sides not yet converged; each stops at the
+ * first iteration whose recursive residual |b - M x| / |b| is below tol
+ * (0 < tol < 1; float32 products limit the attainable residual to about
+ * 1e-6 times the condition number).  A zero right-hand side gives zero.
+ * iters_out and resid_out (host, nrhs entries, may be NULL) receive the
+ * iteration count and the final relative residual.  1 <= nrhs <= 1024,
+ * nrhs * n < 2^31, max_iter >= 1.  Synchronises hip_stream.  Returns
+ * RPY_ERR_NOT_CONVERGED (last iterates written) if any right-hand side
+ * reached max_iter, RPY_ERR_NOT_SPD if a search direction with
+ * p^T M p <= 0 appeared, RPY_ERR_NONFINITE for a non-finite right-hand side.
+ */
+rpy_status rpy_mobility_solve(rpy_solver *s, const void *u_lin, const void *u_ang, int nrhs, double tol,
+                              int max_iter, void *f_out, void *t_out, int *iters_out, double *resid_out,
+                              void *hip_stream);
+
+/*
  * Thermal drift d_X . M (Sec. 3.2, divM; third term of eq. (bdhi)).  In an
  * unbounded fluid M is translation invariant and isotropic, so the
  * divergence vanishes (Sec. 2, Sec. 3.4): writes zeros to lin_out (n x 3)

@@ -22,4 +22,9 @@ What it computes (paper section in brackets):
   differentiation of ``mobility``).
 * ``drift``     - thermal drift: zero in open space [Sec. 2, Sec. 3.4], and
   the deterministic and random finite-difference divergences of Sec. 4.
+* ``integrators`` - the Euler-Maruyama velocities and the stochastic
+  Adams-Bashforth step of eq. (bdhi) [Sec. 3.2, Sec. 5.1].
+* ``krylov``    - conjugate gradients on M (a Krylov consumer of the product,
+  an addition beside the paper's method), pinned against a direct solve and
+  CG's finite-termination property.
 """

@@ -78,6 +78,7 @@ def load() -> ctypes.CDLL:
         "rpy_set_multi_config": ([vp, i], i),
         "rpy_sqrt_mdot_w": ([vp, vp, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_sqrt_mdot_w_multi": ([vp, vp, i, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
+        "rpy_mobility_solve": ([vp, vp, vp, i, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_div_m": ([vp, vp, vp, vp], i),
         "rpy_div_m_rfd": ([vp, vp, d, vp, vp, vp], i),
         "rpy_langevin_velocities": ([vp, vp, vp, vp, d, d, d, i, vp, vp, ctypes.POINTER(i), vp], i),
@@ -208,6 +209,21 @@ def rpy_sqrt_mdot_w_multi(h, w, nrhs, prefactor, tol, max_iter, lin_out, ang_out
         raise NotConvergedError(st, load().rpy_last_error(h).decode(), (lin_out, ang_out), its, incs)
     _check(h, st)
     return its, incs
+
+
+def rpy_mobility_solve(h, u_lin, u_ang, nrhs, tol, max_iter, f_out, t_out, dtype, n):
+    """Per right-hand side (iterations, relative residuals) lists."""
+    iters = (ctypes.c_int * nrhs)()
+    resid = (ctypes.c_double * nrhs)()
+    m = 3 * n * nrhs
+    st = load().rpy_mobility_solve(h, _ptr(u_lin, dtype, m, "U"), _ptr(u_ang, dtype, m, "Omega"), int(nrhs),
+                                   float(tol), int(max_iter), _ptr(f_out, dtype, m, "f_out"),
+                                   _ptr(t_out, dtype, m, "t_out"), iters, resid, _stream(f_out))
+    its, res = list(iters), list(resid)
+    if st == Status.NOT_CONVERGED:
+        raise NotConvergedError(st, load().rpy_last_error(h).decode(), (f_out, t_out), its, res)
+    _check(h, st)
+    return its, res
 
 
 def rpy_div_m(h, lin_out, ang_out, dtype, n):

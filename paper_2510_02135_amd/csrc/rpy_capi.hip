@@ -248,7 +248,7 @@ const char *rpy_last_error(const rpy_solver *s) { return s ? s->err.c_str() : "n
 void rpy_destroy(rpy_solver *s) {
     if (!s) return;
     for (DevBuf *b : {&s->pos, &s->f, &s->t, &s->part, &s->flag, &s->lz_basis, &s->lz_w, &s->lz_scal, &s->lz_red,
-                      &s->lz_q, &s->lz_vec, &s->lz_mon, &s->drift})
+                      &s->lz_q, &s->lz_vec, &s->lz_mon, &s->drift, &s->cg_vec, &s->cg_scal})
         b->release();
     for (auto &v : s->ev)
         for (auto &pr : v) {

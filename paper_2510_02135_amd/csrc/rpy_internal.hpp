@@ -78,6 +78,8 @@ struct rpy_solver {
     rpy::DevBuf pos, f, t, part, flag;
     // Lanczos workspace (float64): basis, scratch vectors, tridiagonal data
     rpy::DevBuf lz_basis, lz_w, lz_scal, lz_red, lz_q, lz_vec, lz_mon, drift;
+    // conjugate-gradient workspace (float64): x, r, p and a product slot per right-hand side; scalars
+    rpy::DevBuf cg_vec, cg_scal;
     // launch timing (rpy_enable_timing): event pairs and pair counts per kernel class
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[rpy::kKernelClasses];

@@ -156,6 +156,30 @@ class Solver:
         self.last_iterations, self.last_increment = it, inc
         return lin, ang
 
+    def solve(self, U: torch.Tensor, Omega: torch.Tensor | None = None, tol: float = 1e-8, maxIter: int = 1000):
+        """Forces (and torques) with M [F; T] = [U; Omega] by conjugate
+        gradients.  U (and Omega, required with includeAngular) of shape
+        (N, 3) or (nrhs, N, 3); returns arrays of the same shape.
+        last_iterations / last_residual hold per-right-hand-side lists."""
+        self._require_positions()
+        single = U.dim() == 2
+        nrhs = U.numel() // (3 * self._n) if U.numel() % (3 * self._n) == 0 else -1
+        if nrhs < 1:
+            raise ValueError(f"U must have shape (N, 3) or (nrhs, {self._n}, 3)")
+        if self._angular and Omega is None:
+            raise ValueError("includeAngular needs Omega")
+        if not self._angular and Omega is not None:
+            raise ValueError("Omega needs includeAngular")
+        u = self._as_multi(U, "U", nrhs)
+        w = self._as_multi(Omega, "Omega", nrhs) if self._angular else None
+        f = torch.empty((nrhs, self._n, 3), dtype=self._dtype, device=self._device)
+        t = torch.empty_like(f) if self._angular else None
+        it, res = _lib.rpy_mobility_solve(self._h, u, w, nrhs, tol, maxIter, f, t, self._dtype, self._n)
+        self.last_iterations, self.last_residual = it, res
+        if single:
+            return f[0], (t[0] if t is not None else None)
+        return f, t
+
     def divM(self):
         """Thermal drift: zero in an unbounded fluid."""
         self._require_positions()
