@@ -54,7 +54,11 @@ enum { BS_BETA0 = 0, BS_INCR, BS_NSPD, BS_TSCALE, BS_BREAK, BS_DONE, BS_CODE, BS
 // persistent batched pair kernel
 // ---------------------------------------------------------------------------
 // A task is (system, tile of 64 TM targets); lane l of the wave owns targets
-// tile * 64 TM + m * 64 + l, m < TM.
+// tile * 64 TM + m * 64 + l, m < TM.  The wave walks its system's sources in
+// chunks of 64: each lane loads one source record (coalesced, issued one
+// chunk ahead) into the wave's own LDS slots, and the chunk is then read by
+// broadcast.  Only the wave itself touches its slots, and a wave's LDS
+// operations complete in program order, so no workgroup barrier is needed.
 template <typename Real, typename Tout, int TM>
 __global__ void __launch_bounds__(kBatchBlock)
 batch_pair_kernel(const vec4_t<Real> *__restrict__ rec, const int64_t *__restrict__ off,
@@ -63,7 +67,12 @@ batch_pair_kernel(const vec4_t<Real> *__restrict__ rec, const int64_t *__restric
                   const int *__restrict__ active, Tout *__restrict__ out) {
     using R4 = vec4_t<Real>;
     constexpr bool COMP = std::is_same<Real, float>::value;
+    constexpr int kWaves = kBatchBlock / 64;
+    static_assert(kSrcChunk % 64 == 0, "fold points must fall on chunk ends");
+    __shared__ R4 tile_p[kWaves][64];
+    __shared__ R4 tile_f[kWaves][64];
     const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
     const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
     while (true) {
         unsigned t = 0;
@@ -85,28 +94,42 @@ batch_pair_kernel(const vec4_t<Real> *__restrict__ rec, const int64_t *__restric
         for (int m = 0; m < TM; ++m)
 #pragma unroll
             for (int d = 0; d < 3; ++d) acc[m][d] = sum[m][d] = cmp[m][d] = Real(0);
-        // the next source record is loaded before the current one is used
-        R4 sp = src[0], sf = src[1];
-        for (int j0 = 0; j0 < ns; j0 += kSrcChunk) {
-            const int cnt = min(kSrcChunk, ns - j0);
+        // this lane's record of the first chunk
+        R4 np = zero4, nf = zero4;
+        if (lane < ns) {
+            np = src[2 * lane];
+            nf = src[2 * lane + 1];
+        }
+        for (int j0 = 0; j0 < ns; j0 += 64) {
+            tile_p[wv][lane] = np;
+            tile_f[wv][lane] = nf;
+            // the next chunk's record, loaded while this chunk is evaluated
+            const int jn = j0 + 64 + lane;
+            if (jn < ns) {
+                np = src[2 * jn];
+                nf = src[2 * jn + 1];
+            }
+            __builtin_amdgcn_wave_barrier();
+            const int cnt = min(64, ns - j0);
 #pragma unroll 4
             for (int q = 0; q < cnt; ++q) {
-                const int jn = min(j0 + q + 1, ns - 1);
-                const R4 np = src[2 * jn];
-                const R4 nf = src[2 * jn + 1];
+                const R4 sp = tile_p[wv][q];
+                const R4 sf = tile_f[wv][q];
 #pragma unroll
                 for (int m = 0; m < TM; ++m) interact<Real, false>(p[m].x, p[m].y, p[m].z, sp, sf, zero4, c, acc[m], nullptr);
-                sp = np;
-                sf = nf;
             }
+            __builtin_amdgcn_wave_barrier();
             if constexpr (COMP) {
+                // fold every kSrcChunk sources and at the end, as before the staging
+                if ((j0 + 64) % kSrcChunk == 0 || j0 + 64 >= ns) {
 #pragma unroll
-                for (int m = 0; m < TM; ++m)
+                    for (int m = 0; m < TM; ++m)
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        neumaier(sum[m][d], cmp[m][d], acc[m][d]);
-                        acc[m][d] = Real(0);
-                    }
+                        for (int d = 0; d < 3; ++d) {
+                            neumaier(sum[m][d], cmp[m][d], acc[m][d]);
+                            acc[m][d] = Real(0);
+                        }
+                }
             }
         }
         const double kk = kfac[s];
