@@ -60,6 +60,9 @@ def parse():
                    help="skip the batched-systems and bead-chain measurements")
     p.add_argument("--tile-cache", default=None,
                    help="autotune cache file (read if it has an entry, else written)")
+    p.add_argument("--sweep", action="store_true",
+                   help="instead of the step: Mdot time against N = 2^10 .. 2^20 at number densities 0.1 and "
+                        "0.001 per a^3 (translational, float32), the axes of the paper's timing figure")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -161,9 +164,9 @@ def bench_batched(rpy, workloads, dev, stream, timed):
 def oracle_timings(workloads, pairloop):
     """Seconds of the other oracle routes on the host (context for the
     GPU numbers, not targets): dense float64 assembly + product at N = 1024
-    (translational, as the 1024-particle workload), the oracle's Lanczos
-    square root there (tol 1e-6), and the C pair loop on 1024 sampled rows
-    of the 1,048,576-bead chains (with torques)."""
+    and N = 4096 (translational), the oracle's Lanczos square root at
+    N = 1024 (tol 1e-6), and the C pair loop on 1024 sampled rows of the
+    1,048,576-bead chains (with torques)."""
     import numpy as np
     from oracle import lanczos as olz, mobility as omob
     out = {}
@@ -172,6 +175,12 @@ def oracle_timings(workloads, pairloop):
     m = omob.grand_mobility(c1.pos, c1.radius, c1.viscosity)
     u = m @ c1.forces.reshape(-1)
     out["n1024_dense_assembly_and_product_s"] = round(time.perf_counter() - t0, 3)
+    c4096 = workloads.uniform_cube(4096, 0.1, 1001)
+    t0 = time.perf_counter()
+    m4 = omob.grand_mobility(c4096.pos, c4096.radius, c4096.viscosity)
+    u4 = m4 @ c4096.forces.reshape(-1)
+    out["n4096_dense_assembly_and_product_s"] = round(time.perf_counter() - t0, 3)
+    del m4, u4
     w = np.random.default_rng(1001).standard_normal(3 * c1.n)
     t0 = time.perf_counter()
     _, info = olz.lanczos_sqrt(lambda v: m @ v, w, tol=1e-6)
@@ -219,6 +228,39 @@ def timed(fn, reps, stream, warmup=0):
     return times[len(times) // 2]
 
 
+def bench_sweep(rpy, workloads, dev, stream):
+    """One translational float32 Mdot per size, N = 2^10 .. 2^20, uniform cubes
+    at number density rho = 0.1 and 0.001 per a^3 (volume fractions 0.419 and
+    0.0042), forces N(0, 1): median of timed products (at least 3, about
+    0.3 s per size) after two warm-ups, with autotuned tiles up to N = 2^16
+    and the default tiles above (where tuning would take longer than the
+    sweep)."""
+    import numpy as np
+    import torch
+    out = []
+    for rho in (0.1, 0.001):
+        phi = rho * 4.0 / 3.0 * math.pi
+        for e in range(10, 21):
+            n = 1 << e
+            c = workloads.uniform_cube(n, phi, 2000 + e)
+            sol = rpy.Solver()
+            sol.initialize(viscosity=c.viscosity, hydrodynamicRadius=c.radius, includeAngular=False)
+            sol.setPositions(torch.tensor(c.pos, dtype=torch.float32, device=dev))
+            F = torch.tensor(c.forces, dtype=torch.float32, device=dev)
+            if n <= 1 << 16:
+                sol.autotune()
+            t1 = timed(lambda: sol.Mdot(forces=F), 1, stream, warmup=2)
+            reps = int(min(50, max(3, 300.0 / max(t1, 1e-3))))
+            t = timed(lambda: sol.Mdot(forces=F), reps, stream)
+            out.append({"n": n, "rho": rho, "phi": round(phi, 5), "mdot_ms": round(t, 4),
+                        "tiles": sol.tileConfig(False),
+                        "pairs_per_s": float(n) * n / (t * 1e-3), "reps": reps,
+                        "guide_4e-12_n2_ms": round(4e-12 * n * n * 1e3, 4)})
+            print(f"bench: sweep rho={rho} N={n}: {t:.3f} ms", file=sys.stderr, flush=True)
+            sol.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -236,6 +278,14 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    if args.sweep:
+        sweep = bench_sweep(rpy, workloads, dev, stream)
+        print(json.dumps({"metric": "Mdot time against N (translational, float32)", "unit": "ms",
+                          "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": "uniform cubes, N = 2^10 .. 2^20, number density 0.1 and 0.001 "
+                                                 "per a^3, a = 1, eta = 1/(6 pi), seeds 2010 .. 2020"},
+                          "sweep": sweep}), flush=True)
+        return
     s = workloads.c2_suspension(args.n)
     n = s.n
     rng = np.random.default_rng(4242)
@@ -465,6 +515,9 @@ def main():
                          f"float64 C/OpenMP pair loop ({dt_cpu:.1f} s)",
                "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count()}
         cpu["other_oracle_timings"] = oracle_timings(workloads, pairloop)
+        # the step's products at the oracle's rate (extrapolated from the sample, not run)
+        cpu["other_oracle_timings"]["step_products_extrapolated_s"] = round(products / args.steps * float(n) * n
+                                                                            / cpu["value"], 1)
 
     out = {
         "metric": METRIC,

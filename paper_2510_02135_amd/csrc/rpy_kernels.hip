@@ -42,7 +42,9 @@ int choose_splits(int64_t n, int tm, bool fp64, bool ang) {
     (void)ang;
     const int64_t tblocks = (n + targets_per_block(tm) - 1) / targets_per_block(tm);
     const int64_t max_split = std::max<int64_t>(1, (n + kTile - 1) / kTile);
-    const int64_t want = (2048 + tblocks - 1) / tblocks;   // ~8 workgroups per CU
+    // ~32 workgroups per CU: the split count the autotuner picks at
+    // N = 65,536, and at larger N it keeps the grid's tail short
+    const int64_t want = (8192 + tblocks - 1) / tblocks;
     return (int)std::max<int64_t>(1, std::min(want, max_split));
 }
 
