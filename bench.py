@@ -302,6 +302,12 @@ def main():
     sol.setPositions(X)
     print("bench: autotuning the pair kernel tiles", file=sys.stderr, flush=True)
     tiles = sol.autotune(args.tile_cache)
+    if tiles[1][0] == 0:   # the symmetric pair mode (each unordered pair once)
+        kernel_name = "sym_pair_kernel<float, true>"
+        kernel_label = f"{kernel_name} (angular, symmetric mode, {tiles[1][1]} source blocks per task)"
+    else:
+        kernel_name = f"pair_kernel<float, true, {tiles[1][0]}>"
+        kernel_label = f"{kernel_name} (angular, {tiles[1][1]} source splits)"
 
     iters = []
 
@@ -338,8 +344,8 @@ def main():
     achieved = FLOPS_PER_PAIR["angular"] * float(n) * float(n) / (avg_pair_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": hbm_traffic(f"pair_kernel<float, true, {tiles[1][0]}>", n, tiles[1]),
-                "kernel": f"pair_kernel<float, true, {tiles[1][0]}> (angular, {tiles[1][1]} source splits)",
+                "traffic": hbm_traffic(kernel_name, n, tiles[1]),
+                "kernel": kernel_label,
                 "avg_launch_ms": round(avg_pair_ms, 4),
                 "launches": pair_launches, "flops_per_pair": FLOPS_PER_PAIR["angular"]}
 

@@ -370,7 +370,13 @@ void rpy_batch_destroy(rpy_batch *b);
  * (angular = 0) and with (angular = 1) the angular blocks:
  * targets_per_lane in {1, 2, 4}; source_splits = number of source ranges
  * the grid is split into (0 = chosen from N; clamped to ceil(N/256)).
- * Results do not depend on the configuration beyond float rounding order.
+ * targets_per_lane = 0 selects the symmetric pair mode instead: every
+ * unordered pair is evaluated once and applied in both directions (blocks
+ * of 512 particles, two targets per lane), source_splits then being the
+ * number of 512-particle source blocks per task (0 = automatic); it is
+ * available up to N = 2^18 (RPY_ERR_INVALID_ARG beyond, at the product)
+ * and needs (N/512) x 6 x N values of workspace.  Results do not depend on
+ * the configuration beyond float rounding order.
  */
 rpy_status rpy_set_tile_config(rpy_solver *s, int angular, int targets_per_lane, int source_splits);
 rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_per_lane, int *source_splits);
@@ -378,7 +384,8 @@ rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_pe
 /*
  * Autotuner (an addition beside the paper's method): for the stored
  * positions' N and dtype, times every candidate (targets per lane x source
- * splits) of the pair kernel with HIP events on hip_stream, for the
+ * splits, and for 4096 <= N <= 2^18 the symmetric mode with 1 or 2 source
+ * blocks per task) of the pair kernel with HIP events on hip_stream, for the
  * translational product and, with include_angular, the angular one: a
  * screen of single products, then the fastest split of each targets-per-lane
  * value re-timed in interleaved rounds of back-to-back bursts (about 100 ms

@@ -112,6 +112,7 @@ bool write_cache(const char *path, const std::map<std::string, Entry> &m) {
 template <typename Real>
 rpy_status run_config(rpy_solver *s, bool ang, const TileConfig &c, hipStream_t st, Real *out) {
     const int64_t n = s->n;
+    if (c.tm == 0) return apply_sym<Real, Real>(s, ang, c.n_split, out, ang ? out + 3 * n : nullptr, st);
     const PairConst<Real> pc = make_pair_const<Real>(s->radius);
     const auto *pos = s->pos.as<vec4_t<Real>>();
     const auto *f = s->f.as<vec4_t<Real>>();
@@ -200,6 +201,19 @@ rpy_status tune_mode(rpy_solver *s, bool ang, hipStream_t st, Entry *best) {
         }
         if (r != RPY_OK) break;
     }
+    // the symmetric pair mode, spans of 1 and 2 source blocks per task, where
+    // its source-side partials stay modest and there are blocks to pair
+    if (r == RPY_OK && n >= 4096 && n <= sym_max_n()) {
+        for (int span : {1, 2}) {
+            TileConfig c;
+            c.tm = 0;
+            c.n_split = span;
+            double ms = 0.0;
+            r = time_config<Real>(s, ang, c, 3, st, a, b, out.as<Real>(), &ms);
+            if (r != RPY_OK) break;
+            screened.push_back({ms, c});
+        }
+    }
     // stage 2: the fastest screened split of each targets-per-lane value,
     // re-timed in interleaved rounds of bursts of back-to-back products (so
     // clock and thermal drift affect them alike and the sustained rate
@@ -257,8 +271,8 @@ extern "C" {
 
 rpy_status rpy_set_tile_config(rpy_solver *s, int angular, int targets_per_lane, int source_splits) {
     if (!s) return RPY_ERR_INVALID_ARG;
-    if (targets_per_lane != 1 && targets_per_lane != 2 && targets_per_lane != 4)
-        return fail(s, RPY_ERR_INVALID_ARG, "targets per lane must be 1, 2 or 4");
+    if (targets_per_lane != 0 && targets_per_lane != 1 && targets_per_lane != 2 && targets_per_lane != 4)
+        return fail(s, RPY_ERR_INVALID_ARG, "targets per lane must be 1, 2 or 4 (0: symmetric pair mode)");
     if (source_splits < 0) return fail(s, RPY_ERR_INVALID_ARG, "source splits must be >= 0");
     TileConfig &c = s->cfg[angular ? 1 : 0];
     c.tm = targets_per_lane;

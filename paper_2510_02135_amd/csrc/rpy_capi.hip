@@ -29,6 +29,9 @@ double k_factor(const rpy_solver *s) { return 1.0 / (8.0 * M_PI * s->eta); }
 
 int splits_for(const rpy_solver *s, bool ang) {
     const TileConfig &c = s->cfg[ang ? 1 : 0];
+    // in the symmetric mode n_split is a task span; other kernels that share
+    // the split layout (multi-vector products) then choose their own
+    if (c.tm == 0) return choose_splits(s->n, 2, s->dtype == RPY_F64, ang);
     if (c.n_split > 0) return std::min(c.n_split, max_splits(s->n));
     return choose_splits(s->n, c.tm, s->dtype == RPY_F64, ang);
 }
@@ -37,6 +40,7 @@ int splits_for(const rpy_solver *s, bool ang) {
 // Output type Tout: the caller's dtype, or double for Lanczos products.
 template <typename Real, typename Tout>
 rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *angout, hipStream_t st, const void *pos_in) {
+    if (s->cfg[ang ? 1 : 0].tm == 0) return apply_sym<Real, Tout>(s, ang, s->cfg[ang ? 1 : 0].n_split, lin, angout, st, pos_in);
     const int64_t n = s->n;
     const int splits = splits_for(s, ang);
     const int nc = (ang ? 6 : 3) * (std::is_same<Real, float>::value ? 2 : 1);
@@ -248,7 +252,8 @@ const char *rpy_last_error(const rpy_solver *s) { return s ? s->err.c_str() : "n
 void rpy_destroy(rpy_solver *s) {
     if (!s) return;
     for (DevBuf *b : {&s->pos, &s->f, &s->t, &s->part, &s->flag, &s->lz_basis, &s->lz_w, &s->lz_scal, &s->lz_red,
-                      &s->lz_q, &s->lz_vec, &s->lz_mon, &s->drift, &s->cg_vec, &s->cg_scal})
+                      &s->lz_q, &s->lz_vec, &s->lz_mon, &s->drift, &s->cg_vec, &s->cg_scal, &s->sym_task_buf,
+                      &s->sym_slot_buf, &s->sym_jpart})
         b->release();
     for (auto &v : s->ev)
         for (auto &pr : v) {

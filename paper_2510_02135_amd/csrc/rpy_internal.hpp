@@ -18,8 +18,8 @@ constexpr int kMaxRhs = 1024;       // vectors per multi-vector product
 
 // Tile configuration of the pair kernels.
 struct TileConfig {
-    int tm = 2;          // targets per lane (1, 2 or 4)
-    int n_split = 0;     // source splits (0 = choose from N)
+    int tm = 2;          // targets per lane (1, 2 or 4), or 0: symmetric pair mode (rpy_sym.hip)
+    int n_split = 0;     // source splits (0 = choose from N); symmetric mode: source blocks per task
 };
 
 // Plain device buffer that only grows.
@@ -80,6 +80,10 @@ struct rpy_solver {
     rpy::DevBuf lz_basis, lz_w, lz_scal, lz_red, lz_q, lz_vec, lz_mon, drift;
     // conjugate-gradient workspace (float64): x, r, p and a product slot per right-hand side; scalars
     rpy::DevBuf cg_vec, cg_scal;
+    // symmetric pair mode: task list and block slot offsets (cached for sym_n, sym_span), source-side partials
+    rpy::DevBuf sym_task_buf, sym_slot_buf, sym_jpart;
+    int64_t sym_n = -1;
+    int sym_span = 0, sym_ntasks = 0;
     // launch timing (rpy_enable_timing): event pairs and pair counts per kernel class
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[rpy::kKernelClasses];

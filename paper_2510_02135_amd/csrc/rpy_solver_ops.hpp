@@ -26,6 +26,15 @@ template <typename Real, typename Tout>
 rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *ang_out, hipStream_t st,
                         const void *pos = nullptr);
 
+// M [F; T] by the symmetric pair kernel (each unordered pair once), with
+// F, T staged as for apply_staged; `span` source blocks per task (0 =
+// automatic).  RPY_ERR_INVALID_ARG above sym_max_n() particles.  Defined in
+// rpy_sym.hip.
+template <typename Real, typename Tout>
+rpy_status apply_sym(rpy_solver *s, bool ang, int span, Tout *lin, Tout *ang_out, hipStream_t st,
+                     const void *pos = nullptr);
+int64_t sym_max_n();
+
 // nrhs products M [F_r; T_r] with the vectors staged in s->f (s->t) as
 // [vector][n] vec4 arrays (stage_multi); vector r's outputs are the n x 3
 // arrays at lin + r * ostride and ang_out + r * ostride.  Defined in

@@ -1,0 +1,90 @@
+"""GPU parity of the symmetric pair mode (each unordered pair evaluated once
+and applied in both directions; tile configuration targets_per_lane = 0)
+through the C interface: Mdot against the float64 oracle (bars 1e-12 /
+1e-5) at sizes around the 512-particle block and 64-source chunk edges,
+with 1 to 3 source blocks per task, translational and angular; agreement
+with the ordinary kernel; the Lanczos square root and the adjoint's
+forward product through the same mode; the size limit."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import lanczos, mobility
+from tests.gpu_util import emax, host, rounded, say, to_dev, tol_for
+
+pytestmark = pytest.mark.gpu
+DTYPES = [torch.float64, torch.float32]
+
+
+def _solver(angular, a=1.1, eta=0.8):
+    import paper_2510_02135_amd as rpy
+    s = rpy.Solver("open", "open", "open")
+    s.initialize(viscosity=eta, hydrodynamicRadius=a, includeAngular=angular)
+    return s
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("angular", [False, True])
+@pytest.mark.parametrize("n,span", [(1, 0), (5, 1), (64, 0), (511, 0), (512, 1), (513, 1), (1100, 0),
+                                    (1100, 1), (2047, 3), (2900, 2)])
+def test_symmetric_mode_against_oracle(dtype, angular, n, span):
+    say(f"case symmetric n={n} span={span} angular={angular} {dtype}")
+    rng = np.random.default_rng(900 + n + span)
+    x = (rng.random((n, 3)) - 0.5) * workloads.cube_side(n, 0.2, 1.1)    # overlapping pairs present
+    F = rng.standard_normal((n, 3))
+    T = rng.standard_normal((n, 3)) if angular else None
+    sol = _solver(angular)
+    sol.setPositions(to_dev(x, dtype))
+    Fd, Td = to_dev(F, dtype), to_dev(T, dtype)
+    l0, a0 = sol.Mdot(Fd, Td)
+    sol.setTileConfig(angular, 0, span)
+    assert sol.tileConfig(angular) == (0, span)
+    l1, a1 = sol.Mdot(Fd, Td)
+    xr = rounded(x, dtype)
+    u, w = mobility.mdot_dense(xr, rounded(F, dtype), rounded(T, dtype) if angular else None, 1.1, 0.8)
+    e = emax(host(l1), u)
+    d = emax(host(l1), host(l0))
+    if angular:
+        e = max(e, emax(host(a1), w))
+        d = max(d, emax(host(a1), host(a0)))
+    say(f"  e_max vs oracle {e:.2e}, vs the ordinary kernel {d:.2e}")
+    assert e <= tol_for(dtype)
+    assert d <= 2 * tol_for(dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_symmetric_mode_lanczos_and_repeatability(dtype):
+    """sqrtMdotW through the symmetric mode against the oracle's Lanczos at the
+    reported iteration count, and two products bitwise equal."""
+    say(f"case symmetric Lanczos {dtype}")
+    s = workloads.uniform_cube(1500, 0.15, 901, torques=True, w=True, angular_w=True)
+    sol = _solver(True, s.radius, s.viscosity)
+    sol.setPositions(to_dev(s.pos, dtype))
+    sol.setTileConfig(True, 0, 1)
+    lin, ang = sol.sqrtMdotW(to_dev(s.w, dtype), prefactor=0.9, tol=1e-6)
+    k = sol.last_iterations
+    xr, wr = rounded(s.pos, dtype), rounded(s.w, dtype)
+    m = mobility.grand_mobility(xr, s.radius, s.viscosity, True)
+    y_ref, _ = lanczos.lanczos_sqrt(lambda v: m @ v, wr, iters=k, prefactor=0.9)
+    y = np.concatenate([host(lin).reshape(-1), host(ang).reshape(-1)])
+    e = float(np.abs(y - y_ref).max() / np.abs(y_ref).max())
+    say(f"  iterations {k}, matched-iteration max rel {e:.2e}")
+    assert e <= (1e-12 if dtype == torch.float64 else 1e-5)
+    F, T = to_dev(s.forces, dtype), to_dev(s.torques, dtype)
+    a1, b1 = sol.Mdot(F, T)
+    a2, b2 = sol.Mdot(F, T)
+    assert torch.equal(a1, a2) and torch.equal(b1, b2)
+
+
+def test_symmetric_mode_size_limit():
+    import paper_2510_02135_amd as rpy
+    say("case symmetric size limit")
+    n = (1 << 18) + 1
+    sol = _solver(False)
+    sol.setPositions(torch.arange(3 * n, dtype=torch.float32, device="cuda").reshape(n, 3))
+    sol.setTileConfig(False, 0, 0)
+    with pytest.raises(rpy.RpyError):
+        sol.Mdot(torch.zeros((n, 3), dtype=torch.float32, device="cuda"))
