@@ -291,6 +291,16 @@ rpy_status rpy_mdot_backward(rpy_solver *s, const void *forces, const void *torq
                              void *grad_forces, void *grad_torques, void *hip_stream);
 
 /*
+ * Pair evaluation of rpy_mdot_backward: 0 = automatic (the symmetric mode
+ * for 4096 <= N <= 2^18, the one-sided kernel otherwise), 1 = one-sided
+ * (every ordered pair evaluated for its target), 2 = symmetric (each
+ * unordered pair once, its position-gradient term added to one particle and
+ * subtracted from the other; N <= 2^18, RPY_ERR_INVALID_ARG beyond, at the
+ * call).  Results agree to rounding.  RPY_ERR_INVALID_ARG for other values.
+ */
+rpy_status rpy_set_adjoint_mode(rpy_solver *s, int mode);
+
+/*
  * Batched solver: many independent open-boundary systems of uneven size
  * (an addition beside the paper's method).  System s owns particles
  * offsets[s] .. offsets[s+1]-1 of every concatenated per-particle array

@@ -84,6 +84,7 @@ def load() -> ctypes.CDLL:
         "rpy_langevin_velocities": ([vp, vp, vp, vp, d, d, d, i, vp, vp, ctypes.POINTER(i), vp], i),
         "rpy_ab2_step": ([vp, vp, vp, vp, d, d, d, i, vp, i, vp, vp, ctypes.POINTER(i), vp], i),
         "rpy_mdot_backward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i),
+        "rpy_set_adjoint_mode": ([vp, i], i),
         "rpy_batch_create": ([ctypes.c_int32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d), i,
                               ctypes.POINTER(vp)], i),
         "rpy_batch_set_positions": ([vp, vp, vp], i),
@@ -176,6 +177,10 @@ def rpy_mdot_multi(h, forces, torques, nrhs, lin_out, ang_out, dtype, n):
     _check(h, load().rpy_mdot_multi(h, _ptr(forces, dtype, m, "forces"), _ptr(torques, dtype, m, "torques"),
                                     int(nrhs), _ptr(lin_out, dtype, m, "lin_out"), _ptr(ang_out, dtype, m, "ang_out"),
                                     _stream(lin_out)))
+
+
+def rpy_set_adjoint_mode(h, mode):
+    _check(h, load().rpy_set_adjoint_mode(h, int(mode)))
 
 
 def rpy_set_multi_config(h, targets_per_lane):

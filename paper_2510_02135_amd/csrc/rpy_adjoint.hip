@@ -21,6 +21,7 @@
 // Same decomposition as the forward pair kernel: target blocks x source
 // splits, LDS source tiles (position, F, g_U [, T, g_W]), fp32 in-tile sums
 // folded into Neumaier pairs per tile, fp64 plain sums.
+#include "rpy_adjoint.hpp"
 #include "rpy_device.hpp"
 #include "rpy_internal.hpp"
 #include "rpy_solver_ops.hpp"
@@ -33,112 +34,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kTile = 256;
-
-template <typename Real>
-__device__ __forceinline__ Real dot3(Real ax, Real ay, Real az, Real bx, Real by, Real bz) {
-    return fma(ax, bx, fma(ay, by, az * bz));
-}
-
-// Target-side data of one lane.
-template <typename Real, bool ANG>
-struct Tgt {
-    Real x, y, z;
-    Real fx, fy, fz;
-    Real gx, gy, gz;          // g_U
-    Real tx, ty, tz;          // T      (ANG)
-    Real hx, hy, hz;          // g_W    (ANG)
-};
-
-// Output accumulator layout: [0..2] dX, [3..5] dF (= (M g)_U), [6..8] dT.
-template <typename Real, bool ANG>
-__device__ __forceinline__ void adj_interact(const Tgt<Real, ANG> &k, const vec4_t<Real> &sp, const vec4_t<Real> &sf,
-                                             const vec4_t<Real> &sg, const vec4_t<Real> &st, const vec4_t<Real> &sh,
-                                             const PairConst<Real> &c, Real *acc) {
-    const Real dx = k.x - sp.x, dy = k.y - sp.y, dz = k.z - sp.z;
-    const Real r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-    const Real ri = rsq(r2);
-    const Real ri2 = ri * ri;
-    const Real ri3 = ri * ri2;
-    const Real ri5 = ri3 * ri2;
-    const Real ri7 = ri5 * ri2;
-    // far branch; c.m_two_a2 = -2a^2, c.two_a2_3 = 2a^2/3
-    Real A = fma(c.two_a2_3, ri3, ri);
-    Real B = fma(c.m_two_a2, ri5, ri3);
-    Real Ar = fma(c.m_two_a2, ri5, -ri3);                    // -1/r^3 - 2a^2/r^5
-    Real Br = fma(Real(-5) * c.m_two_a2, ri7, Real(-3) * ri5);  // -3/r^5 + 10a^2/r^7
-    Real G = ri3, Gg = ri3, Gr = Real(-3) * ri5;
-    Real D = Real(-0.5) * ri3, Dr = Real(1.5) * ri5;
-    Real E = Real(1.5) * ri5, Er = Real(-7.5) * ri7;
-    if (__builtin_expect(r2 < c.four_a2, 0)) {
-        const Real rs = r2 > Real(0) ? ri : Real(0);
-        const Real r = r2 * rs;
-        const Real rs3 = rs * rs * rs;
-        A = fma(c.nA1, r, c.nA0);
-        Ar = c.nA1 * rs;
-        B = c.nB * rs;
-        Br = -c.nB * rs3;
-        if constexpr (ANG) {
-            G = fma(c.nG1, r, c.nG0);
-            Gg = r2 > Real(0) ? G : Real(0);
-            Gr = c.nG1 * rs;
-            D = fma(fma(c.nD3, r * r, c.nD1), r, c.nD0);
-            Dr = fma(c.nD1, rs, Real(3) * c.nD3 * r);
-            E = fma(c.nE_1, rs, c.nE1 * r);
-            Er = fma(-c.nE_1, rs3, c.nE1 * rs);
-        }
-    }
-    // dot products shared by the terms
-    const Real dFj = dot3(dx, dy, dz, sf.x, sf.y, sf.z);
-    const Real dgj = dot3(dx, dy, dz, sg.x, sg.y, sg.z);
-    const Real dFk = dot3(dx, dy, dz, k.fx, k.fy, k.fz);
-    const Real dgk = dot3(dx, dy, dz, k.gx, k.gy, k.gz);
-    const Real gkFj = dot3(k.gx, k.gy, k.gz, sf.x, sf.y, sf.z);
-    const Real gjFk = dot3(sg.x, sg.y, sg.z, k.fx, k.fy, k.fz);
-    Real S = fma(Ar, gkFj + gjFk, Br * fma(dgk, dFj, dgj * dFk));
-    const Real b1 = B * dFj, b2 = B * dgk, b3 = B * dFk, b4 = B * dgj;
-    Real ox = fma(b1, k.gx, fma(b2, sf.x, fma(b3, sg.x, b4 * k.fx)));
-    Real oy = fma(b1, k.gy, fma(b2, sf.y, fma(b3, sg.y, b4 * k.fy)));
-    Real oz = fma(b1, k.gz, fma(b2, sf.z, fma(b3, sg.z, b4 * k.fz)));
-    // (M g)_U += A gUj + B (d.gUj) d
-    acc[3] = fma(A, sg.x, fma(b4, dx, acc[3]));
-    acc[4] = fma(A, sg.y, fma(b4, dy, acc[4]));
-    acc[5] = fma(A, sg.z, fma(b4, dz, acc[5]));
-    if constexpr (ANG) {
-        // C = gUk x Tj + gWk x Fj - gUj x Tk - gWj x Fk, one fused chain per component
-        const Real cx = fma(k.gy, st.z, fma(-k.gz, st.y, fma(k.hy, sf.z, fma(-k.hz, sf.y,
-                        fma(-sg.y, k.tz, fma(sg.z, k.ty, fma(-sh.y, k.fz, sh.z * k.fy)))))));
-        const Real cy = fma(k.gz, st.x, fma(-k.gx, st.z, fma(k.hz, sf.x, fma(-k.hx, sf.z,
-                        fma(-sg.z, k.tx, fma(sg.x, k.tz, fma(-sh.z, k.fx, sh.x * k.fz)))))));
-        const Real cz = fma(k.gx, st.y, fma(-k.gy, st.x, fma(k.hx, sf.y, fma(-k.hy, sf.x,
-                        fma(-sg.x, k.ty, fma(sg.y, k.tx, fma(-sh.x, k.fy, sh.y * k.fx)))))));
-        // gUk.(Tj x d) + gWk.(Fj x d) - gUj.(Tk x d) - gWj.(Fk x d) = d.C (cyclic triple products)
-        const Real gsum = dot3(dx, dy, dz, cx, cy, cz);
-        const Real dTj = dot3(dx, dy, dz, st.x, st.y, st.z);
-        const Real dhj = dot3(dx, dy, dz, sh.x, sh.y, sh.z);
-        const Real dTk = dot3(dx, dy, dz, k.tx, k.ty, k.tz);
-        const Real dhk = dot3(dx, dy, dz, k.hx, k.hy, k.hz);
-        const Real hkTj = dot3(k.hx, k.hy, k.hz, st.x, st.y, st.z);
-        const Real hjTk = dot3(sh.x, sh.y, sh.z, k.tx, k.ty, k.tz);
-        S = fma(Gr, gsum, fma(Dr, hkTj + hjTk, fma(Er, fma(dhk, dTj, dhj * dTk), S)));
-        // G C
-        const Real e1 = E * dTj, e2 = E * dhk, e3 = E * dTk, e4 = E * dhj;
-        ox = fma(Gg, cx, fma(e1, k.hx, fma(e2, st.x, fma(e3, sh.x, fma(e4, k.tx, ox)))));
-        oy = fma(Gg, cy, fma(e1, k.hy, fma(e2, st.y, fma(e3, sh.y, fma(e4, k.ty, oy)))));
-        oz = fma(Gg, cz, fma(e1, k.hz, fma(e2, st.z, fma(e3, sh.z, fma(e4, k.tz, oz)))));
-        // (M g)_U += G (gWj x d);  (M g)_W += G (gUj x d) + D gWj + E (d.gWj) d
-        const Real hjx = sh.y * dz - sh.z * dy, hjy = sh.z * dx - sh.x * dz, hjz = sh.x * dy - sh.y * dx;
-        const Real gjx = sg.y * dz - sg.z * dy, gjy = sg.z * dx - sg.x * dz, gjz = sg.x * dy - sg.y * dx;
-        acc[3] = fma(G, hjx, acc[3]);
-        acc[4] = fma(G, hjy, acc[4]);
-        acc[5] = fma(G, hjz, acc[5]);
-        acc[6] = fma(G, gjx, fma(D, sh.x, fma(e4, dx, acc[6])));
-        acc[7] = fma(G, gjy, fma(D, sh.y, fma(e4, dy, acc[7])));
-        acc[8] = fma(G, gjz, fma(D, sh.z, fma(e4, dz, acc[8])));
-    }
-    acc[0] = fma(S, dx, acc[0] + ox);
-    acc[1] = fma(S, dy, acc[1] + oy);
-    acc[2] = fma(S, dz, acc[2] + oz);
-}
+constexpr int64_t kSymAdjointMinN = 4096;   // automatic choice of the symmetric mode from this N on
 
 template <typename Real, bool ANG>
 __global__ void __launch_bounds__(kBlock)
@@ -270,6 +166,9 @@ rpy_status backward_typed(rpy_solver *s, const Real *F, const Real *T, const Rea
         HIP_TRY(s, (launch_stage_vec<Real, Real>(T, n, t4, st)));
         HIP_TRY(s, (launch_stage_vec<Real, Real>(ga, n, h4, st)));
     }
+    // the symmetric mode evaluates each unordered pair once (rpy_sym.hip)
+    const bool sym = s->adjoint_mode == 2 || (s->adjoint_mode == 0 && n >= kSymAdjointMinN && n <= sym_max_n());
+    if (sym) return adjoint_sym<Real>(s, ang, f4, g4, t4, h4, gp, gf, gt, st);
     const int nc = (ang ? 9 : 6) * (std::is_same<Real, float>::value ? 2 : 1);
     const int64_t tblocks = (n + kBlock - 1) / kBlock;
     const int splits = (int)std::max<int64_t>(1, std::min<int64_t>((2048 + tblocks - 1) / tblocks,
@@ -324,4 +223,11 @@ extern "C" rpy_status rpy_mdot_backward(rpy_solver *s, const void *forces, const
                                  static_cast<const float *>(grad_lin), static_cast<const float *>(grad_ang),
                                  static_cast<float *>(grad_pos), static_cast<float *>(grad_forces),
                                  static_cast<float *>(grad_torques), st);
+}
+
+extern "C" rpy_status rpy_set_adjoint_mode(rpy_solver *s, int mode) {
+    if (!s) return RPY_ERR_INVALID_ARG;
+    if (mode < 0 || mode > 2) return rpy::fail(s, RPY_ERR_INVALID_ARG, "adjoint mode must be 0, 1 or 2");
+    s->adjoint_mode = mode;
+    return RPY_OK;
 }

@@ -31,6 +31,13 @@ struct DevBuf {
     template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Task list of the symmetric pair mode (rpy_sym.hip), cached for (n, span, block).
+struct SymTasks {
+    DevBuf task, slot;
+    int64_t n = -1;
+    int span = 0, blk = 0, ntasks = 0;
+};
+
 // Launchers (defined in rpy_kernels.hip).  All take the caller's stream.
 // stage_positions: AoS n x 3 (float or double) -> vec4 of Real, counts non-finite entries.
 template <typename Tin, typename Real>
@@ -80,10 +87,10 @@ struct rpy_solver {
     rpy::DevBuf lz_basis, lz_w, lz_scal, lz_red, lz_q, lz_vec, lz_mon, drift;
     // conjugate-gradient workspace (float64): x, r, p and a product slot per right-hand side; scalars
     rpy::DevBuf cg_vec, cg_scal;
-    // symmetric pair mode: task list and block slot offsets (cached for sym_n, sym_span), source-side partials
-    rpy::DevBuf sym_task_buf, sym_slot_buf, sym_jpart;
-    int64_t sym_n = -1;
-    int sym_span = 0, sym_ntasks = 0;
+    // symmetric pair mode: task lists of the forward and adjoint kernels, source-side partials
+    rpy::SymTasks sym_fwd, sym_adj;
+    rpy::DevBuf sym_jpart;
+    int adjoint_mode = 0;     // rpy_set_adjoint_mode: 0 automatic, 1 one-sided, 2 symmetric
     // launch timing (rpy_enable_timing): event pairs and pair counts per kernel class
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[rpy::kKernelClasses];

@@ -34,6 +34,11 @@ template <typename Real, typename Tout>
 rpy_status apply_sym(rpy_solver *s, bool ang, int span, Tout *lin, Tout *ang_out, hipStream_t st,
                      const void *pos = nullptr);
 int64_t sym_max_n();
+// The adjoint by the symmetric mode (rpy_sym.hip): staged vec4 F, g_U (,
+// T, g_W); outputs as rpy_mdot_backward's (each may be NULL).
+template <typename Real>
+rpy_status adjoint_sym(rpy_solver *s, bool ang, const vec4_t<Real> *f, const vec4_t<Real> *g, const vec4_t<Real> *t,
+                       const vec4_t<Real> *h, Real *gp, Real *gf, Real *gt, hipStream_t st);
 
 // nrhs products M [F_r; T_r] with the vectors staged in s->f (s->t) as
 // [vector][n] vec4 arrays (stage_multi); vector r's outputs are the n x 3

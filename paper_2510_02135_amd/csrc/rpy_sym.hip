@@ -33,6 +33,7 @@
 // Memory: the source-side partials take (N / 512) x NC x N values, so the
 // mode is offered up to N = 2^18 (about 3 GB in float64 with angular
 // blocks).
+#include "rpy_adjoint.hpp"
 #include "rpy_device.hpp"
 #include "rpy_internal.hpp"
 #include "rpy_solver_ops.hpp"
@@ -44,11 +45,9 @@
 namespace rpy {
 namespace {
 
-constexpr int kSymThreads = 256;                   // 4 wavefronts
-constexpr int kSymBlock = 512;                     // particles per block (two per lane)
-constexpr int kSymChunk = 64;                      // sources per LDS chunk
-constexpr int kSymChunks = kSymBlock / kSymChunk;  // chunks per block
-constexpr int kSymFold = 4;                        // chunks between float32 folds (256 sources)
+constexpr int kSymThreads = 256;   // 4 wavefronts; blocks of 256 x (targets per lane) particles
+constexpr int kSymChunk = 64;      // sources per LDS chunk
+constexpr int kSymFold = 4;        // chunks between float32 folds (256 sources)
 
 // Both directions of one angular pair in the regrouped form of interact_ang
 // (rpy_device.hpp).  d = X_i - X_j.  Source records of j: p = (x, y, z, F'x),
@@ -152,24 +151,155 @@ __device__ __forceinline__ void sym_lin(Real xi, Real yi, Real zi, const vec4_t<
     uj[2] = fma(A, fi.z, fma(sj, dz, uj[2]));
 }
 
+// ---------------------------------------------------------------------------
+// pair policies: what a target holds, what a source record is, and the two
+// pair evaluations (one-sided for the diagonal block, both directions
+// elsewhere)
+// ---------------------------------------------------------------------------
+// Forward product M [F; T]: records (x, y, z, F'x), (F, F'y), (T, F'z),
+// (T~, 0) of the regrouped angular pair, or position and force.
+template <typename Real, bool ANG>
+struct FwdPairs {
+    using R4 = vec4_t<Real>;
+    static constexpr int TM = 2;                 // targets per lane
+    static constexpr int NC = ANG ? 6 : 3;       // output components
+    static constexpr int NR = ANG ? 4 : 2;       // records per source
+    struct Args {
+        const R4 *pos, *frc, *trq;
+    };
+    struct Tgt {
+        Real x, y, z, fpx;
+        R4 f, t, h;
+    };
+    __device__ static Tgt target(const Args &a, const PairConst<Real> &c, int idx, int n) {
+        const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+        const R4 p = a.pos[min(idx, n - 1)];
+        R4 f = idx < n ? a.frc[idx] : zero4;
+        R4 t = (ANG && idx < n) ? a.trq[idx] : zero4;
+        Tgt k;
+        k.x = p.x;
+        k.y = p.y;
+        k.z = p.z;
+        k.fpx = c.two_a2_3 * f.x;
+        f.w = c.two_a2_3 * f.y;
+        t.w = c.two_a2_3 * f.z;
+        k.f = f;
+        k.t = t;
+        k.h = R4{Real(-0.5) * t.x, Real(-0.5) * t.y, Real(-0.5) * t.z, Real(0)};
+        return k;
+    }
+    __device__ static R4 record(const Args &a, const PairConst<Real> &c, int r, int js, int n) {
+        const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+        const bool ok = js < n;
+        const R4 p = a.pos[min(js, n - 1)];
+        const R4 f = ok ? a.frc[js] : zero4;
+        if constexpr (ANG) {
+            const R4 t = ok ? a.trq[js] : zero4;
+            if (r == 0) return R4{p.x, p.y, p.z, c.two_a2_3 * f.x};
+            if (r == 1) return R4{f.x, f.y, f.z, c.two_a2_3 * f.y};
+            if (r == 2) return R4{t.x, t.y, t.z, c.two_a2_3 * f.z};
+            return R4{Real(-0.5) * t.x, Real(-0.5) * t.y, Real(-0.5) * t.z, Real(0)};
+        } else {
+            return r == 0 ? R4{p.x, p.y, p.z, Real(0)} : R4{f.x, f.y, f.z, Real(0)};
+        }
+    }
+    __device__ static void one_sided(const Tgt &k, const R4 *q, const PairConst<Real> &c, Real *acc) {
+        if constexpr (ANG) {
+            interact_ang<Real>(k.x, k.y, k.z, q[0], q[1], q[2], q[3], c, acc, acc + 3);
+        } else {
+            const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+            interact<Real, false>(k.x, k.y, k.z, q[0], q[1], zero4, c, acc, nullptr);
+        }
+    }
+    __device__ static void both(const Tgt &k, const R4 *q, const PairConst<Real> &c, Real *acc, Real *sj) {
+        if constexpr (ANG)
+            sym_ang<Real>(k.x, k.y, k.z, q[0], q[1], q[2], q[3], k.fpx, k.f, k.t, k.h, c, acc, acc + 3, sj, sj + 3);
+        else
+            sym_lin<Real>(k.x, k.y, k.z, q[0], q[1], k.f, c, acc, sj);
+    }
+};
+
+// Adjoint: records position, F, g_U (, T, g_W); outputs dX, (M g)_U (,
+// (M g)_W), the pair term of rpy_adjoint.hpp.
+template <typename Real, bool ANG>
+struct AdjPairs {
+    using R4 = vec4_t<Real>;
+    static constexpr int TM = 1;
+    static constexpr int NC = ANG ? 9 : 6;
+    static constexpr int NR = ANG ? 5 : 3;
+    struct Args {
+        const R4 *pos, *frc, *gu, *trq, *gw;
+    };
+    using Tgt = rpy::Tgt<Real, ANG>;
+    __device__ static Tgt target(const Args &a, const PairConst<Real> &c, int idx, int n) {
+        (void)c;
+        const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+        const bool ok = idx < n;
+        const R4 p = a.pos[min(idx, n - 1)];
+        const R4 f = ok ? a.frc[idx] : zero4, g = ok ? a.gu[idx] : zero4;
+        Tgt k;
+        k.x = p.x;
+        k.y = p.y;
+        k.z = p.z;
+        k.fx = f.x;
+        k.fy = f.y;
+        k.fz = f.z;
+        k.gx = g.x;
+        k.gy = g.y;
+        k.gz = g.z;
+        if constexpr (ANG) {
+            const R4 t = ok ? a.trq[idx] : zero4, h = ok ? a.gw[idx] : zero4;
+            k.tx = t.x;
+            k.ty = t.y;
+            k.tz = t.z;
+            k.hx = h.x;
+            k.hy = h.y;
+            k.hz = h.z;
+        }
+        return k;
+    }
+    __device__ static R4 record(const Args &a, const PairConst<Real> &c, int r, int js, int n) {
+        (void)c;
+        const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+        if (r == 0) return a.pos[min(js, n - 1)];
+        if (js >= n) return zero4;
+        if (r == 1) return a.frc[js];
+        if (r == 2) return a.gu[js];
+        if (r == 3) return a.trq[js];
+        return a.gw[js];
+    }
+    __device__ static void one_sided(const Tgt &k, const R4 *q, const PairConst<Real> &c, Real *acc) {
+        const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+        adj_pair<Real, ANG, false>(k, q[0], q[1], q[2], ANG ? q[NR > 3 ? 3 : 0] : zero4,
+                                   ANG ? q[NR > 4 ? 4 : 0] : zero4, c, acc, nullptr);
+    }
+    __device__ static void both(const Tgt &k, const R4 *q, const PairConst<Real> &c, Real *acc, Real *sj) {
+        const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+        adj_pair<Real, ANG, true>(k, q[0], q[1], q[2], ANG ? q[NR > 3 ? 3 : 0] : zero4,
+                                  ANG ? q[NR > 4 ? 4 : 0] : zero4, c, acc, sj);
+    }
+};
+
 // One task per workgroup: tasks[b] = (target block I, first source block,
-// end source block, target-side partial slot).
-//   ipart: [slot][PC][512]  target-side partials (float32: sums, then
+// end source block, target-side partial slot); blocks of BLK = 256 TM
+// particles.
+//   ipart: [slot][PC][BLK]  target-side partials (float32: sums, then
 //          compensations; PC = 2 NC, float64: NC)
 //   jpart: [I][NC][n]       source-side partials
-template <typename Real, bool ANG>
+template <typename Real, typename P>
 __global__ void __launch_bounds__(kSymThreads)
-sym_pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__restrict__ frc,
-                const vec4_t<Real> *__restrict__ trq, int n, const int4 *__restrict__ tasks, PairConst<Real> c,
-                Real *__restrict__ ipart, Real *__restrict__ jpart) {
+sym_kernel(typename P::Args args, int n, const int4 *__restrict__ tasks, PairConst<Real> c, Real *__restrict__ ipart,
+           Real *__restrict__ jpart) {
     using R4 = vec4_t<Real>;
-    constexpr int NC = ANG ? 6 : 3;
+    constexpr int TM = P::TM, NC = P::NC, NR = P::NR;
+    constexpr int BLK = kSymThreads * TM;
+    constexpr int CHUNKS = BLK / kSymChunk;
     constexpr bool COMP = std::is_same<Real, float>::value;
-    constexpr int NR = ANG ? 4 : 2;   // records per source
     constexpr int kWaves = kSymThreads / 64;
+    constexpr int RPW = (NR + kWaves - 1) / kWaves;   // records staged per lane
     // double-buffered source records and source-side accumulators: one
-    // barrier per chunk, the next chunk's records loaded during this one
-    // the records are stored twice (columns q and q + 64) and the
+    // barrier per chunk, the next chunk's records loaded during this one.
+    // The records are stored twice (columns q and q + 64) and the
     // accumulators keep 128 columns (q and q + 64 summed at the end), so a
     // lane's source at step st is column lane + st without a wrap: the
     // addresses are the lane's base plus a constant per step
@@ -179,37 +309,16 @@ sym_pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__rest
     const int4 task = tasks[blockIdx.x];
     const int bi = task.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
 
-    // targets bi * 512 + m * 256 + tid; padding targets beyond n repeat the
+    // targets bi * BLK + m * 256 + tid; padding targets beyond n repeat the
     // last position with zero vectors, so their source-side terms vanish
-    Real xi[2], yi[2], zi[2], fpx[2];
-    R4 fi[2], ti[2], hi[2];
+    typename P::Tgt tg[TM];
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        const int idx = bi * kSymBlock + m * kSymThreads + tid;
-        const R4 p = pos[min(idx, n - 1)];
-        xi[m] = p.x;
-        yi[m] = p.y;
-        zi[m] = p.z;
-        R4 f = idx < n ? frc[idx] : zero4;
-        R4 t = (ANG && idx < n) ? trq[idx] : zero4;
-        fpx[m] = c.two_a2_3 * f.x;
-        f.w = c.two_a2_3 * f.y;
-        t.w = c.two_a2_3 * f.z;
-        R4 h;
-        h.x = Real(-0.5) * t.x;
-        h.y = Real(-0.5) * t.y;
-        h.z = Real(-0.5) * t.z;
-        h.w = Real(0);
-        fi[m] = f;
-        ti[m] = t;
-        hi[m] = h;
-    }
-    Real acc[2][NC];
-    Real sum[2][COMP ? NC : 1], cmp[2][COMP ? NC : 1];
+    for (int m = 0; m < TM; ++m) tg[m] = P::target(args, c, bi * BLK + m * kSymThreads + tid, n);
+    Real acc[TM][NC];
+    Real sum[TM][COMP ? NC : 1], cmp[TM][COMP ? NC : 1];
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < TM; ++m)
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             acc[m][k] = Real(0);
@@ -226,22 +335,6 @@ sym_pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__rest
             jl[bf][wv][k][lane + kSymChunk] = Real(0);
         }
 
-    // record `wv` (wave r stages record r) of source base + lane
-    auto load_record = [&](int base) -> R4 {
-        const int js = base + lane;
-        const bool ok = js < n;
-        const R4 p = pos[min(js, n - 1)];
-        const R4 f = ok ? frc[js] : zero4;
-        if constexpr (ANG) {
-            const R4 t = ok ? trq[js] : zero4;
-            if (wv == 0) return R4{p.x, p.y, p.z, c.two_a2_3 * f.x};
-            if (wv == 1) return R4{f.x, f.y, f.z, c.two_a2_3 * f.y};
-            if (wv == 2) return R4{t.x, t.y, t.z, c.two_a2_3 * f.z};
-            return R4{Real(-0.5) * t.x, Real(-0.5) * t.y, Real(-0.5) * t.z, Real(0)};
-        } else {
-            return wv == 0 ? R4{p.x, p.y, p.z, Real(0)} : R4{f.x, f.y, f.z, Real(0)};
-        }
-    };
     // source-side sums of a finished chunk: the four waves in order, stored
     // as the partial of (bi, source); the entries are cleared for reuse
     auto combine = [&](int bf, int base) {
@@ -259,61 +352,54 @@ sym_pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__rest
         }
     };
 
-    const int nchunks = (task.z - task.y) * kSymChunks;
-    auto chunk_base = [&](int ci) { return (task.y + ci / kSymChunks) * kSymBlock + (ci % kSymChunks) * kSymChunk; };
-    R4 nxt = zero4;
-    if (wv < NR) nxt = load_record(chunk_base(0));
+    const int nchunks = (task.z - task.y) * CHUNKS;
+    auto chunk_base = [&](int ci) { return (task.y + ci / CHUNKS) * BLK + (ci % CHUNKS) * kSymChunk; };
+    R4 nxt[RPW];
+#pragma unroll
+    for (int u = 0; u < RPW; ++u)
+        if (wv + u * kWaves < NR) nxt[u] = P::record(args, c, wv + u * kWaves, chunk_base(0) + lane, n);
     int chunks_since_fold = 0;
     for (int ci = 0; ci < nchunks; ++ci) {
         const int bf = ci & 1;
-        const int base = chunk_base(ci);
-        const bool diag = task.y + ci / kSymChunks == bi;
-        if (wv < NR) {
-            rec[bf][wv][lane] = nxt;
-            rec[bf][wv][lane + kSymChunk] = nxt;
+        const bool diag = task.y + ci / CHUNKS == bi;
+#pragma unroll
+        for (int u = 0; u < RPW; ++u) {
+            const int r = wv + u * kWaves;
+            if (r < NR) {
+                rec[bf][r][lane] = nxt[u];
+                rec[bf][r][lane + kSymChunk] = nxt[u];
+            }
         }
         // rec[bf] complete; every wave has finished chunk ci - 1
         __syncthreads();
-        if (ci > 0 && task.y + (ci - 1) / kSymChunks != bi) combine(bf ^ 1, chunk_base(ci - 1));
-        if (wv < NR && ci + 1 < nchunks) nxt = load_record(chunk_base(ci + 1));
+        if (ci > 0 && task.y + (ci - 1) / CHUNKS != bi) combine(bf ^ 1, chunk_base(ci - 1));
+        if (ci + 1 < nchunks) {
+#pragma unroll
+            for (int u = 0; u < RPW; ++u)
+                if (wv + u * kWaves < NR) nxt[u] = P::record(args, c, wv + u * kWaves, chunk_base(ci + 1) + lane, n);
+        }
         if (diag) {
             // one-sided, every source of the block (self pair included)
 #pragma unroll 2
             for (int q = 0; q < kSymChunk; ++q) {
-                const R4 a = rec[bf][0][q];
-                const R4 b = rec[bf][1][q];
-                if constexpr (ANG) {
-                    const R4 d = rec[bf][2][q];
-                    const R4 e = rec[bf][3][q];
+                R4 rq[NR];
 #pragma unroll
-                    for (int m = 0; m < 2; ++m)
-                        interact_ang<Real>(xi[m], yi[m], zi[m], a, b, d, e, c, acc[m], acc[m] + 3);
-                } else {
+                for (int r = 0; r < NR; ++r) rq[r] = rec[bf][r][q];
 #pragma unroll
-                    for (int m = 0; m < 2; ++m)
-                        interact<Real, false>(xi[m], yi[m], zi[m], a, b, zero4, c, acc[m], nullptr);
-                }
+                for (int m = 0; m < TM; ++m) P::one_sided(tg[m], rq, c, acc[m]);
             }
         } else {
 #pragma unroll 2
             for (int st = 0; st < kSymChunk; ++st) {
                 const int q = lane + st;
-                const R4 a = rec[bf][0][q];
-                const R4 b = rec[bf][1][q];
+                R4 rq[NR];
+#pragma unroll
+                for (int r = 0; r < NR; ++r) rq[r] = rec[bf][r][q];
                 Real sj[NC];
 #pragma unroll
                 for (int k = 0; k < NC; ++k) sj[k] = Real(0);
-                if constexpr (ANG) {
-                    const R4 d = rec[bf][2][q];
-                    const R4 e = rec[bf][3][q];
 #pragma unroll
-                    for (int m = 0; m < 2; ++m)
-                        sym_ang<Real>(xi[m], yi[m], zi[m], a, b, d, e, fpx[m], fi[m], ti[m], hi[m], c, acc[m],
-                                      acc[m] + 3, sj, sj + 3);
-                } else {
-#pragma unroll
-                    for (int m = 0; m < 2; ++m) sym_lin<Real>(xi[m], yi[m], zi[m], a, b, fi[m], c, acc[m], sj);
-                }
+                for (int m = 0; m < TM; ++m) P::both(tg[m], rq, c, acc[m], sj);
                 // each lane owns column q of its wave's accumulator in this step,
                 // and a wave's LDS operations complete in order: a plain
                 // read-add-write is race-free (float64 uses the LDS add, which
@@ -331,7 +417,7 @@ sym_pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__rest
             if (++chunks_since_fold == kSymFold) {
                 chunks_since_fold = 0;
 #pragma unroll
-                for (int m = 0; m < 2; ++m)
+                for (int m = 0; m < TM; ++m)
 #pragma unroll
                     for (int k = 0; k < NC; ++k) {
                         neumaier(sum[m][k], cmp[m][k], acc[m][k]);
@@ -341,74 +427,67 @@ sym_pair_kernel(const vec4_t<Real> *__restrict__ pos, const vec4_t<Real> *__rest
         }
     }
     __syncthreads();
-    if (nchunks > 0 && task.y + (nchunks - 1) / kSymChunks != bi) combine((nchunks - 1) & 1, chunk_base(nchunks - 1));
+    if (nchunks > 0 && task.y + (nchunks - 1) / CHUNKS != bi) combine((nchunks - 1) & 1, chunk_base(nchunks - 1));
     constexpr int PC = COMP ? 2 * NC : NC;
-    Real *out = ipart + (size_t)task.w * PC * kSymBlock;
+    Real *out = ipart + (size_t)task.w * PC * BLK;
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
+    for (int m = 0; m < TM; ++m) {
         const int t = m * kSymThreads + tid;
 #pragma unroll
         for (int k = 0; k < NC; ++k) {
             if constexpr (COMP) {
                 neumaier(sum[m][k], cmp[m][k], acc[m][k]);
-                out[(size_t)k * kSymBlock + t] = sum[m][k];
-                out[(size_t)(NC + k) * kSymBlock + t] = cmp[m][k];
+                out[(size_t)k * BLK + t] = sum[m][k];
+                out[(size_t)(NC + k) * BLK + t] = cmp[m][k];
             } else {
-                out[(size_t)k * kSymBlock + t] = acc[m][k];
+                out[(size_t)k * BLK + t] = acc[m][k];
             }
         }
     }
 }
 
-// Per particle i (component blockIdx.y): the target-side partials of the
-// tasks of its block (slots slot0[b] .. slot0[b + 1] - 1), then the
-// source-side partials of blocks 0 .. b - 1, scaled by k.
-template <typename Real, typename Tout, bool ANG>
+// Per particle i and component c = blockIdx.y (NC of them): the target-side
+// partials of the tasks of its block (slots slot0[b] .. slot0[b + 1] - 1),
+// then the source-side partials of blocks 0 .. b - 1, scaled by k; output
+// component c goes to outs[c / 3][3 i + c % 3] (skipped when NULL).
+template <typename Real, typename Tout, int NC, int BLK>
 __global__ void __launch_bounds__(256)
 sym_reduce_kernel(const Real *__restrict__ ipart, const Real *__restrict__ jpart, const int *__restrict__ slot0,
-                  int n, double k, Tout *__restrict__ lin, Tout *__restrict__ ang) {
-    constexpr int NC = ANG ? 6 : 3;
+                  int n, double k, Tout *o0, Tout *o1, Tout *o2) {
     constexpr bool COMP = std::is_same<Real, float>::value;
     constexpr int PC = COMP ? 2 * NC : NC;
     const int c = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int b = i / kSymBlock, t = i % kSymBlock;
+    Tout *o = c < 3 ? o0 : (c < 6 ? o1 : o2);
+    if (i >= n || !o) return;
+    const int b = i / BLK, t = i % BLK;
     const int s0 = slot0[b], s1 = slot0[b + 1];
     double v;
     if constexpr (COMP) {
         float s = 0.f, cp = 0.f, extra = 0.f;
         for (int q = s0; q < s1; ++q) {
-            const Real *p = ipart + (size_t)q * PC * kSymBlock;
-            neumaier(s, cp, p[(size_t)c * kSymBlock + t]);
-            extra += p[(size_t)(NC + c) * kSymBlock + t];
+            const Real *p = ipart + (size_t)q * PC * BLK;
+            neumaier(s, cp, p[(size_t)c * BLK + t]);
+            extra += p[(size_t)(NC + c) * BLK + t];
         }
         for (int bb = 0; bb < b; ++bb) neumaier(s, cp, jpart[((size_t)bb * NC + c) * (size_t)n + i]);
         v = (double)s + ((double)cp + (double)extra);
     } else {
         double s = 0.0;
-        for (int q = s0; q < s1; ++q) s += (double)ipart[((size_t)q * PC + c) * kSymBlock + t];
+        for (int q = s0; q < s1; ++q) s += (double)ipart[((size_t)q * PC + c) * BLK + t];
         for (int bb = 0; bb < b; ++bb) s += (double)jpart[((size_t)bb * NC + c) * (size_t)n + i];
         v = s;
     }
-    const Tout out = (Tout)(k * v);
-    if (c < 3)
-        lin[3 * (size_t)i + c] = out;
-    else
-        ang[3 * (size_t)i + (c - 3)] = out;
+    o[3 * (size_t)i + (c % 3)] = (Tout)(k * v);
 }
 
-}  // namespace
-
-int64_t sym_max_n() { return (int64_t)1 << 18; }
-
-// Task list for n particles and `span` source blocks per task (0 = automatic);
-// cached on the solver.
-rpy_status sym_tasks(rpy_solver *s, int span) {
+// Task list for n particles, blocks of blk and `span` source blocks per
+// task (0 = automatic), cached in T.
+rpy_status sym_tasks(rpy_solver *s, SymTasks &T, int blk, int span) {
     const int64_t n = s->n;
-    const int nb = (int)((n + kSymBlock - 1) / kSymBlock);
+    const int nb = (int)((n + blk - 1) / blk);
     if (span <= 0) span = std::max(1, std::min(nb, 2));
-    if (s->sym_n == n && s->sym_span == span) return RPY_OK;
+    if (T.n == n && T.span == span && T.blk == blk) return RPY_OK;
     std::vector<int4> tasks;
     std::vector<int> slot0(nb + 1, 0);
     for (int bi = 0; bi < nb; ++bi) {
@@ -417,59 +496,87 @@ rpy_status sym_tasks(rpy_solver *s, int span) {
             tasks.push_back(make_int4(bi, j0, std::min(nb, j0 + span), (int)tasks.size()));
     }
     slot0[nb] = (int)tasks.size();
-    HIP_TRY(s, s->sym_task_buf.ensure(sizeof(int4) * tasks.size()));
-    HIP_TRY(s, s->sym_slot_buf.ensure(sizeof(int) * slot0.size()));
-    HIP_TRY(s, hipMemcpy(s->sym_task_buf.p, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice));
-    HIP_TRY(s, hipMemcpy(s->sym_slot_buf.p, slot0.data(), sizeof(int) * slot0.size(), hipMemcpyHostToDevice));
-    s->sym_n = n;
-    s->sym_span = span;
-    s->sym_ntasks = (int)tasks.size();
+    T.n = -1;
+    HIP_TRY(s, T.task.ensure(sizeof(int4) * tasks.size()));
+    HIP_TRY(s, T.slot.ensure(sizeof(int) * slot0.size()));
+    HIP_TRY(s, hipMemcpy(T.task.p, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice));
+    HIP_TRY(s, hipMemcpy(T.slot.p, slot0.data(), sizeof(int) * slot0.size(), hipMemcpyHostToDevice));
+    T.n = n;
+    T.span = span;
+    T.blk = blk;
+    T.ntasks = (int)tasks.size();
     return RPY_OK;
 }
 
-// M [F; T] for the stored positions with F (and T) staged in s->f (s->t), by
-// the symmetric pair kernel; the tile configuration's n_split is the task's
-// span in source blocks.
-template <typename Real, typename Tout>
-rpy_status apply_sym(rpy_solver *s, bool ang, int span, Tout *lin, Tout *ang_out, hipStream_t st, const void *pos_in) {
+// Launch the symmetric kernel of policy P and its reduction into outs.
+template <typename Real, typename P, typename Tout>
+rpy_status run_sym(rpy_solver *s, SymTasks &T, int span, const typename P::Args &args, int kind, Tout *o0, Tout *o1,
+                   Tout *o2, hipStream_t st) {
+    constexpr int BLK = kSymThreads * P::TM;
     const int64_t n = s->n;
     if (n > sym_max_n()) return fail(s, RPY_ERR_INVALID_ARG, "the symmetric pair mode is limited to N <= 2^18");
-    rpy_status r = sym_tasks(s, span);
+    rpy_status r = sym_tasks(s, T, BLK, span);
     if (r != RPY_OK) return r;
-    const int nb = (int)((n + kSymBlock - 1) / kSymBlock);
-    const int nc = ang ? 6 : 3;
-    const int pc = nc * (std::is_same<Real, float>::value ? 2 : 1);
-    HIP_TRY(s, s->part.ensure(sizeof(Real) * (size_t)s->sym_ntasks * pc * kSymBlock));
-    HIP_TRY(s, s->sym_jpart.ensure(sizeof(Real) * (size_t)nb * nc * n));
+    const int nb = (int)((n + BLK - 1) / BLK);
+    const int pc = P::NC * (std::is_same<Real, float>::value ? 2 : 1);
+    HIP_TRY(s, s->part.ensure(sizeof(Real) * (size_t)T.ntasks * pc * BLK));
+    HIP_TRY(s, s->sym_jpart.ensure(sizeof(Real) * (size_t)nb * P::NC * n));
     const PairConst<Real> c = make_pair_const<Real>(s->radius);
-    const auto *pos = pos_in ? static_cast<const vec4_t<Real> *>(pos_in) : s->pos.as<vec4_t<Real>>();
-    const auto *f = s->f.as<vec4_t<Real>>();
-    const auto *t = ang ? s->t.as<vec4_t<Real>>() : nullptr;
-    hipEvent_t e0 = timing_begin(s, RPY_KERNEL_PAIR, (double)n * (double)n);
+    hipEvent_t e0 = timing_begin(s, kind, (double)n * (double)n);
     if (e0) HIP_TRY(s, hipEventRecord(e0, st));
-    if (ang)
-        hipLaunchKernelGGL((sym_pair_kernel<Real, true>), dim3((unsigned)s->sym_ntasks), dim3(kSymThreads), 0, st, pos,
-                           f, t, (int)n, s->sym_task_buf.as<int4>(), c, s->part.as<Real>(), s->sym_jpart.as<Real>());
-    else
-        hipLaunchKernelGGL((sym_pair_kernel<Real, false>), dim3((unsigned)s->sym_ntasks), dim3(kSymThreads), 0, st,
-                           pos, f, t, (int)n, s->sym_task_buf.as<int4>(), c, s->part.as<Real>(),
-                           s->sym_jpart.as<Real>());
+    hipLaunchKernelGGL((sym_kernel<Real, P>), dim3((unsigned)T.ntasks), dim3(kSymThreads), 0, st, args, (int)n,
+                       T.task.as<int4>(), c, s->part.as<Real>(), s->sym_jpart.as<Real>());
     HIP_TRY(s, hipGetLastError());
-    if (hipEvent_t e1 = timing_end(s, RPY_KERNEL_PAIR)) HIP_TRY(s, hipEventRecord(e1, st));
-    const dim3 rg((unsigned)((n + 255) / 256), (unsigned)nc);
-    if (ang)
-        hipLaunchKernelGGL((sym_reduce_kernel<Real, Tout, true>), rg, dim3(256), 0, st, s->part.as<Real>(),
-                           s->sym_jpart.as<Real>(), s->sym_slot_buf.as<int>(), (int)n, k_factor(s), lin, ang_out);
-    else
-        hipLaunchKernelGGL((sym_reduce_kernel<Real, Tout, false>), rg, dim3(256), 0, st, s->part.as<Real>(),
-                           s->sym_jpart.as<Real>(), s->sym_slot_buf.as<int>(), (int)n, k_factor(s), lin, ang_out);
+    if (hipEvent_t e1 = timing_end(s, kind)) HIP_TRY(s, hipEventRecord(e1, st));
+    const dim3 rg((unsigned)((n + 255) / 256), (unsigned)P::NC);
+    hipLaunchKernelGGL((sym_reduce_kernel<Real, Tout, P::NC, BLK>), rg, dim3(256), 0, st, s->part.as<Real>(),
+                       s->sym_jpart.as<Real>(), T.slot.as<int>(), (int)n, k_factor(s), o0, o1, o2);
     HIP_TRY(s, hipGetLastError());
     return RPY_OK;
+}
+
+}  // namespace
+
+int64_t sym_max_n() { return (int64_t)1 << 18; }
+
+// M [F; T] for the stored positions with F (and T) staged in s->f (s->t), by
+// the symmetric pair kernel; `span` = source blocks per task.
+template <typename Real, typename Tout>
+rpy_status apply_sym(rpy_solver *s, bool ang, int span, Tout *lin, Tout *ang_out, hipStream_t st, const void *pos_in) {
+    const auto *pos = pos_in ? static_cast<const vec4_t<Real> *>(pos_in) : s->pos.as<vec4_t<Real>>();
+    const auto *f = s->f.as<vec4_t<Real>>();
+    if (ang) {
+        typename FwdPairs<Real, true>::Args a{pos, f, s->t.as<vec4_t<Real>>()};
+        return run_sym<Real, FwdPairs<Real, true>, Tout>(s, s->sym_fwd, span, a, RPY_KERNEL_PAIR, lin, ang_out,
+                                                         (Tout *)nullptr, st);
+    }
+    typename FwdPairs<Real, false>::Args a{pos, f, nullptr};
+    return run_sym<Real, FwdPairs<Real, false>, Tout>(s, s->sym_fwd, span, a, RPY_KERNEL_PAIR, lin, (Tout *)nullptr,
+                                                      (Tout *)nullptr, st);
+}
+
+// Adjoint by the symmetric mode: staged vectors f, g (, t, h) as vec4 of
+// Real; outputs grad_pos, M g linear rows, angular rows (each may be NULL).
+template <typename Real>
+rpy_status adjoint_sym(rpy_solver *s, bool ang, const vec4_t<Real> *f, const vec4_t<Real> *g,
+                       const vec4_t<Real> *t, const vec4_t<Real> *h, Real *gp, Real *gf, Real *gt, hipStream_t st) {
+    const auto *pos = s->pos.as<vec4_t<Real>>();
+    if (ang) {
+        typename AdjPairs<Real, true>::Args a{pos, f, g, t, h};
+        return run_sym<Real, AdjPairs<Real, true>, Real>(s, s->sym_adj, 0, a, RPY_KERNEL_ADJOINT, gp, gf, gt, st);
+    }
+    typename AdjPairs<Real, false>::Args a{pos, f, g, nullptr, nullptr};
+    return run_sym<Real, AdjPairs<Real, false>, Real>(s, s->sym_adj, 0, a, RPY_KERNEL_ADJOINT, gp, gf, (Real *)nullptr,
+                                                      st);
 }
 
 template rpy_status apply_sym<float, float>(rpy_solver *, bool, int, float *, float *, hipStream_t, const void *);
 template rpy_status apply_sym<float, double>(rpy_solver *, bool, int, double *, double *, hipStream_t, const void *);
 template rpy_status apply_sym<double, double>(rpy_solver *, bool, int, double *, double *, hipStream_t,
                                               const void *);
+template rpy_status adjoint_sym<float>(rpy_solver *, bool, const float4 *, const float4 *, const float4 *,
+                                       const float4 *, float *, float *, float *, hipStream_t);
+template rpy_status adjoint_sym<double>(rpy_solver *, bool, const double4 *, const double4 *, const double4 *,
+                                        const double4 *, double *, double *, double *, hipStream_t);
 
 }  // namespace rpy

@@ -256,6 +256,10 @@ class Solver:
     def setTileConfig(self, angular: bool, targets_per_lane: int, source_splits: int = 0):
         _lib.rpy_set_tile_config(self._h, angular, targets_per_lane, source_splits)
 
+    def setAdjointMode(self, mode: int):
+        """Pair evaluation of Mdot_backward: 0 automatic, 1 one-sided, 2 symmetric."""
+        _lib.rpy_set_adjoint_mode(self._h, mode)
+
     def setMultiConfig(self, targets_per_lane: int):
         """Targets per lane (0 = automatic, 1 or 2) of the multi-vector pair kernel."""
         _lib.rpy_set_multi_config(self._h, targets_per_lane)

@@ -84,6 +84,7 @@ def test_parameter_and_initialize_checks(lib):
 def test_call_order_checks(lib):
     h = _solver(lib)
     buf = ctypes.c_void_p(16)   # never dereferenced: every call below fails validation first
+    assert lib.rpy_set_adjoint_mode(h, 3) == INVALID and lib.rpy_set_adjoint_mode(h, 2) == OK
     lib.rpy_mdot_multi.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     try:

@@ -1,10 +1,11 @@
 """GPU parity of the symmetric pair mode (each unordered pair evaluated once
-and applied in both directions; tile configuration targets_per_lane = 0)
-through the C interface: Mdot against the float64 oracle (bars 1e-12 /
-1e-5) at sizes around the 512-particle block and 64-source chunk edges,
-with 1 to 3 source blocks per task, translational and angular; agreement
-with the ordinary kernel; the Lanczos square root and the adjoint's
-forward product through the same mode; the size limit."""
+and applied in both directions; tile configuration targets_per_lane = 0,
+adjoint mode 2) through the C interface: Mdot against the float64 oracle
+(bars 1e-12 / 1e-5) at sizes around the 512-particle block and 64-source
+chunk edges, with 1 to 3 source blocks per task, translational and
+angular; agreement with the ordinary kernel; the Lanczos square root
+through the same mode; the adjoint against the oracle's gradient and the
+one-sided kernel; the size limits and mode checks."""
 import math
 
 import numpy as np
@@ -88,3 +89,53 @@ def test_symmetric_mode_size_limit():
     sol.setTileConfig(False, 0, 0)
     with pytest.raises(rpy.RpyError):
         sol.Mdot(torch.zeros((n, 3), dtype=torch.float32, device="cuda"))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("angular", [False, True])
+@pytest.mark.parametrize("n", [7, 300, 700, 1300])
+def test_symmetric_adjoint_against_oracle(dtype, angular, n):
+    """Mdot_backward in the symmetric mode (each unordered pair once, its
+    position-gradient term added to one particle and subtracted from the
+    other) against the oracle's analytic gradient and M g, and against the
+    one-sided kernel."""
+    from oracle import gradient
+    say(f"case symmetric adjoint n={n} angular={angular} {dtype}")
+    rng = np.random.default_rng(950 + n)
+    x = (rng.random((n, 3)) - 0.5) * workloads.cube_side(n, 0.25)
+    F, GU = rng.standard_normal((2, n, 3))
+    T, GW = (rng.standard_normal((2, n, 3)) if angular else (None, None))
+    sol = _solver(angular, 1.2, 0.9)
+    sol.setPositions(to_dev(x, dtype))
+    args = [to_dev(v, dtype) for v in (F, T, GU, GW)]
+    sol.setAdjointMode(1)
+    one = sol.Mdot_backward(*args)
+    sol.setAdjointMode(2)
+    sym = sol.Mdot_backward(*args)
+    xr = rounded(x, dtype)
+    fr, tr, gur, gwr = (rounded(v, dtype) if v is not None else None for v in (F, T, GU, GW))
+    gx = gradient.grad_positions(xr, fr, tr, gur, gwr, 1.2, 0.9)
+    mg_u, mg_w = mobility.mdot_dense(xr, gur, gwr, 1.2, 0.9)
+    e = max(emax(host(sym[0]), gx), emax(host(sym[1]), mg_u))
+    d = max(emax(host(sym[0]), host(one[0])), emax(host(sym[1]), host(one[1])))
+    if angular:
+        e = max(e, emax(host(sym[2]), mg_w))
+        d = max(d, emax(host(sym[2]), host(one[2])))
+    say(f"  e_max vs oracle {e:.2e}, vs the one-sided kernel {d:.2e}")
+    assert e <= tol_for(dtype)
+    assert d <= 2 * tol_for(dtype)
+
+
+def test_adjoint_mode_checks():
+    import paper_2510_02135_amd as rpy
+    say("case adjoint mode checks")
+    sol = _solver(False)
+    for bad in (-1, 3):
+        with pytest.raises(rpy.RpyError):
+            sol.setAdjointMode(bad)
+    n = (1 << 18) + 1
+    sol.setPositions(torch.arange(3 * n, dtype=torch.float32, device="cuda").reshape(n, 3))
+    sol.setAdjointMode(2)
+    z = torch.zeros((n, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(rpy.RpyError):
+        sol.Mdot_backward(z, None, z, None)
