@@ -292,11 +292,12 @@ rpy_status rpy_mdot_backward(rpy_solver *s, const void *forces, const void *torq
 
 /*
  * Pair evaluation of rpy_mdot_backward: 0 = automatic (the symmetric mode
- * for 4096 <= N <= 2^18, the one-sided kernel otherwise), 1 = one-sided
+ * for 4096 <= N <= 2^17, the one-sided kernel otherwise), 1 = one-sided
  * (every ordered pair evaluated for its target), 2 = symmetric (each
  * unordered pair once, its position-gradient term added to one particle and
- * subtracted from the other; N <= 2^18, RPY_ERR_INVALID_ARG beyond, at the
- * call).  Results agree to rounding.  RPY_ERR_INVALID_ARG for other values.
+ * subtracted from the other; workspace (N/256) x 9 x N values of the
+ * solver's dtype; N <= 2^18, RPY_ERR_INVALID_ARG beyond, at the call).
+ * Results agree to rounding.  RPY_ERR_INVALID_ARG for other values.
  */
 rpy_status rpy_set_adjoint_mode(rpy_solver *s, int mode);
 
