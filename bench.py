@@ -80,24 +80,29 @@ def hbm_traffic(kernel: str, n: int, tile):
     committed counter summary (FETCH_SIZE and WRITE_SIZE passes scaled by a
     plain copy), or None when the summary has no entry for that kernel, N
     and tile, or the kernel sources have changed since the counters were
-    taken."""
+    taken (an entry may name its own sources and hash; the others use the
+    summary's)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "pair_kernel_f32_angular_n65536_hbm.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    h = hashlib.sha256()
-    for f in d.get("kernel_sources", []):
-        try:
-            h.update(open(os.path.join(ROOT, f), "rb").read())
-        except OSError:
-            return None
-    if h.hexdigest() != d.get("kernel_source_sha256"):
-        return None
+
+    def sources_unchanged(files, digest):
+        h = hashlib.sha256()
+        for f in files:
+            try:
+                h.update(open(os.path.join(ROOT, f), "rb").read())
+            except OSError:
+                return False
+        return bool(files) and h.hexdigest() == digest
+
     for e in d.get("entries", []):
         if e.get("kernel") == kernel and e.get("n") == n and list(e.get("tile", [])) == list(tile):
-            return e.get("traffic_bytes_per_dispatch")
+            files = e.get("kernel_sources", d.get("kernel_sources", []))
+            digest = e.get("kernel_source_sha256", d.get("kernel_source_sha256"))
+            return e.get("traffic_bytes_per_dispatch") if sources_unchanged(files, digest) else None
     return None
 
 
@@ -303,7 +308,7 @@ def main():
     print("bench: autotuning the pair kernel tiles", file=sys.stderr, flush=True)
     tiles = sol.autotune(args.tile_cache)
     if tiles[1][0] == 0:   # the symmetric pair mode (each unordered pair once)
-        kernel_name = "sym_pair_kernel<float, true>"
+        kernel_name = "sym_kernel<float, FwdPairs<float, true>>"
         kernel_label = f"{kernel_name} (angular, symmetric mode, {tiles[1][1]} source blocks per task)"
     else:
         kernel_name = f"pair_kernel<float, true, {tiles[1][0]}>"

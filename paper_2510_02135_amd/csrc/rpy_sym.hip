@@ -17,10 +17,12 @@
 //   chunk's records loaded while this one is evaluated).  On an
 //   off-diagonal chunk, lane l pairs its targets
 //   with source (l + s) mod 64 at step s, so that in one step the 64 lanes
-//   touch 64 different sources: each lane adds its targets' contributions
-//   to that source into the wave's own LDS accumulator column (no
-//   conflicts, in step order).  After the chunk the four
-//   waves' columns are summed in order and stored as the source-side
+//   touch 64 different sources.  The wave's running sums for a source
+//   travel with it: lane l holds those of source (l + s) mod 64, adds its
+//   targets' contributions, and takes the next lane's sums for step s + 1
+//   (a DPP rotate of the wavefront by one lane), so no LDS traffic is
+//   spent on them.  After the chunk the four waves' sums are combined in
+//   order and stored as the source-side
 //   partial of (I, source).  The diagonal block J = I (self pair included)
 //   is evaluated one-sided with broadcast reads, as in the ordinary kernel.
 //   A reduction kernel sums, per particle, the target-side partials of its
@@ -48,6 +50,19 @@ namespace {
 constexpr int kSymThreads = 256;   // 4 wavefronts; blocks of 256 x (targets per lane) particles
 constexpr int kSymChunk = 64;      // sources per LDS chunk
 constexpr int kSymFold = 4;        // chunks between float32 folds (256 sources)
+
+// The value lane (l + 1) mod 64 holds, for lane l: a DPP wavefront rotate
+// by one lane (control 0x134, every row and bank enabled).  The caller runs
+// with all 64 lanes active.
+__device__ __forceinline__ float from_next_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x134, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_next_lane(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0x134, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x134, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 
 // Both directions of one angular pair in the regrouped form of interact_ang
 // (rpy_device.hpp).  d = X_i - X_j.  Source records of j: p = (x, y, z, F'x),
@@ -164,6 +179,11 @@ struct FwdPairs {
     static constexpr int TM = 2;                 // targets per lane
     static constexpr int NC = ANG ? 6 : 3;       // output components
     static constexpr int NR = ANG ? 4 : 2;       // records per source
+    // float32 angular: steps not unrolled and at most 128 VGPRs, so that
+    // four waves share a SIMD (measured 1-2 % faster than two unrolled steps
+    // at three waves)
+    static constexpr int kUnroll = (ANG && std::is_same<Real, float>::value) ? 1 : 2;
+    static constexpr int kMinWaves = (ANG && std::is_same<Real, float>::value) ? 4 : 1;
     struct Args {
         const R4 *pos, *frc, *trq;
     };
@@ -227,6 +247,8 @@ struct AdjPairs {
     static constexpr int TM = 1;
     static constexpr int NC = ANG ? 9 : 6;
     static constexpr int NR = ANG ? 5 : 3;
+    static constexpr int kUnroll = 2;
+    static constexpr int kMinWaves = 1;
     struct Args {
         const R4 *pos, *frc, *gu, *trq, *gw;
     };
@@ -287,7 +309,7 @@ struct AdjPairs {
 //          compensations; PC = 2 NC, float64: NC)
 //   jpart: [I][NC][n]       source-side partials
 template <typename Real, typename P>
-__global__ void __launch_bounds__(kSymThreads)
+__global__ void __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(P::kMinWaves)))
 sym_kernel(typename P::Args args, int n, const int4 *__restrict__ tasks, PairConst<Real> c, Real *__restrict__ ipart,
            Real *__restrict__ jpart) {
     using R4 = vec4_t<Real>;
@@ -297,14 +319,15 @@ sym_kernel(typename P::Args args, int n, const int4 *__restrict__ tasks, PairCon
     constexpr bool COMP = std::is_same<Real, float>::value;
     constexpr int kWaves = kSymThreads / 64;
     constexpr int RPW = (NR + kWaves - 1) / kWaves;   // records staged per lane
-    // double-buffered source records and source-side accumulators: one
-    // barrier per chunk, the next chunk's records loaded during this one.
-    // The records are stored twice (columns q and q + 64) and the
-    // accumulators keep 128 columns (q and q + 64 summed at the end), so a
-    // lane's source at step st is column lane + st without a wrap: the
-    // addresses are the lane's base plus a constant per step
+    // double-buffered source records and source-side sums: one barrier per
+    // chunk, the next chunk's records loaded during this one.  The records
+    // are stored twice (columns q and q + 64), so a lane's source at step st
+    // is column lane + st without a wrap: the addresses are the lane's base
+    // plus a constant per step.  Source-side sums travel with their source
+    // through the lanes (registers rotated by one lane per step) and land in
+    // jl[bf][wave][k][q] at the end of the chunk
     __shared__ R4 rec[2][NR][2 * kSymChunk];
-    __shared__ Real jl[2][kWaves][NC][2 * kSymChunk];
+    __shared__ Real jl[2][kWaves][NC][kSymChunk];
 
     const int4 task = tasks[blockIdx.x];
     const int bi = task.x;
@@ -327,26 +350,15 @@ sym_kernel(typename P::Args args, int n, const int4 *__restrict__ tasks, PairCon
                 cmp[m][k] = Real(0);
             }
         }
-#pragma unroll
-    for (int bf = 0; bf < 2; ++bf)
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-            jl[bf][wv][k][lane] = Real(0);
-            jl[bf][wv][k][lane + kSymChunk] = Real(0);
-        }
 
     // source-side sums of a finished chunk: the four waves in order, stored
-    // as the partial of (bi, source); the entries are cleared for reuse
+    // as the partial of (bi, source)
     auto combine = [&](int bf, int base) {
         for (int e = tid; e < NC * kSymChunk; e += kSymThreads) {
             const int k = e / kSymChunk, q = e % kSymChunk;
             Real v = Real(0);
 #pragma unroll
-            for (int w2 = 0; w2 < kWaves; ++w2) {
-                v += jl[bf][w2][k][q] + jl[bf][w2][k][q + kSymChunk];
-                jl[bf][w2][k][q] = Real(0);
-                jl[bf][w2][k][q + kSymChunk] = Real(0);
-            }
+            for (int w2 = 0; w2 < kWaves; ++w2) v += jl[bf][w2][k][q];
             const int js = base + q;
             if (js < n) jpart[((size_t)bi * NC + k) * (size_t)n + js] = v;
         }
@@ -389,29 +401,25 @@ sym_kernel(typename P::Args args, int n, const int4 *__restrict__ tasks, PairCon
                 for (int m = 0; m < TM; ++m) P::one_sided(tg[m], rq, c, acc[m]);
             }
         } else {
-#pragma unroll 2
+            // sj holds the wave's sums for source (lane + st) mod 64; after
+            // the step the next lane's register is the one for this lane's
+            // next source.  64 rotations bring source l's sums back to lane l
+            Real sj[NC];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) sj[k] = Real(0);
+#pragma unroll P::kUnroll
             for (int st = 0; st < kSymChunk; ++st) {
                 const int q = lane + st;
                 R4 rq[NR];
 #pragma unroll
                 for (int r = 0; r < NR; ++r) rq[r] = rec[bf][r][q];
-                Real sj[NC];
-#pragma unroll
-                for (int k = 0; k < NC; ++k) sj[k] = Real(0);
 #pragma unroll
                 for (int m = 0; m < TM; ++m) P::both(tg[m], rq, c, acc[m], sj);
-                // each lane owns column q of its wave's accumulator in this step,
-                // and a wave's LDS operations complete in order: a plain
-                // read-add-write is race-free (float64 uses the LDS add, which
-                // is as fast; float32 LDS adds were about ten times slower)
-                if constexpr (COMP) {
 #pragma unroll
-                    for (int k = 0; k < NC; ++k) jl[bf][wv][k][q] += sj[k];
-                } else {
-#pragma unroll
-                    for (int k = 0; k < NC; ++k) atomicAdd(&jl[bf][wv][k][q], sj[k]);
-                }
+                for (int k = 0; k < NC; ++k) sj[k] = from_next_lane(sj[k]);
             }
+#pragma unroll
+            for (int k = 0; k < NC; ++k) jl[bf][wv][k][lane] = sj[k];
         }
         if constexpr (COMP) {
             if (++chunks_since_fold == kSymFold) {
