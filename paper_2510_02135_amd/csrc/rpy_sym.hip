@@ -457,33 +457,77 @@ sym_kernel(typename P::Args args, int n, const int4 *__restrict__ tasks, PairCon
 // Per particle i and component c = blockIdx.y (NC of them): the target-side
 // partials of the tasks of its block (slots slot0[b] .. slot0[b + 1] - 1),
 // then the source-side partials of blocks 0 .. b - 1, scaled by k; output
-// component c goes to outs[c / 3][3 i + c % 3] (skipped when NULL).
+// component c goes to outs[c / 3][3 i + c % 3] (skipped when NULL).  The
+// loads of kAhead partials are issued before they enter the sequential,
+// fixed-order sum.
 template <typename Real, typename Tout, int NC, int BLK>
 __global__ void __launch_bounds__(256)
 sym_reduce_kernel(const Real *__restrict__ ipart, const Real *__restrict__ jpart, const int *__restrict__ slot0,
                   int n, double k, Tout *o0, Tout *o1, Tout *o2) {
     constexpr bool COMP = std::is_same<Real, float>::value;
     constexpr int PC = COMP ? 2 * NC : NC;
+    constexpr int kAhead = 8;
     const int c = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     Tout *o = c < 3 ? o0 : (c < 6 ? o1 : o2);
     if (i >= n || !o) return;
     const int b = i / BLK, t = i % BLK;
     const int s0 = slot0[b], s1 = slot0[b + 1];
+    const size_t istride = (size_t)PC * BLK, jstride = (size_t)NC * (size_t)n;
+    const Real *pi = ipart + (size_t)s0 * istride + (size_t)c * BLK + t;
+    const Real *pj = jpart + (size_t)c * (size_t)n + i;
+    const int ni = s1 - s0;
     double v;
     if constexpr (COMP) {
         float s = 0.f, cp = 0.f, extra = 0.f;
-        for (int q = s0; q < s1; ++q) {
-            const Real *p = ipart + (size_t)q * PC * BLK;
-            neumaier(s, cp, p[(size_t)c * BLK + t]);
-            extra += p[(size_t)(NC + c) * BLK + t];
+        int q = 0;
+        for (; q + kAhead <= ni; q += kAhead) {
+            float x[kAhead], e[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                x[u] = pi[(size_t)(q + u) * istride];
+                e[u] = pi[(size_t)(q + u) * istride + (size_t)NC * BLK];
+            }
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                neumaier(s, cp, x[u]);
+                extra += e[u];
+            }
         }
-        for (int bb = 0; bb < b; ++bb) neumaier(s, cp, jpart[((size_t)bb * NC + c) * (size_t)n + i]);
+        for (; q < ni; ++q) {
+            neumaier(s, cp, pi[(size_t)q * istride]);
+            extra += pi[(size_t)q * istride + (size_t)NC * BLK];
+        }
+        int bb = 0;
+        for (; bb + kAhead <= b; bb += kAhead) {
+            float x[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) x[u] = pj[(size_t)(bb + u) * jstride];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) neumaier(s, cp, x[u]);
+        }
+        for (; bb < b; ++bb) neumaier(s, cp, pj[(size_t)bb * jstride]);
         v = (double)s + ((double)cp + (double)extra);
     } else {
         double s = 0.0;
-        for (int q = s0; q < s1; ++q) s += (double)ipart[((size_t)q * PC + c) * BLK + t];
-        for (int bb = 0; bb < b; ++bb) s += (double)jpart[((size_t)bb * NC + c) * (size_t)n + i];
+        int q = 0;
+        for (; q + kAhead <= ni; q += kAhead) {
+            double x[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) x[u] = pi[(size_t)(q + u) * istride];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) s += x[u];
+        }
+        for (; q < ni; ++q) s += pi[(size_t)q * istride];
+        int bb = 0;
+        for (; bb + kAhead <= b; bb += kAhead) {
+            double x[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) x[u] = pj[(size_t)(bb + u) * jstride];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) s += x[u];
+        }
+        for (; bb < b; ++bb) s += pj[(size_t)bb * jstride];
         v = s;
     }
     o[3 * (size_t)i + (c % 3)] = (Tout)(k * v);
