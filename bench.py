@@ -395,6 +395,28 @@ def main():
                             gp.double().cpu().numpy(), gf.double().cpu().numpy())
             so.close()
 
+    # ---- the N = 16,384, phi = 0.2 gradient workload: loss
+    # 0.5 |M(X) F - M(X + delta) F|^2, its backward against the forward
+    gradient = None
+    if not args.no_breakdown:
+        print("bench: N=16384 phi=0.2 backward vs forward", file=sys.stderr, flush=True)
+        c3 = workloads.c3_gradient()
+        gradient = {"workload": f"{c3.name}: uniform cube, seed 1003, translational, target M(X + delta) F"}
+        for dt, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+            so = rpy.Solver()
+            so.initialize(viscosity=c3.viscosity, hydrodynamicRadius=c3.radius, includeAngular=False)
+            Fd = dev_t(c3.forces, dt)
+            so.setPositions(dev_t(c3.pos + c3.extra["delta"], dt))
+            target = so.Mdot(forces=Fd)[0].clone()
+            so.setPositions(dev_t(c3.pos, dt))
+            so.autotune(args.tile_cache)
+            g = (so.Mdot(forces=Fd)[0] - target).contiguous()
+            tf = timed(lambda: so.Mdot(forces=Fd), 10, stream, warmup=3)
+            tb = timed(lambda: so.Mdot_backward(Fd, None, g, None), 10, stream, warmup=3)
+            gradient[name] = {"mdot_ms": round(tf, 4), "backward_ms": round(tb, 4),
+                              "backward_over_forward": round(tb / tf, 3)}
+            so.close()
+
     # ---- several vectors at one geometry (float32, 8 force sets; 4 noise
     # vectors) against one call per vector --------------------------------
     multi = None
@@ -551,6 +573,7 @@ def main():
         "cpu_baseline": cpu,
         "lanczos_vector_ops": lanczos_cgs,
         "breakdown": breakdown,
+        "gradient_n16384": gradient,
         "accuracy_vs_fp64_oracle": acc,
         "batched": batched,
         "chains": chains,

@@ -292,12 +292,14 @@ rpy_status rpy_mdot_backward(rpy_solver *s, const void *forces, const void *torq
 
 /*
  * Pair evaluation of rpy_mdot_backward: 0 = automatic (the symmetric mode
- * for 4096 <= N <= 2^17, the one-sided kernel otherwise), 1 = one-sided
- * (every ordered pair evaluated for its target), 2 = symmetric (each
- * unordered pair once, its position-gradient term added to one particle and
- * subtracted from the other; workspace (N/256) x 9 x N values of the
- * solver's dtype; N <= 2^18, RPY_ERR_INVALID_ARG beyond, at the call).
- * Results agree to rounding.  RPY_ERR_INVALID_ARG for other values.
+ * from N = 4096 on, the one-sided kernel below), 1 = one-sided (every
+ * ordered pair evaluated for its target), 2 = symmetric (each unordered
+ * pair once, its position-gradient term added to one particle and
+ * subtracted from the other).  The symmetric mode's partials ((N/256) x 9
+ * x N source-side values of the solver's dtype, plus the target-side ones)
+ * are produced and reduced in slabs of target blocks of at most about
+ * 8 GiB of workspace each.  Results agree to rounding.
+ * RPY_ERR_INVALID_ARG for other values.
  */
 rpy_status rpy_set_adjoint_mode(rpy_solver *s, int mode);
 
@@ -384,10 +386,11 @@ void rpy_batch_destroy(rpy_batch *b);
  * targets_per_lane = 0 selects the symmetric pair mode instead: every
  * unordered pair is evaluated once and applied in both directions (blocks
  * of 512 particles, two targets per lane), source_splits then being the
- * number of 512-particle source blocks per task (0 = automatic); it is
- * available up to N = 2^18 (RPY_ERR_INVALID_ARG beyond, at the product)
- * and needs (N/512) x 6 x N values of workspace.  Results do not depend on
- * the configuration beyond float rounding order.
+ * number of 512-particle source blocks per task (0 = automatic); its
+ * partials ((N/512) x 6 x N source-side values plus the target-side ones)
+ * are produced and reduced in slabs of target blocks of at most about
+ * 8 GiB of workspace each.  Results do not depend on the configuration
+ * beyond float rounding order.
  */
 rpy_status rpy_set_tile_config(rpy_solver *s, int angular, int targets_per_lane, int source_splits);
 rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_per_lane, int *source_splits);

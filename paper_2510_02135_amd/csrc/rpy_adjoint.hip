@@ -34,10 +34,9 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kTile = 256;
-// automatic choice of the symmetric mode: from this N on, and up to the N
-// where its source-side partials ((N/256) x 9 x N values) stay below 5 GB
+// automatic choice of the symmetric mode: from this N on (large N runs in
+// slabs whose partials fit a fixed workspace)
 constexpr int64_t kSymAdjointMinN = 4096;
-constexpr int64_t kSymAdjointMaxN = (int64_t)1 << 17;
 
 template <typename Real, bool ANG>
 __global__ void __launch_bounds__(kBlock)
@@ -170,7 +169,7 @@ rpy_status backward_typed(rpy_solver *s, const Real *F, const Real *T, const Rea
         HIP_TRY(s, (launch_stage_vec<Real, Real>(ga, n, h4, st)));
     }
     // the symmetric mode evaluates each unordered pair once (rpy_sym.hip)
-    const bool sym = s->adjoint_mode == 2 || (s->adjoint_mode == 0 && n >= kSymAdjointMinN && n <= kSymAdjointMaxN);
+    const bool sym = s->adjoint_mode == 2 || (s->adjoint_mode == 0 && n >= kSymAdjointMinN);
     if (sym) return adjoint_sym<Real>(s, ang, f4, g4, t4, h4, gp, gf, gt, st);
     const int nc = (ang ? 9 : 6) * (std::is_same<Real, float>::value ? 2 : 1);
     const int64_t tblocks = (n + kBlock - 1) / kBlock;

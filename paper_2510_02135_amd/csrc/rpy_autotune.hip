@@ -298,9 +298,6 @@ rpy_status rpy_autotune(rpy_solver *s, const char *cache_path, void *hip_stream)
         const bool ang = mode == 1;
         const std::string key = cache_key(s, ang);
         auto it = cache.find(key);
-        // an entry of the symmetric mode is only valid up to its size limit
-        // (the cache key rounds log2 N)
-        if (it != cache.end() && it->second.tm == 0 && s->n > sym_max_n()) it = cache.end();
         if (it != cache.end()) {
             s->cfg[mode].tm = it->second.tm;
             s->cfg[mode].n_split = it->second.split;

@@ -34,6 +34,7 @@ struct DevBuf {
 // Task list of the symmetric pair mode (rpy_sym.hip), cached for (n, span, block).
 struct SymTasks {
     DevBuf task, slot;
+    std::vector<int> slot_host;   // first task of each target block, and the total
     int64_t n = -1;
     int span = 0, blk = 0, ntasks = 0;
 };
@@ -89,7 +90,7 @@ struct rpy_solver {
     rpy::DevBuf cg_vec, cg_scal;
     // symmetric pair mode: task lists of the forward and adjoint kernels, source-side partials
     rpy::SymTasks sym_fwd, sym_adj;
-    rpy::DevBuf sym_jpart;
+    rpy::DevBuf sym_jpart, sym_state;
     int adjoint_mode = 0;     // rpy_set_adjoint_mode: 0 automatic, 1 one-sided, 2 symmetric
     // launch timing (rpy_enable_timing): event pairs and pair counts per kernel class
     bool timing = false;

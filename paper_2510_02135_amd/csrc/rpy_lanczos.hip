@@ -30,6 +30,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <string>
 #include <vector>
@@ -408,6 +409,10 @@ rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t w
     // iteration and never uses the estimate.
     const char *check_env = std::getenv("RPY_LANCZOS_CHECK");
     const bool check_every = check_env && std::string(check_env) == "every";
+    // RPY_LANCZOS_PROGRESS=m prints each running recurrence's iteration and
+    // stopping estimate to stderr every m iterations (long solves)
+    const char *progress_env = std::getenv("RPY_LANCZOS_PROGRESS");
+    const int progress_every = progress_env ? std::max(0, std::atoi(progress_env)) : 0;
     const int gt_blocks = (int)((n + kGtChunk - 1) / kGtChunk);
     std::vector<LzRec *> act;
     for (int k = 1; k <= kmax; ++k) {
@@ -457,6 +462,12 @@ rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t w
             }
             HIP_TRY(s, hipGetLastError());
             if ((r = copy_status()) != RPY_OK) return r;
+            if (progress_every > 0 && k % progress_every == 0) {
+                for (LzRec *R : act)
+                    std::fprintf(stderr, "rpy lanczos: recurrence %d, k = %d, estimate %.3e\n",
+                                 (int)(R - rec.data()), k, hstat[(R->status - status_all) + ST_EST]);
+                std::fflush(stderr);
+            }
             for (LzRec *R : act) {
                 const double *hs = hstat + (R->status - status_all);
                 const double est = hs[ST_EST];

@@ -28,8 +28,9 @@ rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *ang_out, hipSt
 
 // M [F; T] by the symmetric pair kernel (each unordered pair once), with
 // F, T staged as for apply_staged; `span` source blocks per task (0 =
-// automatic).  RPY_ERR_INVALID_ARG above sym_max_n() particles.  Defined in
-// rpy_sym.hip.
+// automatic).  Large N runs in slabs of target blocks whose partials fit a
+// fixed workspace.  sym_max_n() is the largest N for which the autotuner
+// times the mode.  Defined in rpy_sym.hip.
 template <typename Real, typename Tout>
 rpy_status apply_sym(rpy_solver *s, bool ang, int span, Tout *lin, Tout *ang_out, hipStream_t st,
                      const void *pos = nullptr);

@@ -41,6 +41,7 @@
 #include "rpy_solver_ops.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 #include <vector>
 
@@ -304,14 +305,15 @@ struct AdjPairs {
 
 // One task per workgroup: tasks[b] = (target block I, first source block,
 // end source block, target-side partial slot); blocks of BLK = 256 TM
-// particles.
-//   ipart: [slot][PC][BLK]  target-side partials (float32: sums, then
-//          compensations; PC = 2 NC, float64: NC)
-//   jpart: [I][NC][n]       source-side partials
+// particles.  One launch covers the tasks of a slab of target blocks
+// (jbase = its first block, slot_base = its first task's slot).
+//   ipart: [slot - slot_base][PC][BLK]  target-side partials (float32: sums,
+//          then compensations; PC = 2 NC, float64: NC)
+//   jpart: [I - jbase][NC][n]           source-side partials
 template <typename Real, typename P>
 __global__ void __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(P::kMinWaves)))
-sym_kernel(typename P::Args args, int n, const int4 *__restrict__ tasks, PairConst<Real> c, Real *__restrict__ ipart,
-           Real *__restrict__ jpart) {
+sym_kernel(typename P::Args args, int n, const int4 *__restrict__ tasks, int slot_base, int jbase, PairConst<Real> c,
+           Real *__restrict__ ipart, Real *__restrict__ jpart) {
     using R4 = vec4_t<Real>;
     constexpr int TM = P::TM, NC = P::NC, NR = P::NR;
     constexpr int BLK = kSymThreads * TM;
@@ -360,7 +362,7 @@ sym_kernel(typename P::Args args, int n, const int4 *__restrict__ tasks, PairCon
 #pragma unroll
             for (int w2 = 0; w2 < kWaves; ++w2) v += jl[bf][w2][k][q];
             const int js = base + q;
-            if (js < n) jpart[((size_t)bi * NC + k) * (size_t)n + js] = v;
+            if (js < n) jpart[((size_t)(bi - jbase) * NC + k) * (size_t)n + js] = v;
         }
     };
 
@@ -437,7 +439,7 @@ sym_kernel(typename P::Args args, int n, const int4 *__restrict__ tasks, PairCon
     __syncthreads();
     if (nchunks > 0 && task.y + (nchunks - 1) / CHUNKS != bi) combine((nchunks - 1) & 1, chunk_base(nchunks - 1));
     constexpr int PC = COMP ? 2 * NC : NC;
-    Real *out = ipart + (size_t)task.w * PC * BLK;
+    Real *out = ipart + (size_t)(task.w - slot_base) * PC * BLK;
 #pragma unroll
     for (int m = 0; m < TM; ++m) {
         const int t = m * kSymThreads + tid;
@@ -454,32 +456,46 @@ sym_kernel(typename P::Args args, int n, const int4 *__restrict__ tasks, PairCon
     }
 }
 
-// Per particle i and component c = blockIdx.y (NC of them): the target-side
-// partials of the tasks of its block (slots slot0[b] .. slot0[b + 1] - 1),
-// then the source-side partials of blocks 0 .. b - 1, scaled by k; output
-// component c goes to outs[c / 3][3 i + c % 3] (skipped when NULL).  The
-// loads of kAhead partials are issued before they enter the sequential,
-// fixed-order sum.
+// The partials of one slab of target blocks s0 .. s1 - 1, per particle i of
+// blocks s0 and later and component c = blockIdx.y (NC of them): the
+// target-side partials of the tasks of i's own block b when it lies in the
+// slab (slots slot0[b] .. slot0[b + 1] - 1, stored from slot_base on), then
+// the source-side partials of the slab's blocks before b.  The running sums
+// start at zero on the first slab (s0 = 0) and are carried between slabs in
+// `state`; a particle is complete after the slab holding its own block,
+// which scales by k and writes component c to outs[c / 3][3 i + c % 3]
+// (skipped when NULL).  One slab holding every block is the plain order:
+// own target-side partials, then the source-side partials of blocks 0 ..
+// b - 1.  The loads of kAhead partials are issued before they enter the
+// sequential, fixed-order sum.
 template <typename Real, typename Tout, int NC, int BLK>
 __global__ void __launch_bounds__(256)
 sym_reduce_kernel(const Real *__restrict__ ipart, const Real *__restrict__ jpart, const int *__restrict__ slot0,
-                  int n, double k, Tout *o0, Tout *o1, Tout *o2) {
+                  int slot_base, int s0, int s1, int n, double k, Real *__restrict__ state, Tout *o0, Tout *o1,
+                  Tout *o2) {
     constexpr bool COMP = std::is_same<Real, float>::value;
     constexpr int PC = COMP ? 2 * NC : NC;
     constexpr int kAhead = 8;
     const int c = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = s0 * BLK + blockIdx.x * blockDim.x + threadIdx.x;
     Tout *o = c < 3 ? o0 : (c < 6 ? o1 : o2);
     if (i >= n || !o) return;
     const int b = i / BLK, t = i % BLK;
-    const int s0 = slot0[b], s1 = slot0[b + 1];
-    const size_t istride = (size_t)PC * BLK, jstride = (size_t)NC * (size_t)n;
-    const Real *pi = ipart + (size_t)s0 * istride + (size_t)c * BLK + t;
-    const Real *pj = jpart + (size_t)c * (size_t)n + i;
-    const int ni = s1 - s0;
+    const bool own = b < s1;
+    const int ni = own ? slot0[b + 1] - slot0[b] : 0;
+    const int jend = own ? b : s1;
+    const size_t istride = (size_t)PC * BLK, jstride = (size_t)NC * (size_t)n, nn = (size_t)n;
+    const Real *pi = ipart + (size_t)(own ? slot0[b] - slot_base : 0) * istride + (size_t)c * BLK + t;
+    const Real *pj = jpart + (size_t)c * nn + i;
+    const int nj = jend - s0;
     double v;
     if constexpr (COMP) {
         float s = 0.f, cp = 0.f, extra = 0.f;
+        if (s0 > 0) {
+            s = state[(size_t)(3 * c) * nn + i];
+            cp = state[(size_t)(3 * c + 1) * nn + i];
+            extra = state[(size_t)(3 * c + 2) * nn + i];
+        }
         int q = 0;
         for (; q + kAhead <= ni; q += kAhead) {
             float x[kAhead], e[kAhead];
@@ -499,17 +515,23 @@ sym_reduce_kernel(const Real *__restrict__ ipart, const Real *__restrict__ jpart
             extra += pi[(size_t)q * istride + (size_t)NC * BLK];
         }
         int bb = 0;
-        for (; bb + kAhead <= b; bb += kAhead) {
+        for (; bb + kAhead <= nj; bb += kAhead) {
             float x[kAhead];
 #pragma unroll
             for (int u = 0; u < kAhead; ++u) x[u] = pj[(size_t)(bb + u) * jstride];
 #pragma unroll
             for (int u = 0; u < kAhead; ++u) neumaier(s, cp, x[u]);
         }
-        for (; bb < b; ++bb) neumaier(s, cp, pj[(size_t)bb * jstride]);
+        for (; bb < nj; ++bb) neumaier(s, cp, pj[(size_t)bb * jstride]);
+        if (!own) {
+            state[(size_t)(3 * c) * nn + i] = s;
+            state[(size_t)(3 * c + 1) * nn + i] = cp;
+            state[(size_t)(3 * c + 2) * nn + i] = extra;
+            return;
+        }
         v = (double)s + ((double)cp + (double)extra);
     } else {
-        double s = 0.0;
+        double s = s0 > 0 ? (double)state[(size_t)c * nn + i] : 0.0;
         int q = 0;
         for (; q + kAhead <= ni; q += kAhead) {
             double x[kAhead];
@@ -520,14 +542,18 @@ sym_reduce_kernel(const Real *__restrict__ ipart, const Real *__restrict__ jpart
         }
         for (; q < ni; ++q) s += pi[(size_t)q * istride];
         int bb = 0;
-        for (; bb + kAhead <= b; bb += kAhead) {
+        for (; bb + kAhead <= nj; bb += kAhead) {
             double x[kAhead];
 #pragma unroll
             for (int u = 0; u < kAhead; ++u) x[u] = pj[(size_t)(bb + u) * jstride];
 #pragma unroll
             for (int u = 0; u < kAhead; ++u) s += x[u];
         }
-        for (; bb < b; ++bb) s += pj[(size_t)bb * jstride];
+        for (; bb < nj; ++bb) s += pj[(size_t)bb * jstride];
+        if (!own) {
+            state[(size_t)c * nn + i] = (Real)s;
+            return;
+        }
         v = s;
     }
     o[3 * (size_t)i + (c % 3)] = (Tout)(k * v);
@@ -553,6 +579,7 @@ rpy_status sym_tasks(rpy_solver *s, SymTasks &T, int blk, int span) {
     HIP_TRY(s, T.slot.ensure(sizeof(int) * slot0.size()));
     HIP_TRY(s, hipMemcpy(T.task.p, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice));
     HIP_TRY(s, hipMemcpy(T.slot.p, slot0.data(), sizeof(int) * slot0.size(), hipMemcpyHostToDevice));
+    T.slot_host = std::move(slot0);
     T.n = n;
     T.span = span;
     T.blk = blk;
@@ -560,36 +587,76 @@ rpy_status sym_tasks(rpy_solver *s, SymTasks &T, int blk, int span) {
     return RPY_OK;
 }
 
-// Launch the symmetric kernel of policy P and its reduction into outs.
+// Workspace of one slab (source-side partials of its blocks plus the
+// target-side partials of their tasks): slabs of consecutive target blocks
+// are formed so that each stays within this many bytes (a single block may
+// exceed it).  RPY_SYM_SLAB_BLOCKS=m also caps a slab at m blocks.
+constexpr size_t kSymSlabBytes = (size_t)8 << 30;
+
+std::vector<int> sym_slabs(const SymTasks &T, int nb, size_t block_bytes, size_t task_bytes) {
+    const char *env = std::getenv("RPY_SYM_SLAB_BLOCKS");
+    const int cap = env && std::atoi(env) > 0 ? std::atoi(env) : nb;
+    std::vector<int> bounds{0};
+    size_t used = 0;
+    for (int b = 0; b < nb; ++b) {
+        const size_t add = block_bytes + task_bytes * (size_t)(T.slot_host[b + 1] - T.slot_host[b]);
+        if (b > bounds.back() && (used + add > kSymSlabBytes || b - bounds.back() >= cap)) {
+            bounds.push_back(b);
+            used = 0;
+        }
+        used += add;
+    }
+    bounds.push_back(nb);
+    return bounds;
+}
+
+// Launch the symmetric kernel of policy P and its reduction into outs, one
+// slab of target blocks at a time.
 template <typename Real, typename P, typename Tout>
 rpy_status run_sym(rpy_solver *s, SymTasks &T, int span, const typename P::Args &args, int kind, Tout *o0, Tout *o1,
                    Tout *o2, hipStream_t st) {
     constexpr int BLK = kSymThreads * P::TM;
+    constexpr bool COMP = std::is_same<Real, float>::value;
     const int64_t n = s->n;
-    if (n > sym_max_n()) return fail(s, RPY_ERR_INVALID_ARG, "the symmetric pair mode is limited to N <= 2^18");
     rpy_status r = sym_tasks(s, T, BLK, span);
     if (r != RPY_OK) return r;
     const int nb = (int)((n + BLK - 1) / BLK);
-    const int pc = P::NC * (std::is_same<Real, float>::value ? 2 : 1);
-    HIP_TRY(s, s->part.ensure(sizeof(Real) * (size_t)T.ntasks * pc * BLK));
-    HIP_TRY(s, s->sym_jpart.ensure(sizeof(Real) * (size_t)nb * P::NC * n));
+    const int pc = P::NC * (COMP ? 2 : 1);
+    const size_t block_bytes = sizeof(Real) * P::NC * (size_t)n, task_bytes = sizeof(Real) * pc * BLK;
+    const std::vector<int> slab = sym_slabs(T, nb, block_bytes, task_bytes);
+    const int nslab = (int)slab.size() - 1;
+    int max_blocks = 0, max_tasks = 0;
+    for (int q = 0; q < nslab; ++q) {
+        max_blocks = std::max(max_blocks, slab[q + 1] - slab[q]);
+        max_tasks = std::max(max_tasks, T.slot_host[slab[q + 1]] - T.slot_host[slab[q]]);
+    }
+    HIP_TRY(s, s->part.ensure(task_bytes * (size_t)max_tasks));
+    HIP_TRY(s, s->sym_jpart.ensure(block_bytes * (size_t)max_blocks));
+    if (nslab > 1) HIP_TRY(s, s->sym_state.ensure(sizeof(Real) * (COMP ? 3 : 1) * P::NC * (size_t)n));
     const PairConst<Real> c = make_pair_const<Real>(s->radius);
+    // with several slabs the timed span also holds the reductions between them
     hipEvent_t e0 = timing_begin(s, kind, (double)n * (double)n);
     if (e0) HIP_TRY(s, hipEventRecord(e0, st));
-    hipLaunchKernelGGL((sym_kernel<Real, P>), dim3((unsigned)T.ntasks), dim3(kSymThreads), 0, st, args, (int)n,
-                       T.task.as<int4>(), c, s->part.as<Real>(), s->sym_jpart.as<Real>());
-    HIP_TRY(s, hipGetLastError());
-    if (hipEvent_t e1 = timing_end(s, kind)) HIP_TRY(s, hipEventRecord(e1, st));
-    const dim3 rg((unsigned)((n + 255) / 256), (unsigned)P::NC);
-    hipLaunchKernelGGL((sym_reduce_kernel<Real, Tout, P::NC, BLK>), rg, dim3(256), 0, st, s->part.as<Real>(),
-                       s->sym_jpart.as<Real>(), T.slot.as<int>(), (int)n, k_factor(s), o0, o1, o2);
-    HIP_TRY(s, hipGetLastError());
+    for (int q = 0; q < nslab; ++q) {
+        const int s0 = slab[q], s1 = slab[q + 1];
+        const int t0 = T.slot_host[s0], t1 = T.slot_host[s1];
+        hipLaunchKernelGGL((sym_kernel<Real, P>), dim3((unsigned)(t1 - t0)), dim3(kSymThreads), 0, st, args, (int)n,
+                           T.task.as<int4>() + t0, t0, s0, c, s->part.as<Real>(), s->sym_jpart.as<Real>());
+        HIP_TRY(s, hipGetLastError());
+        if (q == nslab - 1)
+            if (hipEvent_t e1 = timing_end(s, kind)) HIP_TRY(s, hipEventRecord(e1, st));
+        const dim3 rg((unsigned)((n - (int64_t)s0 * BLK + 255) / 256), (unsigned)P::NC);
+        hipLaunchKernelGGL((sym_reduce_kernel<Real, Tout, P::NC, BLK>), rg, dim3(256), 0, st, s->part.as<Real>(),
+                           s->sym_jpart.as<Real>(), T.slot.as<int>(), t0, s0, s1, (int)n, k_factor(s),
+                           nslab > 1 ? s->sym_state.as<Real>() : (Real *)nullptr, o0, o1, o2);
+        HIP_TRY(s, hipGetLastError());
+    }
     return RPY_OK;
 }
 
 }  // namespace
 
-int64_t sym_max_n() { return (int64_t)1 << 18; }
+int64_t sym_max_n() { return (int64_t)1 << 18; }   // the autotuner's range for the mode
 
 // M [F; T] for the stored positions with F (and T) staged in s->f (s->t), by
 // the symmetric pair kernel; `span` = source blocks per task.

@@ -5,7 +5,9 @@ adjoint mode 2) through the C interface: Mdot against the float64 oracle
 chunk edges, with 1 to 3 source blocks per task, translational and
 angular; agreement with the ordinary kernel; the Lanczos square root
 through the same mode; the adjoint against the oracle's gradient and the
-one-sided kernel; the size limits and mode checks."""
+one-sided kernel; partials produced and reduced in several slabs of target
+blocks (forced small by RPY_SYM_SLAB_BLOCKS) against one slab and the
+oracle; sampled rows above N = 2^18; the mode checks."""
 import math
 
 import numpy as np
@@ -80,15 +82,73 @@ def test_symmetric_mode_lanczos_and_repeatability(dtype):
     assert torch.equal(a1, a2) and torch.equal(b1, b2)
 
 
-def test_symmetric_mode_size_limit():
-    import paper_2510_02135_amd as rpy
-    say("case symmetric size limit")
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("angular", [False, True])
+@pytest.mark.parametrize("slab_blocks", [1, 2])
+def test_symmetric_mode_slabs(dtype, angular, slab_blocks, monkeypatch):
+    """Partials of at most `slab_blocks` target blocks at a time (the running
+    sums carried between slabs): forward product and adjoint against the
+    oracle and against the same products in one slab."""
+    from oracle import gradient
+    n = 2900
+    say(f"case symmetric slabs of {slab_blocks} blocks n={n} angular={angular} {dtype}")
+    rng = np.random.default_rng(960 + slab_blocks)
+    x = (rng.random((n, 3)) - 0.5) * workloads.cube_side(n, 0.2, 1.1)
+    F, GU = rng.standard_normal((2, n, 3))
+    T, GW = (rng.standard_normal((2, n, 3)) if angular else (None, None))
+    sol = _solver(angular)
+    sol.setPositions(to_dev(x, dtype))
+    args = [to_dev(v, dtype) for v in (F, T, GU, GW)]
+    sol.setTileConfig(angular, 0, 1)
+    sol.setAdjointMode(2)
+    monkeypatch.delenv("RPY_SYM_SLAB_BLOCKS", raising=False)
+    one_f = sol.Mdot(args[0], args[1])
+    one_b = sol.Mdot_backward(*args)
+    monkeypatch.setenv("RPY_SYM_SLAB_BLOCKS", str(slab_blocks))
+    many_f = sol.Mdot(args[0], args[1])
+    many_b = sol.Mdot_backward(*args)
+    monkeypatch.delenv("RPY_SYM_SLAB_BLOCKS")
+    xr = rounded(x, dtype)
+    fr, tr, gur, gwr = (rounded(v, dtype) if v is not None else None for v in (F, T, GU, GW))
+    u, w = mobility.mdot_dense(xr, fr, tr, 1.1, 0.8)
+    gx = gradient.grad_positions(xr, fr, tr, gur, gwr, 1.1, 0.8)
+    mg_u, mg_w = mobility.mdot_dense(xr, gur, gwr, 1.1, 0.8)
+    e = max(emax(host(many_f[0]), u), emax(host(many_b[0]), gx), emax(host(many_b[1]), mg_u))
+    d = max(emax(host(many_f[0]), host(one_f[0])), emax(host(many_b[0]), host(one_b[0])),
+            emax(host(many_b[1]), host(one_b[1])))
+    if angular:
+        e = max(e, emax(host(many_f[1]), w), emax(host(many_b[2]), mg_w))
+        d = max(d, emax(host(many_f[1]), host(one_f[1])), emax(host(many_b[2]), host(one_b[2])))
+    say(f"  e_max vs oracle {e:.2e}, vs one slab {d:.2e}")
+    assert e <= tol_for(dtype)
+    assert d <= 2 * tol_for(dtype)
+
+
+def test_symmetric_mode_above_2_18_sampled_rows():
+    """N = 2^18 + 1 (float32, translational) through the symmetric forward
+    product and the symmetric adjoint, whose partials exceed one slab's
+    workspace here: sampled rows against the oracle."""
+    from oracle import gradient, pairloop
     n = (1 << 18) + 1
-    sol = _solver(False)
-    sol.setPositions(torch.arange(3 * n, dtype=torch.float32, device="cuda").reshape(n, 3))
+    say(f"case symmetric mode n={n}")
+    rng = np.random.default_rng(970)
+    x = (rng.random((n, 3)) - 0.5) * workloads.cube_side(n, 0.1)
+    F, GU = rng.standard_normal((2, n, 3))
+    f32 = torch.float32
+    sol = _solver(False, 1.0, 1.0 / (6 * math.pi))
+    sol.setPositions(to_dev(x, f32))
     sol.setTileConfig(False, 0, 0)
-    with pytest.raises(rpy.RpyError):
-        sol.Mdot(torch.zeros((n, 3), dtype=torch.float32, device="cuda"))
+    sol.setAdjointMode(2)
+    lin, _ = sol.Mdot(to_dev(F, f32))
+    gp, gf, _ = sol.Mdot_backward(to_dev(F, f32), None, to_dev(GU, f32), None)
+    rows = np.sort(rng.choice(n, 16, replace=False))
+    xr, fr, gr = rounded(x, f32), rounded(F, f32), rounded(GU, f32)
+    u, _ = pairloop.mdot_rows(xr, rows, fr, None, 1.0, 1.0 / (6 * math.pi))
+    mg, _ = pairloop.mdot_rows(xr, rows, gr, None, 1.0, 1.0 / (6 * math.pi))
+    dx = gradient.grad_positions(xr, fr, None, gr, None, 1.0, 1.0 / (6 * math.pi), rows=rows[:4], chunk=1)
+    e = max(emax(host(lin)[rows], u), emax(host(gf)[rows], mg), emax(host(gp)[rows[:4]], dx))
+    say(f"  sampled e_max {e:.2e}")
+    assert e <= 1e-5
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
@@ -133,9 +193,3 @@ def test_adjoint_mode_checks():
     for bad in (-1, 3):
         with pytest.raises(rpy.RpyError):
             sol.setAdjointMode(bad)
-    n = (1 << 18) + 1
-    sol.setPositions(torch.arange(3 * n, dtype=torch.float32, device="cuda").reshape(n, 3))
-    sol.setAdjointMode(2)
-    z = torch.zeros((n, 3), dtype=torch.float32, device="cuda")
-    with pytest.raises(rpy.RpyError):
-        sol.Mdot_backward(z, None, z, None)
