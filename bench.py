@@ -397,11 +397,11 @@ def main():
 
     # ---- the N = 16,384, phi = 0.2 gradient workload: loss
     # 0.5 |M(X) F - M(X + delta) F|^2, its backward against the forward
-    gradient = None
+    grad_c3 = None
     if not args.no_breakdown:
         print("bench: N=16384 phi=0.2 backward vs forward", file=sys.stderr, flush=True)
         c3 = workloads.c3_gradient()
-        gradient = {"workload": f"{c3.name}: uniform cube, seed 1003, translational, target M(X + delta) F"}
+        grad_c3 = {"workload": f"{c3.name}: uniform cube, seed 1003, translational, target M(X + delta) F"}
         for dt, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
             so = rpy.Solver()
             so.initialize(viscosity=c3.viscosity, hydrodynamicRadius=c3.radius, includeAngular=False)
@@ -413,7 +413,7 @@ def main():
             g = (so.Mdot(forces=Fd)[0] - target).contiguous()
             tf = timed(lambda: so.Mdot(forces=Fd), 10, stream, warmup=3)
             tb = timed(lambda: so.Mdot_backward(Fd, None, g, None), 10, stream, warmup=3)
-            gradient[name] = {"mdot_ms": round(tf, 4), "backward_ms": round(tb, 4),
+            grad_c3[name] = {"mdot_ms": round(tf, 4), "backward_ms": round(tb, 4),
                               "backward_over_forward": round(tb / tf, 3)}
             so.close()
 
@@ -573,7 +573,7 @@ def main():
         "cpu_baseline": cpu,
         "lanczos_vector_ops": lanczos_cgs,
         "breakdown": breakdown,
-        "gradient_n16384": gradient,
+        "gradient_n16384": grad_c3,
         "accuracy_vs_fp64_oracle": acc,
         "batched": batched,
         "chains": chains,
