@@ -65,79 +65,65 @@ __device__ __forceinline__ double from_next_lane(double v) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Both directions of one angular pair in the regrouped form of interact_ang
-// (rpy_device.hpp).  d = X_i - X_j.  Source records of j: p = (x, y, z, F'x),
-// f = (F, F'y), t = (T, F'z), h = (T~, 0); the target's own records (fi, ti,
-// hi, fpx_i) feed the reversed direction, where d -> -d flips the cross
-// products and leaves (d.F) d unchanged.
+// Coefficients of one angular pair in the direct form: with d = X_i - X_j
+// and e = G d,
+//   U_i += A F_j + f1 (d.F_j) e + T_j x e,   W_i += D T_j + f2 (d.T_j) e + F_j x e
+// (eq. (block_mobility) in k-units: far field A = 1/r + (2a^2/3)/r^3,
+// f1 = 1 - 2a^2/r^2, G = 1/r^3, D = -G/2, f2 = 3/(2r^2); the overlap branch
+// r < 2a takes its own A, B/G, G, D, E/G; r = 0 gives the self blocks).
+// The reversed direction (target j, source i) has d -> -d: the same A, D and
+// (d.V) e terms, and the cross products change sign.
 template <typename Real>
-__device__ __forceinline__ void sym_ang(Real xi, Real yi, Real zi, const vec4_t<Real> &p, const vec4_t<Real> &f,
-                                        const vec4_t<Real> &t, const vec4_t<Real> &h, Real fpxi,
-                                        const vec4_t<Real> &fi, const vec4_t<Real> &ti, const vec4_t<Real> &hi,
-                                        const PairConst<Real> &c, Real *u, Real *w, Real *uj, Real *wj) {
-    const Real dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
-    const Real r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+struct AngPair {
+    Real dx, dy, dz, ex, ey, ez, A, f1, f2, D;
+};
+
+template <typename Real>
+__device__ __forceinline__ AngPair<Real> ang_pair(Real xi, Real yi, Real zi, const vec4_t<Real> &p,
+                                                  const PairConst<Real> &c) {
+    AngPair<Real> q;
+    q.dx = xi - p.x;
+    q.dy = yi - p.y;
+    q.dz = zi - p.z;
+    const Real r2 = fma(q.dx, q.dx, fma(q.dy, q.dy, q.dz * q.dz));
     const Real ri = rsq(r2);
     const Real ri2 = ri * ri;
     Real g = ri * ri2;
-    Real a1 = ri;
-    Real f1 = fma(c.m_two_a2, ri2, Real(1));
-    Real f2 = Real(1.5) * ri2;
+    q.A = fma(c.two_a2_3, g, ri);
+    q.f1 = fma(c.m_two_a2, ri2, Real(1));
+    q.f2 = Real(1.5) * ri2;
+    q.D = Real(-0.5) * g;
     if (__builtin_expect(r2 < c.four_a2, 0)) {
         const Real rs = sel_pos(r2, ri);
         const Real r = r2 * rs;
-        const Real An = fma(c.nA1, r, c.nA0);
-        const Real Bn = c.nB * rs;
         const Real Gn = fma(c.nG1, r, c.nG0);
-        const Real Dn = fma(fma(c.nD3, r * r, c.nD1), r, c.nD0);
-        const Real En = fma(c.nE_1, rs, c.nE1 * r);
         const Real inv = Real(1) / Gn;
-        a1 = fma(-c.two_a2_3, Gn, An);
-        f1 = Bn * inv;
-        f2 = En * inv;
+        q.A = fma(c.nA1, r, c.nA0);
+        q.f1 = c.nB * rs * inv;
+        q.f2 = fma(c.nE_1, rs, c.nE1 * r) * inv;
+        q.D = fma(fma(c.nD3, r * r, c.nD1), r, c.nD0);
         g = Gn;
-        const Real dd = fma(Real(0.5), Gn, Dn);
-        w[0] = fma(dd, t.x, w[0]);
-        w[1] = fma(dd, t.y, w[1]);
-        w[2] = fma(dd, t.z, w[2]);
-        wj[0] = fma(dd, ti.x, wj[0]);
-        wj[1] = fma(dd, ti.y, wj[1]);
-        wj[2] = fma(dd, ti.z, wj[2]);
     }
-    // target i from source j
-    {
-        const Real s1 = f1 * fma(dx, f.x, fma(dy, f.y, dz * f.z));
-        const Real s2 = f2 * fma(dx, t.x, fma(dy, t.y, dz * t.z));
-        const Real vux = fma(-t.z, dy, fma(t.y, dz, fma(s1, dx, p.w)));
-        const Real vuy = fma(-t.x, dz, fma(t.z, dx, fma(s1, dy, f.w)));
-        const Real vuz = fma(-t.y, dx, fma(t.x, dy, fma(s1, dz, t.w)));
-        u[0] = fma(a1, f.x, fma(g, vux, u[0]));
-        u[1] = fma(a1, f.y, fma(g, vuy, u[1]));
-        u[2] = fma(a1, f.z, fma(g, vuz, u[2]));
-        const Real vwx = fma(-f.z, dy, fma(f.y, dz, fma(s2, dx, h.x)));
-        const Real vwy = fma(-f.x, dz, fma(f.z, dx, fma(s2, dy, h.y)));
-        const Real vwz = fma(-f.y, dx, fma(f.x, dy, fma(s2, dz, h.z)));
-        w[0] = fma(g, vwx, w[0]);
-        w[1] = fma(g, vwy, w[1]);
-        w[2] = fma(g, vwz, w[2]);
-    }
-    // target j from source i (separation -d)
-    {
-        const Real s1 = f1 * fma(dx, fi.x, fma(dy, fi.y, dz * fi.z));
-        const Real s2 = f2 * fma(dx, ti.x, fma(dy, ti.y, dz * ti.z));
-        const Real vux = fma(ti.z, dy, fma(-ti.y, dz, fma(s1, dx, fpxi)));
-        const Real vuy = fma(ti.x, dz, fma(-ti.z, dx, fma(s1, dy, fi.w)));
-        const Real vuz = fma(ti.y, dx, fma(-ti.x, dy, fma(s1, dz, ti.w)));
-        uj[0] = fma(a1, fi.x, fma(g, vux, uj[0]));
-        uj[1] = fma(a1, fi.y, fma(g, vuy, uj[1]));
-        uj[2] = fma(a1, fi.z, fma(g, vuz, uj[2]));
-        const Real vwx = fma(fi.z, dy, fma(-fi.y, dz, fma(s2, dx, hi.x)));
-        const Real vwy = fma(fi.x, dz, fma(-fi.z, dx, fma(s2, dy, hi.y)));
-        const Real vwz = fma(fi.y, dx, fma(-fi.x, dy, fma(s2, dz, hi.z)));
-        wj[0] = fma(g, vwx, wj[0]);
-        wj[1] = fma(g, vwy, wj[1]);
-        wj[2] = fma(g, vwz, wj[2]);
-    }
+    q.ex = g * q.dx;
+    q.ey = g * q.dy;
+    q.ez = g * q.dz;
+    return q;
+}
+
+// Adds the contribution of force f and torque t at the other end of pair q
+// to (u, w); SIGN = -1 for the reversed direction.
+template <typename Real, int SIGN>
+__device__ __forceinline__ void ang_apply(const AngPair<Real> &q, const vec4_t<Real> &f, const vec4_t<Real> &t,
+                                          Real *u, Real *w) {
+    const Real s1 = q.f1 * fma(q.dx, f.x, fma(q.dy, f.y, q.dz * f.z));
+    const Real s2 = q.f2 * fma(q.dx, t.x, fma(q.dy, t.y, q.dz * t.z));
+    const Real sg = Real(SIGN);
+    u[0] = fma(sg * t.y, q.ez, fma(-sg * t.z, q.ey, fma(s1, q.ex, fma(q.A, f.x, u[0]))));
+    u[1] = fma(sg * t.z, q.ex, fma(-sg * t.x, q.ez, fma(s1, q.ey, fma(q.A, f.y, u[1]))));
+    u[2] = fma(sg * t.x, q.ey, fma(-sg * t.y, q.ex, fma(s1, q.ez, fma(q.A, f.z, u[2]))));
+    w[0] = fma(sg * f.y, q.ez, fma(-sg * f.z, q.ey, fma(s2, q.ex, fma(q.D, t.x, w[0]))));
+    w[1] = fma(sg * f.z, q.ex, fma(-sg * f.x, q.ez, fma(s2, q.ey, fma(q.D, t.y, w[1]))));
+    w[2] = fma(sg * f.x, q.ey, fma(-sg * f.y, q.ex, fma(s2, q.ez, fma(q.D, t.z, w[2]))));
 }
 
 // Both directions of one translational pair (U += A F + B (d.F) d; the
@@ -172,71 +158,62 @@ __device__ __forceinline__ void sym_lin(Real xi, Real yi, Real zi, const vec4_t<
 // pair evaluations (one-sided for the diagonal block, both directions
 // elsewhere)
 // ---------------------------------------------------------------------------
-// Forward product M [F; T]: records (x, y, z, F'x), (F, F'y), (T, F'z),
-// (T~, 0) of the regrouped angular pair, or position and force.
+// Forward product M [F; T]: records position, force (, torque).
 template <typename Real, bool ANG>
 struct FwdPairs {
     using R4 = vec4_t<Real>;
     static constexpr int TM = 2;                 // targets per lane
     static constexpr int NC = ANG ? 6 : 3;       // output components
-    static constexpr int NR = ANG ? 4 : 2;       // records per source
+    static constexpr int NR = ANG ? 3 : 2;       // records per source
     // float32 angular: steps not unrolled and at most 128 VGPRs, so that
-    // four waves share a SIMD (measured 1-2 % faster than two unrolled steps
-    // at three waves)
+    // four waves share a SIMD (two unrolled steps retire as many
+    // instructions per step and need 141 VGPRs, three waves)
     static constexpr int kUnroll = (ANG && std::is_same<Real, float>::value) ? 1 : 2;
     static constexpr int kMinWaves = (ANG && std::is_same<Real, float>::value) ? 4 : 1;
     struct Args {
         const R4 *pos, *frc, *trq;
     };
     struct Tgt {
-        Real x, y, z, fpx;
-        R4 f, t, h;
+        Real x, y, z;
+        R4 f, t;
     };
     __device__ static Tgt target(const Args &a, const PairConst<Real> &c, int idx, int n) {
+        (void)c;
         const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
         const R4 p = a.pos[min(idx, n - 1)];
-        R4 f = idx < n ? a.frc[idx] : zero4;
-        R4 t = (ANG && idx < n) ? a.trq[idx] : zero4;
         Tgt k;
         k.x = p.x;
         k.y = p.y;
         k.z = p.z;
-        k.fpx = c.two_a2_3 * f.x;
-        f.w = c.two_a2_3 * f.y;
-        t.w = c.two_a2_3 * f.z;
-        k.f = f;
-        k.t = t;
-        k.h = R4{Real(-0.5) * t.x, Real(-0.5) * t.y, Real(-0.5) * t.z, Real(0)};
+        k.f = idx < n ? a.frc[idx] : zero4;
+        k.t = (ANG && idx < n) ? a.trq[idx] : zero4;
         return k;
     }
+    // records of source js: position, force (, torque)
     __device__ static R4 record(const Args &a, const PairConst<Real> &c, int r, int js, int n) {
+        (void)c;
         const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
-        const bool ok = js < n;
-        const R4 p = a.pos[min(js, n - 1)];
-        const R4 f = ok ? a.frc[js] : zero4;
-        if constexpr (ANG) {
-            const R4 t = ok ? a.trq[js] : zero4;
-            if (r == 0) return R4{p.x, p.y, p.z, c.two_a2_3 * f.x};
-            if (r == 1) return R4{f.x, f.y, f.z, c.two_a2_3 * f.y};
-            if (r == 2) return R4{t.x, t.y, t.z, c.two_a2_3 * f.z};
-            return R4{Real(-0.5) * t.x, Real(-0.5) * t.y, Real(-0.5) * t.z, Real(0)};
-        } else {
-            return r == 0 ? R4{p.x, p.y, p.z, Real(0)} : R4{f.x, f.y, f.z, Real(0)};
-        }
+        if (r == 0) return a.pos[min(js, n - 1)];
+        if (js >= n) return zero4;
+        return r == 1 ? a.frc[js] : a.trq[js];
     }
     __device__ static void one_sided(const Tgt &k, const R4 *q, const PairConst<Real> &c, Real *acc) {
         if constexpr (ANG) {
-            interact_ang<Real>(k.x, k.y, k.z, q[0], q[1], q[2], q[3], c, acc, acc + 3);
+            const AngPair<Real> g = ang_pair<Real>(k.x, k.y, k.z, q[0], c);
+            ang_apply<Real, 1>(g, q[1], q[2], acc, acc + 3);
         } else {
             const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
             interact<Real, false>(k.x, k.y, k.z, q[0], q[1], zero4, c, acc, nullptr);
         }
     }
     __device__ static void both(const Tgt &k, const R4 *q, const PairConst<Real> &c, Real *acc, Real *sj) {
-        if constexpr (ANG)
-            sym_ang<Real>(k.x, k.y, k.z, q[0], q[1], q[2], q[3], k.fpx, k.f, k.t, k.h, c, acc, acc + 3, sj, sj + 3);
-        else
+        if constexpr (ANG) {
+            const AngPair<Real> g = ang_pair<Real>(k.x, k.y, k.z, q[0], c);
+            ang_apply<Real, 1>(g, q[1], q[2], acc, acc + 3);
+            ang_apply<Real, -1>(g, k.f, k.t, sj, sj + 3);
+        } else {
             sym_lin<Real>(k.x, k.y, k.z, q[0], q[1], k.f, c, acc, sj);
+        }
     }
 };
 
