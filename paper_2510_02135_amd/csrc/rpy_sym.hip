@@ -28,13 +28,15 @@
 //   A reduction kernel sums, per particle, the target-side partials of its
 //   own block's tasks and the source-side partials of every block before
 //   it, in a fixed order (the result does not depend on scheduling).
-// Precision: float32 target-side sums are folded into Neumaier pairs every
-// 256 sources; the source-side sums of one (I, chunk) are plain float32
-// over 512 targets; the reduction uses Neumaier pairs and float64 at the
-// end.  float64 runs plain double sums throughout.
-// Memory: the source-side partials take (N / 512) x NC x N values, so the
-// mode is offered up to N = 2^18 (about 3 GB in float64 with angular
-// blocks).
+// Precision: float32 target-side sums are folded into Neumaier pairs after
+// every chunk of 64 sources (the angular pair adds four rounded terms to
+// each running component, so shorter plain runs keep the error at that of
+// the ordinary kernel); the source-side sums of one (I, chunk) are plain
+// float32 over 512 targets; the reduction uses Neumaier pairs and float64
+// at the end.  float64 runs plain double sums throughout.
+// Memory: the source-side partials take (N / 512) x NC x N values and the
+// target-side ones 2 NC 512 per task; large N is handled in slabs of
+// target blocks whose partials fit a fixed workspace.
 #include "rpy_adjoint.hpp"
 #include "rpy_device.hpp"
 #include "rpy_internal.hpp"
@@ -50,7 +52,7 @@ namespace {
 
 constexpr int kSymThreads = 256;   // 4 wavefronts; blocks of 256 x (targets per lane) particles
 constexpr int kSymChunk = 64;      // sources per LDS chunk
-constexpr int kSymFold = 4;        // chunks between float32 folds (256 sources)
+constexpr int kSymFold = 1;        // chunks between float32 folds (64 sources)
 
 // The value lane (l + 1) mod 64 holds, for lane l: a DPP wavefront rotate
 // by one lane (control 0x134, every row and bank enabled).  The caller runs
