@@ -352,7 +352,11 @@ def main():
                 "traffic": hbm_traffic(kernel_name, n, tiles[1]),
                 "kernel": kernel_label,
                 "avg_launch_ms": round(avg_pair_ms, 4),
-                "launches": pair_launches, "flops_per_pair": FLOPS_PER_PAIR["angular"]}
+                "launches": pair_launches, "flops_per_pair": FLOPS_PER_PAIR["angular"],
+                "flops_counted_per": "ordered pair of the direct formulation (N^2 per product)"}
+    if tiles[1][0] == 0:
+        roofline["note"] = ("symmetric mode: each unordered pair's geometry is evaluated once, so the kernel "
+                            "executes fewer flops than counted; achieved is its effective rate")
 
     # Lanczos vector operations: the two classical Gram-Schmidt passes of
     # every iteration (HBM-bound), algorithmic bytes over their event time
