@@ -468,7 +468,9 @@ def main():
             so.close()
             del Fm, Tm
 
-    # ---- bead chains, N = 1,048,576: one angular float32 product ----------
+    # ---- bead chains, N = 1,048,576: one angular float32 product, with the
+    # default tiles and with the symmetric mode (tuning would take longer
+    # than the product), the faster reported --------------------------------
     chains = None
     if not args.no_batch:
         print("bench: bead chains N=1048576", file=sys.stderr, flush=True)
@@ -477,10 +479,15 @@ def main():
         sc.initialize(viscosity=c5.viscosity, hydrodynamicRadius=c5.radius, includeAngular=True)
         sc.setPositions(dev_t(c5.pos, torch.float32))
         Fc, Tc = dev_t(c5.forces, torch.float32), dev_t(c5.torques, torch.float32)
-        tc = timed(lambda: sc.Mdot(forces=Fc, torques=Tc), 2, stream, warmup=1)
+        by_cfg = {}
+        for cfg in (tuple(sc.tileConfig(True)), (0, 0)):
+            sc.setTileConfig(True, *cfg)
+            by_cfg[cfg] = timed(lambda: sc.Mdot(forces=Fc, torques=Tc), 2, stream, warmup=1)
+        best = min(by_cfg, key=by_cfg.get)
+        tc = by_cfg[best]
         chains = {"n": c5.n, "workload": "4096 random-walk chains x 256 beads, bond 2.1a, phi 0.05, seed 1005",
                   "mdot_angular_fp32_ms": round(tc, 3), "pairs_per_s": float(c5.n) ** 2 / (tc * 1e-3),
-                  "tiles": sc.tileConfig(True)}
+                  "tiles": list(best), "mdot_ms_by_tiles": {f"{k[0]},{k[1]}": round(v, 3) for k, v in by_cfg.items()}}
         sc.close()
         del Fc, Tc
 
