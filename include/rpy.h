@@ -389,8 +389,9 @@ void rpy_batch_destroy(rpy_batch *b);
  * number of 512-particle source blocks per task (0 = automatic); its
  * partials ((N/512) x 6 x N source-side values plus the target-side ones)
  * are produced and reduced in slabs of target blocks of at most about
- * 8 GiB of workspace each.  Results do not depend on the configuration
- * beyond float rounding order.
+ * 8 GiB of workspace each (the environment variable RPY_SYM_SLAB_BLOCKS=m
+ * also caps a slab at m blocks, for testing).  Results do not depend on
+ * the configuration beyond float rounding order.
  */
 rpy_status rpy_set_tile_config(rpy_solver *s, int angular, int targets_per_lane, int source_splits);
 rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_per_lane, int *source_splits);
