@@ -2,7 +2,9 @@
 use, against the float64 oracle on sampled outputs, else through properties
 that hold at any size:
 
-* N = 65,536 suspension (phi = 0.1), float32 pairs: Lanczos at a matched
+* N = 65,536 suspension (phi = 0.1), float32 pairs in the launch
+  configuration the benchmark's autotuner picks there (the symmetric pair
+  mode, one source block per task): Lanczos at a matched
   iteration count against the oracle's Lanczos with C pair-loop products,
   and at convergence the norm identity |y|^2 = W^T M W (M applied by the
   oracle pair loop on sampled rows would not give it; the float64 GPU
@@ -47,6 +49,7 @@ def test_c2_lanczos_matched_iterations_and_convergence():
     f32 = torch.float32
     sol = _solver(True)
     sol.setPositions(torch.tensor(s.pos, dtype=f32, device="cuda"))
+    sol.setTileConfig(True, 0, 1)
     W = torch.tensor(s.w, dtype=f32, device="cuda")
     # matched iterations: 5 Lanczos steps, oracle products from the C pair loop
     try:
@@ -70,6 +73,7 @@ def test_c2_lanczos_matched_iterations_and_convergence():
     y32 = _flat(lin, ang)
     sol64 = _solver(True)
     sol64.setPositions(torch.tensor(xr, dtype=torch.float64, device="cuda"))
+    sol64.setTileConfig(True, 0, 1)
     W64 = torch.tensor(wr, dtype=torch.float64, device="cuda")
     lin64, ang64 = sol64.sqrtMdotW(W64, tol=1e-6)
     y64 = _flat(lin64, ang64)
