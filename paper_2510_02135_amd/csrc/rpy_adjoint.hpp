@@ -110,25 +110,23 @@ __device__ __forceinline__ void adj_pair(const Tgt<Real, ANG> &k, const vec4_t<R
         ox = fma(Gg, cx, fma(e1, k.hx, fma(e2, st.x, fma(e3, sh.x, fma(e4, k.tx, ox)))));
         oy = fma(Gg, cy, fma(e1, k.hy, fma(e2, st.y, fma(e3, sh.y, fma(e4, k.ty, oy)))));
         oz = fma(Gg, cz, fma(e1, k.hz, fma(e2, st.z, fma(e3, sh.z, fma(e4, k.tz, oz)))));
-        // (M g)_U += G (gWj x d);  (M g)_W += G (gUj x d) + D gWj + E (d.gWj) d
-        const Real hjx = sh.y * dz - sh.z * dy, hjy = sh.z * dx - sh.x * dz, hjz = sh.x * dy - sh.y * dx;
-        const Real gjx = sg.y * dz - sg.z * dy, gjy = sg.z * dx - sg.x * dz, gjz = sg.x * dy - sg.y * dx;
-        acc[3] = fma(G, hjx, acc[3]);
-        acc[4] = fma(G, hjy, acc[4]);
-        acc[5] = fma(G, hjz, acc[5]);
-        acc[6] = fma(G, gjx, fma(D, sh.x, fma(e4, dx, acc[6])));
-        acc[7] = fma(G, gjy, fma(D, sh.y, fma(e4, dy, acc[7])));
-        acc[8] = fma(G, gjz, fma(D, sh.z, fma(e4, dz, acc[8])));
+        // (M g)_U += G (gWj x d);  (M g)_W += G (gUj x d) + D gWj + E (d.gWj) d,
+        // the cross products taken with e = G d
+        const Real ex = G * dx, ey = G * dy, ez = G * dz;
+        acc[3] = fma(sh.y, ez, fma(-sh.z, ey, acc[3]));
+        acc[4] = fma(sh.z, ex, fma(-sh.x, ez, acc[4]));
+        acc[5] = fma(sh.x, ey, fma(-sh.y, ex, acc[5]));
+        acc[6] = fma(sg.y, ez, fma(-sg.z, ey, fma(D, sh.x, fma(e4, dx, acc[6]))));
+        acc[7] = fma(sg.z, ex, fma(-sg.x, ez, fma(D, sh.y, fma(e4, dy, acc[7]))));
+        acc[8] = fma(sg.x, ey, fma(-sg.y, ex, fma(D, sh.z, fma(e4, dz, acc[8]))));
         if constexpr (BOTH) {
             // (M g)_U,j -= G (gWk x d);  (M g)_W,j += -G (gUk x d) + D gWk + E (d.gWk) d
-            const Real hkx = k.hy * dz - k.hz * dy, hky = k.hz * dx - k.hx * dz, hkz = k.hx * dy - k.hy * dx;
-            const Real gkx = k.gy * dz - k.gz * dy, gky = k.gz * dx - k.gx * dz, gkz = k.gx * dy - k.gy * dx;
-            jacc[3] = fma(-G, hkx, jacc[3]);
-            jacc[4] = fma(-G, hky, jacc[4]);
-            jacc[5] = fma(-G, hkz, jacc[5]);
-            jacc[6] = fma(-G, gkx, fma(D, k.hx, fma(e2, dx, jacc[6])));
-            jacc[7] = fma(-G, gky, fma(D, k.hy, fma(e2, dy, jacc[7])));
-            jacc[8] = fma(-G, gkz, fma(D, k.hz, fma(e2, dz, jacc[8])));
+            jacc[3] = fma(-k.hy, ez, fma(k.hz, ey, jacc[3]));
+            jacc[4] = fma(-k.hz, ex, fma(k.hx, ez, jacc[4]));
+            jacc[5] = fma(-k.hx, ey, fma(k.hy, ex, jacc[5]));
+            jacc[6] = fma(-k.gy, ez, fma(k.gz, ey, fma(D, k.hx, fma(e2, dx, jacc[6]))));
+            jacc[7] = fma(-k.gz, ex, fma(k.gx, ez, fma(D, k.hy, fma(e2, dy, jacc[7]))));
+            jacc[8] = fma(-k.gx, ey, fma(k.gy, ex, fma(D, k.hz, fma(e2, dz, jacc[8]))));
         }
     }
     if constexpr (BOTH) {

@@ -6,13 +6,17 @@
 // pair (separation, 1/r, the coefficient functions, the overlap branch) is
 // therefore computed once and applied in both directions: to target i from
 // source j's vectors, and to target j from i's.  That saves the geometry on
-// half the ordered pairs (about 12 of the 48 instructions of an angular pair)
-// at the price of summing the source-side results.
+// half the ordered pairs (17 of the 49 instructions of an angular pair in the
+// direct form used here) at the price of summing the source-side results.
+// The same machinery serves the forward product (FwdPairs) and the adjoint
+// (AdjPairs), each a policy giving the target data, the source records and
+// the one- and two-sided pair evaluations.
 //
 // Work decomposition
-//   Particles form blocks of 512.  A task is (target block I, a range of
-//   source blocks J >= I): the lanes of its workgroup own the 512 targets
-//   of I (two per lane) in registers, and the source blocks stream through
+//   Particles form blocks of 256 x TM (512 for the forward product, 256 for
+//   the adjoint).  A task is (target block I, a range of source blocks
+//   J >= I): the lanes of its workgroup own the targets of I (TM per lane)
+//   in registers, and the source blocks stream through
 //   LDS in chunks of 64 (double-buffered: one barrier per chunk, the next
 //   chunk's records loaded while this one is evaluated).  On an
 //   off-diagonal chunk, lane l pairs its targets
