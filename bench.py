@@ -63,6 +63,8 @@ def parse():
     p.add_argument("--sweep", action="store_true",
                    help="instead of the step: Mdot time against N = 2^10 .. 2^20 at number densities 0.1 and "
                         "0.001 per a^3 (translational, float32), the axes of the paper's timing figure")
+    p.add_argument("--batch-only", action="store_true",
+                   help="instead of the step: only the 512 batched systems (one launch against one per system)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -298,6 +300,13 @@ def main():
                           "config": {"workload": "uniform cubes, N = 2^10 .. 2^20, number density 0.1 and 0.001 "
                                                  "per a^3, a = 1, eta = 1/(6 pi), seeds 2010 .. 2020"},
                           "sweep": sweep}), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"metric": "batched systems: Mdot and sqrtMdotW time (float32)", "unit": "ms",
+                          "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": "512 systems, N log-uniform in [64, 8192], phi in [0.05, 0.3], "
+                                                 "seed 1004"},
+                          "batched": bench_batched(rpy, workloads, dev, stream, timed)}), flush=True)
         return
     s = workloads.c2_suspension(args.n)
     n = s.n
