@@ -231,8 +231,10 @@ struct AdjPairs {
     static constexpr int TM = 1;
     static constexpr int NC = ANG ? 9 : 6;
     static constexpr int NR = ANG ? 5 : 3;
+    // float32 angular: at most 128 VGPRs (four waves per SIMD instead of
+    // three; the one value spilled is reloaded only on the overlap branch)
     static constexpr int kUnroll = 2;
-    static constexpr int kMinWaves = 1;
+    static constexpr int kMinWaves = (ANG && std::is_same<Real, float>::value) ? 4 : 1;
     struct Args {
         const R4 *pos, *frc, *gu, *trq, *gw;
     };
