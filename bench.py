@@ -60,11 +60,17 @@ def parse():
                    help="skip the batched-systems and bead-chain measurements")
     p.add_argument("--tile-cache", default=None,
                    help="autotune cache file (read if it has an entry, else written)")
+    p.add_argument("--tiles", default=None,
+                   help="TM,S: fixed pair-kernel tiles for the step's solver instead of autotuning "
+                        "(targets per lane, source splits; 0,B is the symmetric mode with B source blocks per task)")
+    p.add_argument("--chains-lanczos-iters", type=int, default=20,
+                   help="Lanczos iterations of the fixed-length bead-chain leg")
     p.add_argument("--sweep", action="store_true",
                    help="instead of the step: Mdot time against N = 2^10 .. 2^20 at number densities 0.1 and "
                         "0.001 per a^3 (translational, float32), the axes of the paper's timing figure")
-    p.add_argument("--batch-only", action="store_true",
-                   help="instead of the step: only the 512 batched systems (one launch against one per system)")
+    p.add_argument("--batch-only", nargs="?", const="all", default=None, choices=("all", "mdot"),
+                   help="instead of the step: only the 512 batched systems (one launch against one per system); "
+                        "'mdot' stops after the batched products")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -108,7 +114,7 @@ def hbm_traffic(kernel: str, n: int, tile):
     return None
 
 
-def bench_batched(rpy, workloads, dev, stream, timed):
+def bench_batched(rpy, workloads, dev, stream, timed, mdot_only=False):
     """512 independent systems (N log-uniform in [64, 8192], phi in [0.05, 0.3],
     seed 1004), float32: Mdot and sqrtMdotW (tol 1e-6) for all systems in one
     batched call vs one single-system solver call per system."""
@@ -126,6 +132,12 @@ def bench_batched(rpy, workloads, dev, stream, timed):
     batch_tiles = b.autotune()
     b.Mdot(F)
     t_mdot = timed(lambda: b.Mdot(F), 10, stream, warmup=3)
+    pairs = float((ns.astype(np.float64) ** 2).sum())
+    if mdot_only:
+        b.close()
+        return {"systems": len(syss), "total_particles": int(off[-1]), "sum_n2": pairs,
+                "tile_config": {"targets_per_lane": batch_tiles[0], "workgroups_per_cu": batch_tiles[1]},
+                "mdot_ms": round(t_mdot, 4), "mdot_pairs_per_s": pairs / (t_mdot * 1e-3)}
     b.sqrtMdotW(W, tol=1e-6)
     t0 = time.perf_counter()
     b.sqrtMdotW(W, tol=1e-6)
@@ -157,7 +169,6 @@ def bench_batched(rpy, workloads, dev, stream, timed):
     for so in sols:
         so.close()
     b.close()
-    pairs = float((ns.astype(np.float64) ** 2).sum())
     return {"systems": len(syss), "total_particles": int(off[-1]), "sum_n2": pairs,
             "tile_config": {"targets_per_lane": batch_tiles[0], "workgroups_per_cu": batch_tiles[1]},
             "mdot_ms": round(t_mdot, 4), "mdot_pairs_per_s": pairs / (t_mdot * 1e-3),
@@ -306,7 +317,8 @@ def main():
                           "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
                           "config": {"workload": "512 systems, N log-uniform in [64, 8192], phi in [0.05, 0.3], "
                                                  "seed 1004"},
-                          "batched": bench_batched(rpy, workloads, dev, stream, timed)}), flush=True)
+                          "batched": bench_batched(rpy, workloads, dev, stream, timed,
+                                                   mdot_only=args.batch_only == "mdot")}), flush=True)
         return
     s = workloads.c2_suspension(args.n)
     n = s.n
@@ -322,8 +334,14 @@ def main():
     sol = rpy.Solver("open", "open", "open")
     sol.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius, includeAngular=True)
     sol.setPositions(X)
-    print("bench: autotuning the pair kernel tiles", file=sys.stderr, flush=True)
-    tiles = sol.autotune(args.tile_cache)
+    if args.tiles:
+        fixed = tuple(int(v) for v in args.tiles.split(","))
+        sol.setTileConfig(False, *fixed)
+        sol.setTileConfig(True, *fixed)
+        tiles = (fixed, fixed)
+    else:
+        print("bench: autotuning the pair kernel tiles", file=sys.stderr, flush=True)
+        tiles = sol.autotune(args.tile_cache)
     if tiles[1][0] == 0:   # the symmetric pair mode (each unordered pair once)
         kernel_name = "sym_kernel<float, FwdPairs<float, true>>"
         kernel_label = f"{kernel_name} (angular, symmetric mode, {tiles[1][1]} source blocks per task)"
@@ -494,11 +512,40 @@ def main():
             by_cfg[cfg] = timed(lambda: sc.Mdot(forces=Fc, torques=Tc), 2, stream, warmup=1)
         best = min(by_cfg, key=by_cfg.get)
         tc = by_cfg[best]
+        sc.setTileConfig(True, *best)
         chains = {"n": c5.n, "workload": "4096 random-walk chains x 256 beads, bond 2.1a, phi 0.05, seed 1005",
                   "mdot_angular_fp32_ms": round(tc, 3), "pairs_per_s": float(c5.n) ** 2 / (tc * 1e-3),
                   "tiles": list(best), "mdot_ms_by_tiles": {f"{k[0]},{k[1]}": round(v, 3) for k, v in by_cfg.items()}}
+        # one backward pass (cotangents N(0, 1), seed 1007)
+        print("bench: bead chains backward", file=sys.stderr, flush=True)
+        gcu, gcw = (dev_t(v, torch.float32) for v in np.random.default_rng(1007).standard_normal((2, c5.n, 3)))
+        tb = timed(lambda: sc.Mdot_backward(Fc, Tc, gcu, gcw), 1, stream, warmup=1)
+        chains.update({"backward_ms": round(tb, 3), "backward_over_forward": round(tb / tc, 3)})
+        del gcu, gcw
+        # Lanczos run for a fixed number of iterations (the tol-1e-6 solve takes
+        # hundreds): time per iteration, and the bytes of its Gram-Schmidt passes
+        kfix = args.chains_lanczos_iters
+        print(f"bench: bead chains Lanczos, {kfix} iterations", file=sys.stderr, flush=True)
+        Wc = dev_t(c5.w, torch.float32)
+        _lib.rpy_enable_timing(sc._h, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            sc.sqrtMdotW(Wc, tol=1e-15, maxIter=kfix)
+        except rpy.NotConvergedError:
+            pass
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t0
+        cp_ms, cp_n, _ = _lib.rpy_kernel_time(sc._h, "pair")
+        cg_ms, cg_rec, cg_bytes = _lib.rpy_kernel_time(sc._h, "lanczos_cgs")
+        _lib.rpy_enable_timing(sc._h, False)
+        chains.update({"lanczos_iterations": kfix, "lanczos_ms": round(1e3 * tl, 1),
+                       "lanczos_ms_per_iteration": round(1e3 * tl / kfix, 2),
+                       "lanczos_pair_kernel_ms_per_product": round(cp_ms / max(cp_n, 1), 2),
+                       "lanczos_cgs_ms": round(cg_ms, 2), "lanczos_cgs_bytes": cg_bytes,
+                       "lanczos_cgs_gbps": round(cg_bytes / (cg_ms * 1e-3) / 1e9, 1) if cg_ms > 0 else None})
         sc.close()
-        del Fc, Tc
+        del Fc, Tc, Wc
 
     # ---- batched systems: one persistent launch vs one launch per system ----
     batched = None

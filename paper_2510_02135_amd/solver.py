@@ -399,6 +399,7 @@ class _MdotFunction(torch.autograd.Function):
         return lin, ang
 
     @staticmethod
+    @torch.autograd.function.once_differentiable
     def backward(ctx, g_lin, g_ang):
         solver = ctx.solver
         positions, forces, torques = ctx.saved_tensors
@@ -409,7 +410,10 @@ class _MdotFunction(torch.autograd.Function):
                                           need_pos=ctx.needs_input_grad[1],
                                           need_forces=ctx.needs_input_grad[2],
                                           need_torques=ctx.needs_input_grad[3] and ctx.has_t)
-        return None, gp, (gf if forces is not None else None), (gt if ctx.has_t else None)
+        gp = gp.reshape_as(positions) if gp is not None else None
+        gf = gf.reshape_as(forces) if (gf is not None and forces is not None) else None
+        gt = gt.reshape_as(torques) if (gt is not None and ctx.has_t) else None
+        return None, gp, gf, gt
 
 
 def mdot(solver: Solver, positions: torch.Tensor, forces: torch.Tensor | None,

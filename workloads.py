@@ -36,7 +36,7 @@ def cube_side(n: int, phi: float, a: float = RADIUS) -> float:
 
 @dataclass
 class Suspension:
-    """One synthetic system: float64 draws, with float32 copies made on demand."""
+    """One synthetic system: the float64 draws (float32 users round them once)."""
     name: str
     pos: np.ndarray                       # (N, 3) float64
     forces: np.ndarray                    # (N, 3) float64
@@ -50,19 +50,6 @@ class Suspension:
     @property
     def n(self) -> int:
         return int(self.pos.shape[0])
-
-    def as_dtype(self, dtype) -> "Suspension":
-        """Copy with every array rounded to ``dtype`` (float32 rounds once)."""
-        cast = (lambda a: None if a is None else np.ascontiguousarray(a, dtype=dtype))
-        return Suspension(self.name, cast(self.pos), cast(self.forces), cast(self.torques),
-                          cast(self.w), self.radius, self.viscosity, self.box,
-                          {k: (cast(v) if isinstance(v, np.ndarray) and v.dtype.kind == "f" else v)
-                           for k, v in self.extra.items()})
-
-    def rounded64(self, dtype=np.float32) -> "Suspension":
-        """The arrays rounded to ``dtype`` and promoted back to float64."""
-        s = self.as_dtype(dtype)
-        return s.as_dtype(np.float64)
 
 
 def uniform_cube(n: int, phi: float, seed: int, *, torques: bool = False,
@@ -171,7 +158,3 @@ def c5_chains(n_chains: int = 4096, beads: int = 256, bond: float = 2.1,
     s.extra["subset"] = np.sort(rng.choice(n, size=min(4096, n), replace=False))
     return s
 
-
-def scaled_chain_workload(n_chains: int, beads: int = 256, seed: int = 1005) -> Suspension:
-    """Same chain recipe at fewer chains (for tests that cannot afford 1M beads)."""
-    return c5_chains(n_chains=n_chains, beads=beads, seed=seed)
