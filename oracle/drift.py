@@ -26,11 +26,14 @@ def div_m_open(n: int, angular: bool = False):
     return np.zeros((n, 3)), (np.zeros((n, 3)) if angular else None)
 
 
-def divergence_fd(x, delta, a, eta, angular: bool = False):
+def divergence_fd(x, delta, a, eta, angular: bool = False, mobility=None):
     """Deterministic finite-difference divergence of M (the test of Sec. 4).
 
     Returns the 3N (or 6N, linear rows first) vector sum_j dM_ij/dq_j.
+    ``mobility(x, a, eta, angular)`` gives the dense matrix (default: the
+    open-boundary one).
     """
+    grand_mobility_ = grand_mobility if mobility is None else mobility
     n = x.shape[0]
     dim = 6 * n if angular else 3 * n
     out = np.zeros(dim)
@@ -39,8 +42,8 @@ def divergence_fd(x, delta, a, eta, angular: bool = False):
         xm = x.copy()
         xp.flat[j] += 0.5 * delta
         xm.flat[j] -= 0.5 * delta
-        out += (grand_mobility(xp, a, eta, angular)[:, j]
-                - grand_mobility(xm, a, eta, angular)[:, j]) / delta
+        out += (grand_mobility_(xp, a, eta, angular)[:, j]
+                - grand_mobility_(xm, a, eta, angular)[:, j]) / delta
     return out
 
 
