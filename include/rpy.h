@@ -115,6 +115,26 @@ rpy_status rpy_mdot(rpy_solver *s, const void *forces, const void *torques,
                     void *lin_out, void *ang_out, void *hip_stream);
 
 /*
+ * rpy_mdot without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, checks and result as rpy_mdot (to rounding:
+ * it always runs the ordinary one-sided pair kernel, never the symmetric
+ * mode, with the source splits of the solver's tiles lowered until its
+ * partial sums fit).  The staged forces / torques and the partial sums live
+ * in one fixed 64 MiB device array per GPU (taken on the first call made
+ * with that device current and held until the process ends), so N is
+ * limited: with S = 16 (float) or 32 (double) bytes per staged vector and P
+ * = 3 or 6 components x 4 or 8 bytes (float32 pairs keep sums and
+ * compensations: 2 x 4), N x (S x (1 or 2 vectors) + P) must not exceed
+ * 64 MiB, else RPY_ERR_INVALID_ARG (nothing enqueued).  The solver's
+ * positions are those stored by rpy_set_positions (which does allocate).
+ * Every call on one GPU shares that array: calls that overlap in time on
+ * one GPU (several streams or host threads) race on it.  Asynchronous.
+ */
+rpy_status rpy_mdot_noalloc(rpy_solver *s, const void *forces, const void *torques,
+                            void *lin_out, void *ang_out, void *hip_stream);
+
+/*
  * Several deterministic products with one geometry (an addition beside the
  * paper's method, which applies M to one vector per call; Sec. 3.3 notes
  * that a Krylov method may need several products at the same positions):

@@ -74,6 +74,7 @@ def load() -> ctypes.CDLL:
         "rpy_initialize": ([vp, d, d, i], i),
         "rpy_set_positions": ([vp, vp, i64, i, vp], i),
         "rpy_mdot": ([vp, vp, vp, vp, vp, vp], i),
+        "rpy_mdot_noalloc": ([vp, vp, vp, vp, vp, vp], i),
         "rpy_mdot_multi": ([vp, vp, vp, i, vp, vp, vp], i),
         "rpy_set_multi_config": ([vp, i], i),
         "rpy_sqrt_mdot_w": ([vp, vp, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
@@ -170,6 +171,12 @@ def rpy_mdot(h, forces, torques, lin_out, ang_out, dtype, n):
     _check(h, load().rpy_mdot(h, _ptr(forces, dtype, 3 * n, "forces"), _ptr(torques, dtype, 3 * n, "torques"),
                               _ptr(lin_out, dtype, 3 * n, "lin_out"), _ptr(ang_out, dtype, 3 * n, "ang_out"),
                               _stream(lin_out)))
+
+
+def rpy_mdot_noalloc(h, forces, torques, lin_out, ang_out, dtype, n):
+    _check(h, load().rpy_mdot_noalloc(h, _ptr(forces, dtype, 3 * n, "forces"), _ptr(torques, dtype, 3 * n, "torques"),
+                                      _ptr(lin_out, dtype, 3 * n, "lin_out"), _ptr(ang_out, dtype, 3 * n, "ang_out"),
+                                      _stream(lin_out)))
 
 
 def rpy_mdot_multi(h, forces, torques, nrhs, lin_out, ang_out, dtype, n):
