@@ -47,7 +47,7 @@ typedef struct rpy_solver rpy_solver;
 typedef enum {
     RPY_OK = 0,
     RPY_ERR_INVALID_ARG = 1,          /* null pointer, N <= 0, eta <= 0, a <= 0, bad tol ... */
-    RPY_ERR_UNSUPPORTED_GEOMETRY = 2, /* any periodicity other than open/open/open        */
+    RPY_ERR_UNSUPPORTED_GEOMETRY = 2, /* geometry not built, or call not built for it    */
     RPY_ERR_NOT_INITIALIZED = 3,      /* rpy_initialize not called yet                     */
     RPY_ERR_NO_POSITIONS = 4,         /* rpy_set_positions not called yet                  */
     RPY_ERR_SIZE_MISMATCH = 5,        /* batch sizes inconsistent                          */
@@ -67,17 +67,28 @@ typedef enum { RPY_F32 = 0, RPY_F64 = 1 } rpy_dtype;
 
 /*
  * Create a solver for the given periodicity of the x, y and z axes
- * (Sec. 3.2, constructor; Sec. 3.5: the N-body solver is open in x and y).
- * Only (open, open, open) is built; anything else returns
- * RPY_ERR_UNSUPPORTED_GEOMETRY and writes NULL.  The caller owns *out and
- * frees it with rpy_destroy.  Does not touch the GPU.
+ * (Sec. 3.2, constructor; Sec. 3.5: the N-body solver is open in x and y,
+ * and open or single_wall in z).  (open, open, open) gives the free-space
+ * RPY blocks; (open, open, single_wall) the Swan-Brady kernel: RPY blocks
+ * for a no-slip plane at z = wallHeight (rpy_set_parameter), built from the
+ * Stokeslet and Blake's image system with Faxen corrections, with the
+ * damping that keeps M positive definite for particles overlapping the
+ * wall (Sec. 3.5): heights h = z - wallHeight are raised to max(h, a) and
+ * particle i's rows and columns are scaled by min(max(h_i / a, 0), 1).
+ * Anything else returns RPY_ERR_UNSUPPORTED_GEOMETRY and writes NULL.  The
+ * caller owns *out and frees it with rpy_destroy.  Does not touch the GPU.
+ * Above a wall, rpy_mdot, rpy_mdot_multi, rpy_sqrt_mdot_w(_multi),
+ * rpy_div_m_rfd, rpy_mobility_solve and the deterministic (kbt = 0) time
+ * steps work; rpy_div_m, rpy_mdot_backward, rpy_mdot_noalloc and the
+ * stochastic (kbt > 0) time steps return RPY_ERR_UNSUPPORTED_GEOMETRY.
  */
 rpy_status rpy_create(rpy_periodicity x, rpy_periodicity y, rpy_periodicity z, rpy_solver **out);
 
 /*
- * Domain-specific parameter by name (Sec. 3.2, setParameters: e.g. the wall
- * height of wall geometries).  Open boundaries have none, so every key
- * returns RPY_ERR_INVALID_ARG.
+ * Domain-specific parameter by name (Sec. 3.2, setParameters).  The
+ * single_wall geometry takes "wallHeight" (finite; default 0), the z of the
+ * wall (particles live above it).  Open boundaries have none.  Any other key
+ * or a non-finite value returns RPY_ERR_INVALID_ARG.
  */
 rpy_status rpy_set_parameter(rpy_solver *s, const char *key, double value);
 
@@ -230,7 +241,10 @@ rpy_status rpy_mobility_solve(rpy_solver *s, const void *u_lin, const void *u_an
  * Thermal drift d_X . M (Sec. 3.2, divM; third term of eq. (bdhi)).  In an
  * unbounded fluid M is translation invariant and isotropic, so the
  * divergence vanishes (Sec. 2, Sec. 3.4): writes zeros to lin_out (n x 3)
- * and to ang_out when given (requires include_angular).  Asynchronous.
+ * and to ang_out when given (requires include_angular).  Above a wall the
+ * drift does not vanish and needs a random vector: this call returns
+ * RPY_ERR_UNSUPPORTED_GEOMETRY there, and rpy_div_m_rfd (eq. (rfd), the
+ * paper's default for such solvers, Sec. 3.4) computes it.  Asynchronous.
  */
 rpy_status rpy_div_m(rpy_solver *s, void *lin_out, void *ang_out, void *hip_stream);
 
@@ -429,7 +443,10 @@ rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_pe
  * configuration (<ms> below is its time per product).  With cache_path
  * != NULL the choice is looked up in / added to a text file of lines
  *   <arch>|<f32|f64>|<lin|ang>|<round(log2 N)> <targets_per_lane> <splits> <ms>
- * (a cached entry is used without timing).  Synchronises hip_stream.
+ * (a cached entry is used without timing).  Synchronises hip_stream.  A
+ * single_wall solver is not timed: its tile configuration is reset to the
+ * defaults of the wall kernel (two targets per lane, one with the angular
+ * blocks; splits from N).
  */
 rpy_status rpy_autotune(rpy_solver *s, const char *cache_path, void *hip_stream);
 

@@ -40,6 +40,9 @@ int splits_for(const rpy_solver *s, bool ang) {
 // Output type Tout: the caller's dtype, or double for Lanczos products.
 template <typename Real, typename Tout>
 rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *angout, hipStream_t st, const void *pos_in) {
+    if (s->wall)
+        return apply_wall<Real, Tout>(s, ang, s->f.as<vec4_t<Real>>(), s->t.as<vec4_t<Real>>(), lin, angout, st,
+                                      pos_in);
     if (s->cfg[ang ? 1 : 0].tm == 0) return apply_sym<Real, Tout>(s, ang, s->cfg[ang ? 1 : 0].n_split, lin, angout, st, pos_in);
     const int64_t n = s->n;
     const int splits = splits_for(s, ang);
@@ -126,19 +129,28 @@ rpy_status rpy_create(rpy_periodicity x, rpy_periodicity y, rpy_periodicity z, r
     *out = nullptr;
     for (rpy_periodicity p : {x, y, z})
         if ((int)p < (int)RPY_PERIODIC || (int)p > (int)RPY_TWO_WALLS) return RPY_ERR_INVALID_ARG;
-    if (x != RPY_OPEN || y != RPY_OPEN || z != RPY_OPEN) return RPY_ERR_UNSUPPORTED_GEOMETRY;
+    if (x != RPY_OPEN || y != RPY_OPEN || (z != RPY_OPEN && z != RPY_SINGLE_WALL)) return RPY_ERR_UNSUPPORTED_GEOMETRY;
     rpy_solver *s = new (std::nothrow) rpy_solver();
     if (!s) return RPY_ERR_OUT_OF_MEMORY;
     s->per[0] = x;
     s->per[1] = y;
     s->per[2] = z;
+    s->wall = z == RPY_SINGLE_WALL;
     *out = s;
     return RPY_OK;
 }
 
 rpy_status rpy_set_parameter(rpy_solver *s, const char *key, double value) {
-    (void)value;
     if (!s || !key) return RPY_ERR_INVALID_ARG;
+    if (s->wall && std::strcmp(key, "wallHeight") == 0) {
+        if (!std::isfinite(value)) return fail(s, RPY_ERR_INVALID_ARG, "wallHeight must be finite");
+        s->wall_height = value;
+        s->err.clear();
+        return RPY_OK;
+    }
+    if (s->wall)
+        return fail(s, RPY_ERR_INVALID_ARG,
+                    std::string("the single-wall geometry takes only 'wallHeight' (got '") + key + "')");
     return fail(s, RPY_ERR_INVALID_ARG,
                 std::string("open boundaries take no domain parameters (got '") + key + "')");
 }
@@ -208,6 +220,9 @@ rpy_status rpy_div_m(rpy_solver *s, void *lin_out, void *ang_out, void *hip_stre
     if (r != RPY_OK) return r;
     if (!lin_out) return fail(s, RPY_ERR_INVALID_ARG, "linear output pointer is NULL");
     if (ang_out && !s->angular) return fail(s, RPY_ERR_ANGULAR_DISABLED, "angular output needs include_angular");
+    if (s->wall)
+        return fail(s, RPY_ERR_UNSUPPORTED_GEOMETRY,
+                    "the drift above a wall is not zero: use rpy_div_m_rfd (random finite differences)");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     // open space: d_X . M = 0 for the linear and the angular rows
     if (s->dtype == RPY_F64) {

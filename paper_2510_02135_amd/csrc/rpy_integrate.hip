@@ -120,6 +120,9 @@ rpy_status check_step_args(rpy_solver *s, const void *w, double dt, double kbt, 
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(s, RPY_ERR_INVALID_ARG, "dt must be positive and finite");
     if (!(kbt >= 0.0) || !std::isfinite(kbt)) return fail(s, RPY_ERR_INVALID_ARG, "kbt must be >= 0 and finite");
     if (kbt > 0.0) {
+        if (s->wall)
+            return fail(s, RPY_ERR_UNSUPPORTED_GEOMETRY,
+                        "kbt > 0 above a wall needs the thermal drift, which this step does not include");
         if (!w) return fail(s, RPY_ERR_INVALID_ARG, "kbt > 0 needs the noise vector W");
         if (!(tol > 0.0 && tol < 1.0)) return fail(s, RPY_ERR_INVALID_ARG, "tol must be in (0, 1)");
         if (max_iter < 1) return fail(s, RPY_ERR_INVALID_ARG, "max_iter must be >= 1");

@@ -75,6 +75,8 @@ int source_tile();
 // Opaque solver object behind the C interface.
 struct rpy_solver {
     rpy_periodicity per[3] = {RPY_OPEN, RPY_OPEN, RPY_OPEN};
+    bool wall = false;          // (open, open, single_wall): Swan-Brady kernel with damping
+    double wall_height = 0.0;   // z of the wall (rpy_set_parameter "wallHeight")
     bool initialized = false;
     double eta = 0.0, radius = 0.0;
     bool angular = false;

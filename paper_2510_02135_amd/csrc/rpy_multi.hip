@@ -404,6 +404,17 @@ template <typename Real, typename Tout>
 rpy_status apply_staged_multi(rpy_solver *s, bool ang, int nrhs, Tout *lin, Tout *ang_out, int64_t ostride,
                               hipStream_t st) {
     const int64_t n = s->n;
+    if (s->wall) {
+        // one wall product per vector
+        for (int r = 0; r < nrhs; ++r) {
+            rpy_status rs = apply_wall<Real, Tout>(s, ang, s->f.as<vec4_t<Real>>() + (size_t)r * n,
+                                                   ang ? s->t.as<vec4_t<Real>>() + (size_t)r * n : nullptr,
+                                                   lin + (size_t)r * ostride,
+                                                   ang_out ? ang_out + (size_t)r * ostride : nullptr, st);
+            if (rs != RPY_OK) return rs;
+        }
+        return RPY_OK;
+    }
     const int splits = splits_for(s, ang);
     const int pc_count = (ang ? 6 : 3) * (std::is_same<Real, float>::value ? 2 : 1);
     HIP_TRY(s, s->part.ensure((size_t)splits * nrhs * pc_count * n * sizeof(Real)));

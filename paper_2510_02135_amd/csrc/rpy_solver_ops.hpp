@@ -26,6 +26,13 @@ template <typename Real, typename Tout>
 rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *ang_out, hipStream_t st,
                         const void *pos = nullptr);
 
+// M [F; T] above the wall of a single_wall solver (rpy_wall.hip), with the
+// staged vectors f (and t) given explicitly; otherwise as apply_staged.
+template <typename Real, typename Tout>
+rpy_status apply_wall(rpy_solver *s, bool ang, const vec4_t<Real> *f, const vec4_t<Real> *t, Tout *lin,
+                      Tout *ang_out, hipStream_t st, const void *pos = nullptr);
+int wall_targets_per_lane(const rpy_solver *s, bool ang);
+
 // M [F; T] by the symmetric pair kernel (each unordered pair once), with
 // F, T staged as for apply_staged; `span` source blocks per task (0 =
 // automatic).  Large N runs in slabs of target blocks whose partials fit a

@@ -18,11 +18,14 @@ from ._lib import NotConvergedError
 
 
 class Solver:
-    """Open-boundary RPY N-body mobility solver on one HIP device."""
+    """RPY N-body mobility solver on one HIP device: open boundaries, or
+    ("open", "open", "single_wall") for a no-slip wall at z = wallHeight
+    (setParameters(wallHeight=...), default 0)."""
 
     def __init__(self, periodicityX: str = "open", periodicityY: str = "open",
                  periodicityZ: str = "open"):
         self._h = _lib.rpy_create(periodicityX, periodicityY, periodicityZ)
+        self.periodicity = (periodicityX, periodicityY, periodicityZ)
         self._n = 0
         self._dtype = None
         self._device = None
@@ -180,9 +183,13 @@ class Solver:
             return f[0], (t[0] if t is not None else None)
         return f, t
 
-    def divM(self):
-        """Thermal drift: zero in an unbounded fluid."""
+    def divM(self, generator: torch.Generator | None = None):
+        """Thermal drift d_X . M: zero in an unbounded fluid; above a wall one
+        random finite difference (divM_rfd with a drawn W), as the paper's
+        default for solvers whose drift does not vanish (Sec. 3.4)."""
         self._require_positions()
+        if self.periodicity[2] == "single_wall":
+            return self.divM_rfd(generator=generator)
         lin = self._empty()
         ang = self._empty() if self._angular else None
         _lib.rpy_div_m(self._h, lin, ang, self._dtype, self._n)

@@ -57,7 +57,10 @@ def _solver(lib):
 
 def test_geometry_checks(lib):
     out = ctypes.c_void_p(123)
-    assert lib.rpy_create(1, 1, 2, ctypes.byref(out)) == GEOM and not out.value
+    assert lib.rpy_create(1, 1, 2, ctypes.byref(out)) == OK and out.value   # open, open, single_wall
+    lib.rpy_destroy(out)
+    out = ctypes.c_void_p(123)
+    assert lib.rpy_create(2, 1, 1, ctypes.byref(out)) == GEOM and not out.value
     assert lib.rpy_create(0, 0, 0, ctypes.byref(out)) == GEOM
     assert lib.rpy_create(1, 1, 3, ctypes.byref(out)) == GEOM
     assert lib.rpy_create(1, 1, 7, ctypes.byref(out)) == INVALID

@@ -158,3 +158,33 @@ def c5_chains(n_chains: int = 4096, beads: int = 256, bond: float = 2.1,
     s.extra["subset"] = np.sort(rng.choice(n, size=min(4096, n), replace=False))
     return s
 
+
+
+def wall_suspension(n: int, seed: int, *, hg: float = 1.5, phi2d: float = 0.11, overlap: float = 0.05,
+                    torques: bool = False, w: bool = False, angular_w: bool = False,
+                    wall_height: float = 0.0) -> Suspension:
+    """Particles above a no-slip wall at z = wall_height (a monolayer-like
+    layer, as in the paper's rollers and wall-diffusion examples).
+
+    In-plane positions uniform in a square of side L = sqrt(N pi a^2 / phi2d)
+    (in-plane packing fraction phi2d, centred at the origin); heights above
+    the wall a + Exp(hg - a), the Gibbs-Boltzmann distribution of a
+    sedimented sphere with gravitational height hg (the paper's rollers use
+    hg = 1.5a and 6.1a), except a fraction ``overlap`` of the particles,
+    chosen at random, whose heights are uniform in (0, a): they overlap the
+    wall.  Draw order: in-plane positions, heights, overlap flags and their
+    heights, forces, torques, W.
+    """
+    rng = np.random.default_rng(seed)
+    side = math.sqrt(n * math.pi * RADIUS ** 2 / phi2d)
+    xy = (rng.random((n, 2)) - 0.5) * side
+    h = RADIUS + rng.exponential((hg - 1.0) * RADIUS, n)
+    low = rng.random(n) < overlap
+    h = np.where(low, rng.random(n) * RADIUS, h)
+    pos = np.column_stack([xy, wall_height + h])
+    forces = rng.standard_normal((n, 3))
+    tq = rng.standard_normal((n, 3)) if torques else None
+    wv = rng.standard_normal(6 * n if angular_w else 3 * n) if w else None
+    s = Suspension(f"wall_n{n}_hg{hg}_s{seed}", pos, forces, tq, wv, box=side)
+    s.extra.update(wall_height=wall_height)
+    return s
