@@ -45,6 +45,8 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBPS = 8000.0       # MI355X HBM3E
 FLOPS_PER_PAIR = {"linear": 34, "angular": 84}
+# single-wall geometry: the open pair plus the image part of the wall kernel
+FLOPS_PER_WALL_PAIR = {"linear": 131, "angular": 305}
 
 
 def parse():
@@ -133,11 +135,32 @@ def bench_batched(rpy, workloads, dev, stream, timed, mdot_only=False):
     b.Mdot(F)
     t_mdot = timed(lambda: b.Mdot(F), 10, stream, warmup=3)
     pairs = float((ns.astype(np.float64) ** 2).sum())
+    # the same systems with angular blocks (torques N(0, 1), seed 1009; 6N noise)
+    rng_a = np.random.default_rng(1009)
+    Ta = torch.tensor(rng_a.standard_normal((int(off[-1]), 3)), dtype=f32, device=dev)
+    Wa = torch.tensor(rng_a.standard_normal(6 * int(off[-1])), dtype=f32, device=dev)
+    ba = rpy.Batch(off, workloads.VISCOSITY, workloads.RADIUS, f32, includeAngular=True)
+    ba.setPositions(X)
+    ba.Mdot(F, Ta)
+    t_mdot_ang = timed(lambda: ba.Mdot(F, Ta), 10, stream, warmup=3)
+    angular = {"mdot_ms": round(t_mdot_ang, 4), "mdot_pairs_per_s": pairs / (t_mdot_ang * 1e-3),
+               "tile_config": "block mode"}
     if mdot_only:
         b.close()
+        ba.close()
         return {"systems": len(syss), "total_particles": int(off[-1]), "sum_n2": pairs,
                 "tile_config": {"targets_per_lane": batch_tiles[0], "workgroups_per_cu": batch_tiles[1]},
-                "mdot_ms": round(t_mdot, 4), "mdot_pairs_per_s": pairs / (t_mdot * 1e-3)}
+                "mdot_ms": round(t_mdot, 4), "mdot_pairs_per_s": pairs / (t_mdot * 1e-3), "angular": angular}
+    ba.sqrtMdotW(Wa, tol=1e-6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ba.sqrtMdotW(Wa, tol=1e-6)
+    torch.cuda.synchronize()
+    angular["sqrt_ms"] = round(1e3 * (time.perf_counter() - t0), 3)
+    ita = np.array(ba.last_iterations)
+    angular["lanczos_iterations"] = {"min": int(ita.min()), "median": float(np.median(ita)), "max": int(ita.max())}
+    ba.close()
+    del Ta, Wa
     b.sqrtMdotW(W, tol=1e-6)
     t0 = time.perf_counter()
     b.sqrtMdotW(W, tol=1e-6)
@@ -176,7 +199,7 @@ def bench_batched(rpy, workloads, dev, stream, timed, mdot_only=False):
             "sqrt_ms": round(t_sqrt, 3), "sqrt_per_system_launches_ms": round(t_sqrt_ps, 3),
             "lanczos_iterations": {"min": int(iters.min()), "median": float(np.median(iters)),
                                    "max": int(iters.max())},
-            "per_system_lanczos_iterations_median": float(np.median(it_ps))}
+            "per_system_lanczos_iterations_median": float(np.median(it_ps)), "angular": angular}
 
 
 def oracle_timings(workloads, pairloop):
@@ -456,6 +479,37 @@ def main():
                               "backward_over_forward": round(tb / tf, 3)}
             so.close()
 
+    # ---- single wall (NBody with a no-slip wall): N = 32,768 particles in a
+    # layer above the wall (the size of the paper's rollers example) ------
+    wall_res = None
+    if not args.no_breakdown:
+        print("bench: single-wall products N=32768", file=sys.stderr, flush=True)
+        ws = workloads.wall_suspension(32768, 1008, hg=1.5, phi2d=0.35, torques=True, w=True, angular_w=True)
+        wall_res = {"workload": f"{ws.name}: in-plane packing 0.35, heights a + Exp(0.5a), 5 % overlapping the wall",
+                    "n": ws.n, "flops_per_pair": FLOPS_PER_WALL_PAIR}
+        for dt, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+            for ang in (False, True):
+                so = rpy.Solver("open", "open", "single_wall")
+                so.setParameters(wallHeight=0.0)
+                so.initialize(viscosity=ws.viscosity, hydrodynamicRadius=ws.radius, includeAngular=ang)
+                so.setPositions(dev_t(ws.pos, dt))
+                Fd = dev_t(ws.forces, dt)
+                Td = dev_t(ws.torques, dt) if ang else None
+                tf = timed(lambda: so.Mdot(forces=Fd, torques=Td), 10, stream, warmup=2)
+                key = f"{name}_{'angular' if ang else 'linear'}"
+                fl = FLOPS_PER_WALL_PAIR["angular" if ang else "linear"]
+                pk = PEAK_FP32_TFLOPS if dt == torch.float32 else PEAK_FP64_TFLOPS
+                tfl = fl * float(ws.n) ** 2 / (tf * 1e-3) / 1e12
+                wall_res[key] = {"mdot_ms": round(tf, 4), "pairs_per_s": float(ws.n) ** 2 / (tf * 1e-3),
+                                 "tflops": round(tfl, 2), "frac_of_peak": round(tfl / pk, 4)}
+                if ang and dt == torch.float32:
+                    t0 = time.perf_counter()
+                    so.sqrtMdotW(dev_t(ws.w, dt), tol=1e-6)
+                    torch.cuda.synchronize()
+                    wall_res[key].update({"sqrt_ms": round(1e3 * (time.perf_counter() - t0), 1),
+                                          "sqrt_iterations": so.last_iterations})
+                so.close()
+
     # ---- several vectors at one geometry (float32, 8 force sets; 4 noise
     # vectors) against one call per vector --------------------------------
     multi = None
@@ -649,6 +703,7 @@ def main():
         "lanczos_vector_ops": lanczos_cgs,
         "breakdown": breakdown,
         "gradient_n16384": grad_c3,
+        "single_wall_n32768": wall_res,
         "accuracy_vs_fp64_oracle": acc,
         "batched": batched,
         "chains": chains,

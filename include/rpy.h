@@ -341,68 +341,87 @@ rpy_status rpy_set_adjoint_mode(rpy_solver *s, int mode);
  * Batched solver: many independent open-boundary systems of uneven size
  * (an addition beside the paper's method).  System s owns particles
  * offsets[s] .. offsets[s+1]-1 of every concatenated per-particle array
- * (positions, forces, outputs: total x 3 row-major) and entries
- * 3*offsets[s] .. 3*offsets[s+1]-1 of noise vectors.  Systems never
- * interact.  Translational blocks only (M_uF).  All systems share one
- * dtype; viscosity and radius are per system.
+ * (positions, forces, torques, linear and angular outputs: total x 3
+ * row-major).  Noise / Lanczos vectors give system s the entries
+ * m*offsets[s] .. m*offsets[s+1]-1, m = 3 (translational) or 6 (with
+ * include_angular: the system's 3 n_s linear entries, then its 3 n_s
+ * angular ones).  Systems never interact.  All systems share one dtype;
+ * viscosity and radius are per system.
  */
 typedef struct rpy_batch rpy_batch;
 
 /*
  * offsets (host, n_systems + 1 entries, offsets[0] = 0, strictly
- * increasing), viscosity and radius (host, n_systems entries each, > 0).
- * The arrays are copied.  Allocates the device task list; the caller owns
- * *out and frees it with rpy_batch_destroy.
+ * increasing), viscosity and radius (host, n_systems entries each, > 0),
+ * include_angular (Sec. 3.2, includeAngular: torques in, angular
+ * velocities out).  The arrays are copied.  Allocates the device task lists
+ * and the block-mode partial sums (about (n_s / 512 + 1) x 3 x n_s values
+ * per system, 6 with angular blocks, plus 6 (12) x 512 per block task in
+ * float32); the caller owns *out and frees it with rpy_batch_destroy.
  */
 rpy_status rpy_batch_create(int32_t n_systems, const int64_t *offsets, const double *viscosity,
-                            const double *radius, rpy_dtype dtype, rpy_batch **out);
+                            const double *radius, int include_angular, rpy_dtype dtype, rpy_batch **out);
 
 /* Store the positions of every system (device, total x 3); checks for
  * NaN/Inf and therefore synchronises hip_stream. */
 rpy_status rpy_batch_set_positions(rpy_batch *b, const void *pos, void *hip_stream);
 
 /*
- * lin_out = M_s F for every system s (device, total x 3), all systems in
- * one persistent kernel launch.  Asynchronous.
+ * lin_out = M_uF F + M_uT T and, with include_angular, ang_out = M_wF F +
+ * M_wT T for every system (device, total x 3 each; ang_out required with
+ * include_angular, forbidden without, like torques).  forces / torques:
+ * either may be NULL (zero), not both.  In the block mode (default) one
+ * launch evaluates every system's unordered particle pairs once (tasks of
+ * one 512-particle target block against one source block of the same
+ * system, the symmetric pair machinery of the single-system solver) and a
+ * second one sums each particle's partials in a fixed order; the one-sided
+ * mode (translational only) is one persistent launch over (system, target
+ * tile) tasks.  Asynchronous.
  */
-rpy_status rpy_batch_mdot(rpy_batch *b, const void *forces, void *lin_out, void *hip_stream);
+rpy_status rpy_batch_mdot(rpy_batch *b, const void *forces, const void *torques, void *lin_out, void *ang_out,
+                          void *hip_stream);
 
 /*
- * lin_out = prefactor * M_s^{1/2} w_s for every system (device w of
- * 3 x total entries, lin_out total x 3) by Lanczos (Sec. 3.3) with the
- * stopping rule of rpy_sqrt_mdot_w applied to each system separately:
- * each system stops at the first k >= 2 meeting it, as if it were solved
- * alone.  All systems advance together; one iteration (persistent pair
- * kernel for all systems, segmented float64 vector operations, the
- * per-system stopping test decided on the device) is one replay of a
- * captured HIP graph.  The host polls the number of systems still active
- * every `check_every` iterations (>= 1); a larger value saves host round
- * trips at the price of up to check_every - 1 idle replays at the end, and
- * does not change any result.  iters_out (host, n_systems entries, may be
- * NULL) receives each system's iteration count.  Synchronises hip_stream.  Returns RPY_ERR_NOT_CONVERGED if any
- * system reached max_iter (all results written), RPY_ERR_NOT_SPD if any
- * system's matrix was found indefinite.
+ * lin_out (and, with include_angular, ang_out) = prefactor * M_s^{1/2} w_s
+ * for every system (device w of m x total entries in the layout above;
+ * outputs total x 3) by Lanczos (Sec. 3.3) with the stopping rule of
+ * rpy_sqrt_mdot_w applied to each system separately: each system stops at
+ * the first k >= 2 meeting it, as if it were solved alone.  All systems
+ * advance together; one iteration (the batched product for all active
+ * systems, segmented float64 vector operations, the per-system stopping
+ * test decided on the device) is one replay of a captured HIP graph.  The
+ * host polls the number of systems still active every `check_every`
+ * iterations (>= 1); a larger value saves host round trips at the price of
+ * up to check_every - 1 idle replays at the end, and does not change any
+ * result.  iters_out (host, n_systems entries, may be NULL) receives each
+ * system's iteration count.  Synchronises hip_stream.  Returns
+ * RPY_ERR_NOT_CONVERGED if any system reached max_iter (all results
+ * written), RPY_ERR_NOT_SPD if any system's matrix was found indefinite.
  */
 rpy_status rpy_batch_sqrt_mdot_w(rpy_batch *b, const void *w, double prefactor, double tol, int max_iter,
-                                 int check_every, void *lin_out, int *iters_out, void *hip_stream);
+                                 int check_every, void *lin_out, void *ang_out, int *iters_out, void *hip_stream);
 
 /*
- * Configuration of the batched pair kernel: targets_per_lane in {1, 2}
- * (each task covers 64 x targets_per_lane targets of one system) and
- * workgroups_per_cu in [1, 32] (size of the persistent grid).  Defaults 1
- * and 8.  Setting it rebuilds the task list (synchronous host-to-device
- * copy).  RPY_ERR_INVALID_ARG outside those ranges.
+ * Configuration of the batched product: targets_per_lane = 0 selects the
+ * block mode (the default; the only one with include_angular); 1 or 2 the
+ * one-sided persistent kernel, each task covering 64 x targets_per_lane
+ * targets of one system, with workgroups_per_cu in [1, 32] workgroups per
+ * CU in its persistent grid (default 8).  Setting it rebuilds the one-sided
+ * task list (synchronous host-to-device copy).  RPY_ERR_INVALID_ARG
+ * outside those ranges.
  */
 rpy_status rpy_batch_set_tile_config(rpy_batch *b, int targets_per_lane, int workgroups_per_cu);
 rpy_status rpy_batch_get_tile_config(const rpy_batch *b, int *targets_per_lane, int *workgroups_per_cu);
 
 /*
- * Autotuner of the batched pair kernel for the current systems and
- * positions: times every (targets per lane, workgroups per CU) in
- * {1, 2} x {4, 8, 16} on a fixed pseudo-random force vector, screens them
- * with single products, re-times the best of each tile width in interleaved
- * rounds of ~100 ms bursts, and keeps the fastest.  Synchronises
- * hip_stream.  RPY_ERR_NO_POSITIONS before rpy_batch_set_positions.
+ * Autotuner of the batched product for the current systems and positions:
+ * times the block mode and every (targets per lane, workgroups per CU) in
+ * {1, 2} x {4, 8, 16} of the one-sided kernel on a fixed pseudo-random
+ * force vector, screens them with single products, re-times the best of
+ * each mode and tile width in interleaved rounds of ~100 ms bursts, and
+ * keeps the fastest.  With include_angular only the block mode exists and
+ * nothing is timed.  Synchronises hip_stream.  RPY_ERR_NO_POSITIONS before
+ * rpy_batch_set_positions.
  */
 rpy_status rpy_batch_autotune(rpy_batch *b, void *hip_stream);
 

@@ -86,11 +86,11 @@ def load() -> ctypes.CDLL:
         "rpy_ab2_step": ([vp, vp, vp, vp, d, d, d, i, vp, i, vp, vp, ctypes.POINTER(i), vp], i),
         "rpy_mdot_backward": ([vp, vp, vp, vp, vp, vp, vp, vp, vp], i),
         "rpy_set_adjoint_mode": ([vp, i], i),
-        "rpy_batch_create": ([ctypes.c_int32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d), i,
+        "rpy_batch_create": ([ctypes.c_int32, ctypes.POINTER(i64), ctypes.POINTER(d), ctypes.POINTER(d), i, i,
                               ctypes.POINTER(vp)], i),
         "rpy_batch_set_positions": ([vp, vp, vp], i),
-        "rpy_batch_mdot": ([vp, vp, vp, vp], i),
-        "rpy_batch_sqrt_mdot_w": ([vp, vp, d, d, i, i, vp, ctypes.POINTER(i), vp], i),
+        "rpy_batch_mdot": ([vp, vp, vp, vp, vp, vp], i),
+        "rpy_batch_sqrt_mdot_w": ([vp, vp, d, d, i, i, vp, vp, ctypes.POINTER(i), vp], i),
         "rpy_batch_last_error": ([vp], ctypes.c_char_p),
         "rpy_batch_set_tile_config": ([vp, i, i], i),
         "rpy_batch_get_tile_config": ([vp, ctypes.POINTER(i), ctypes.POINTER(i)], i),
@@ -306,7 +306,7 @@ def _bcheck(h, status: int):
         raise RpyError(status, load().rpy_batch_last_error(h).decode() if h else "")
 
 
-def rpy_batch_create(offsets, viscosity, radius, dtype: torch.dtype):
+def rpy_batch_create(offsets, viscosity, radius, dtype: torch.dtype, include_angular: bool = False):
     """Batch of independent systems; offsets has n_systems + 1 entries."""
     import numpy as np
     off = np.ascontiguousarray(offsets, dtype=np.int64)
@@ -320,7 +320,8 @@ def rpy_batch_create(offsets, viscosity, radius, dtype: torch.dtype):
     out = ctypes.c_void_p()
     st = load().rpy_batch_create(ns, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                  eta.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                 rad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), DTYPE[dtype],
+                                 rad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(bool(include_angular)),
+                                 DTYPE[dtype],
                                  ctypes.byref(out))
     if st != 0:
         raise RpyError(st, "rpy_batch_create")
@@ -331,19 +332,23 @@ def rpy_batch_set_positions(h, pos, dtype, total):
     _bcheck(h, load().rpy_batch_set_positions(h, _ptr(pos, dtype, 3 * total, "positions"), _stream(pos)))
 
 
-def rpy_batch_mdot(h, forces, lin_out, dtype, total):
-    _bcheck(h, load().rpy_batch_mdot(h, _ptr(forces, dtype, 3 * total, "forces"),
-                                     _ptr(lin_out, dtype, 3 * total, "lin_out"), _stream(lin_out)))
+def rpy_batch_mdot(h, forces, torques, lin_out, ang_out, dtype, total):
+    m = 3 * total
+    _bcheck(h, load().rpy_batch_mdot(h, _ptr(forces, dtype, m, "forces"), _ptr(torques, dtype, m, "torques"),
+                                     _ptr(lin_out, dtype, m, "lin_out"), _ptr(ang_out, dtype, m, "ang_out"),
+                                     _stream(lin_out)))
 
 
-def rpy_batch_sqrt_mdot_w(h, w, prefactor, tol, max_iter, check_every, lin_out, dtype, total, n_systems):
+def rpy_batch_sqrt_mdot_w(h, w, prefactor, tol, max_iter, check_every, lin_out, ang_out, dtype, total, n_systems):
     iters = (ctypes.c_int * n_systems)()
-    st = load().rpy_batch_sqrt_mdot_w(h, _ptr(w, dtype, 3 * total, "W"), float(prefactor), float(tol),
+    wn = (6 if ang_out is not None else 3) * total
+    st = load().rpy_batch_sqrt_mdot_w(h, _ptr(w, dtype, wn, "W"), float(prefactor), float(tol),
                                       int(max_iter), int(check_every), _ptr(lin_out, dtype, 3 * total, "lin_out"),
-                                      iters, _stream(lin_out))
+                                      _ptr(ang_out, dtype, 3 * total, "ang_out"), iters, _stream(lin_out))
     it = list(iters)
     if st == Status.NOT_CONVERGED:
-        raise NotConvergedError(st, load().rpy_batch_last_error(h).decode(), lin_out, it, float("nan"))
+        raise NotConvergedError(st, load().rpy_batch_last_error(h).decode(),
+                                lin_out if ang_out is None else (lin_out, ang_out), it, float("nan"))
     _bcheck(h, st)
     return it
 

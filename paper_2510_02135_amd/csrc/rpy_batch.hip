@@ -26,6 +26,7 @@
 #include "rpy_krylov.hpp"
 #include "rpy_internal.hpp"
 #include "rpy_solver_ops.hpp"
+#include "rpy_sym.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -147,9 +148,10 @@ batch_pair_kernel(const vec4_t<Real> *__restrict__ rec, const int64_t *__restric
     }
 }
 
-// positions (AoS total x 3) -> pos slots of the records, counting non-finite entries
+// positions (AoS total x 3) -> slot 0 of the nrs records of each particle,
+// counting non-finite entries
 template <typename Real>
-__global__ void batch_stage_pos(const Real *__restrict__ in, int64_t ntot, vec4_t<Real> *__restrict__ rec,
+__global__ void batch_stage_pos(const Real *__restrict__ in, int64_t ntot, int nrs, vec4_t<Real> *__restrict__ rec,
                                 unsigned *__restrict__ nonfinite) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ntot) return;
@@ -160,23 +162,188 @@ __global__ void batch_stage_pos(const Real *__restrict__ in, int64_t ntot, vec4_
     v.y = y;
     v.z = z;
     v.w = Real(0);
-    rec[2 * i] = v;
+    rec[(int64_t)nrs * i] = v;
 }
 
-// AoS total x 3 vector (caller dtype, or the float64 Lanczos column at
-// V + (k-1) ld when kdev is given) -> force slots of the records
+// A 3-vector per particle -> record slot `slot` (1 force, 2 torque) of the
+// nrs records of each particle.  Sources: the caller's AoS total x 3 array
+// (NULL = zeros), or (kdev != NULL) column kdev[0] - 1 of the float64
+// Lanczos basis, whose layout gives system s the entries
+// [vmul o_s, vmul o_{s+1}): its 3 n_s linear rows, then (vmul = 6) its 3 n_s
+// angular rows; psys (particle -> system) is needed for vmul = 6.
 template <typename Tin, typename Real>
 __global__ void batch_stage_vec(const Tin *__restrict__ in, const int *__restrict__ kdev, int64_t ld, int64_t ntot,
-                                vec4_t<Real> *__restrict__ rec) {
+                                int nrs, int slot, int vmul, const int *__restrict__ psys,
+                                const int64_t *__restrict__ off, vec4_t<Real> *__restrict__ rec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ntot) return;
-    const Tin *v = kdev ? in + (size_t)(kdev[0] - 1) * ld : in;
     vec4_t<Real> r;
-    r.x = (Real)v[3 * i];
-    r.y = (Real)v[3 * i + 1];
-    r.z = (Real)v[3 * i + 2];
     r.w = Real(0);
-    rec[2 * i + 1] = r;
+    if (!in) {
+        r.x = r.y = r.z = Real(0);
+    } else {
+        const Tin *v = kdev ? in + (size_t)(kdev[0] - 1) * ld : in;
+        int64_t e = 3 * i;
+        if (kdev && vmul == 6) {
+            const int s = psys[i];
+            e = 3 * ((slot == 2 ? off[s + 1] : off[s]) + i);
+        }
+        r.x = (Real)v[e];
+        r.y = (Real)v[e + 1];
+        r.z = (Real)v[e + 2];
+    }
+    rec[(int64_t)nrs * i + slot] = r;
+}
+
+// ---------------------------------------------------------------------------
+// block mode: each system's unordered pairs evaluated once (the symmetric
+// pair machinery of rpy_sym.hpp), all systems' block tasks in one launch
+// ---------------------------------------------------------------------------
+// Records of the batch: NRS = 2 (position, force) or 3 (+ torque) vec4 per
+// particle, systems contiguous.
+template <typename Real, bool ANG>
+struct BatchPairs : FwdPairs<Real, ANG> {
+    using R4 = vec4_t<Real>;
+    using Tgt = typename FwdPairs<Real, ANG>::Tgt;
+    static constexpr int NRS = ANG ? 3 : 2;
+    struct Args {
+        const R4 *rec;   // the system's first record
+    };
+    __device__ static Tgt target(const Args &a, const PairConst<Real> &c, int idx, int n) {
+        (void)c;
+        const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+        const R4 p = a.rec[NRS * min(idx, n - 1)];
+        Tgt k;
+        k.x = p.x;
+        k.y = p.y;
+        k.z = p.z;
+        k.f = idx < n ? a.rec[NRS * idx + 1] : zero4;
+        k.t = zero4;
+        if constexpr (ANG) k.t = idx < n ? a.rec[NRS * idx + 2] : zero4;
+        return k;
+    }
+    __device__ static R4 record(const Args &a, const PairConst<Real> &c, int r, int js, int n) {
+        (void)c;
+        const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+        if (r == 0) return a.rec[NRS * min(js, n - 1)];
+        if (js >= n) return zero4;
+        return a.rec[NRS * js + r];
+    }
+};
+
+// One block task per workgroup: tasks[b] = (target block, first source
+// block, end source block, slot) of system task_sys[b]; its source-side
+// partials go to jpart + joff[s] ([block][NC][n_s]), its target-side ones to
+// slot `slot` of ipart.  Tasks of inactive systems (converged Lanczos
+// recurrences) return at once.
+template <typename Real, bool ANG>
+__global__ void __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(BatchPairs<Real, ANG>::kMinWaves)))
+batch_block_kernel(const vec4_t<Real> *__restrict__ rec, const int64_t *__restrict__ off,
+                   const int4 *__restrict__ tasks, const int *__restrict__ task_sys, const int64_t *__restrict__ joff,
+                   const PairConst<Real> *__restrict__ pcs, const int *__restrict__ active, Real *__restrict__ ipart,
+                   Real *__restrict__ jpart) {
+    using P = BatchPairs<Real, ANG>;
+    const int s = task_sys[blockIdx.x];
+    if (active && active[s] == 0) return;
+    const int64_t o = off[s];
+    const int n = (int)(off[s + 1] - o);
+    const typename P::Args a{rec + (int64_t)P::NRS * o};
+    const PairConst<Real> c = pcs[s];
+    sym_block_task<Real, P>(a, n, tasks[blockIdx.x], 0, 0, c, ipart, jpart + joff[s]);
+}
+
+// Per particle i of system s (chunks of 256 particles: chunks[x] = (s,
+// first particle)) and component c = blockIdx.y: the target-side partials
+// of the tasks of i's block b (slots slot0[soff[s] + b] ..
+// slot0[soff[s] + b + 1] - 1), then the source-side partials of the
+// system's blocks 0 .. b - 1, in that fixed order; scaled by k_s.  Output
+// component c < 3 goes to lin[3 (o_s + i) + c] and c >= 3 to
+// ang[3 (o_s + i) + c - 3] (separate outputs, vec_layout = 0), or, for a
+// Lanczos vector with angular rows (vec_layout = 1, lin = ang = the
+// vector), to entries 6 o_s + 3 i + c and 6 o_s + 3 n_s + 3 i + c - 3.
+template <typename Real, typename Tout, int NC>
+__global__ void __launch_bounds__(256)
+batch_block_reduce(const Real *__restrict__ ipart, const Real *__restrict__ jpart, const int64_t *__restrict__ joff,
+                   const int *__restrict__ slot0, const int *__restrict__ soff, const int2 *__restrict__ chunks,
+                   const int64_t *__restrict__ off, const double *__restrict__ kfac, const int *__restrict__ active,
+                   int vec_layout, Tout *__restrict__ lin, Tout *__restrict__ ang) {
+    constexpr int BLK = kSymThreads * 2;
+    constexpr bool COMP = std::is_same<Real, float>::value;
+    constexpr int PC = COMP ? 2 * NC : NC;
+    constexpr int kAhead = 8;
+    const int2 ch = chunks[blockIdx.x];
+    const int s = ch.x;
+    if (active && active[s] == 0) return;
+    const int64_t o = off[s];
+    const int n = (int)(off[s + 1] - o);
+    const int i = ch.y + (int)threadIdx.x;
+    if (i >= n) return;
+    const int c = blockIdx.y;
+    const int b = i / BLK, t = i % BLK;
+    const int q0 = slot0[soff[s] + b], ni = slot0[soff[s] + b + 1] - q0;
+    const size_t istride = (size_t)PC * BLK, jstride = (size_t)NC * (size_t)n;
+    const Real *pi = ipart + (size_t)q0 * istride + (size_t)c * BLK + t;
+    const Real *pj = jpart + joff[s] + (size_t)c * n + i;
+    double v;
+    if constexpr (COMP) {
+        float sm = 0.f, cp = 0.f, extra = 0.f;
+        int q = 0;
+        for (; q + kAhead <= ni; q += kAhead) {
+            float x[kAhead], e[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                x[u] = pi[(size_t)(q + u) * istride];
+                e[u] = pi[(size_t)(q + u) * istride + (size_t)NC * BLK];
+            }
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                neumaier(sm, cp, x[u]);
+                extra += e[u];
+            }
+        }
+        for (; q < ni; ++q) {
+            neumaier(sm, cp, pi[(size_t)q * istride]);
+            extra += pi[(size_t)q * istride + (size_t)NC * BLK];
+        }
+        int bb = 0;
+        for (; bb + kAhead <= b; bb += kAhead) {
+            float x[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) x[u] = pj[(size_t)(bb + u) * jstride];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) neumaier(sm, cp, x[u]);
+        }
+        for (; bb < b; ++bb) neumaier(sm, cp, pj[(size_t)bb * jstride]);
+        v = (double)sm + ((double)cp + (double)extra);
+    } else {
+        double sm = 0.0;
+        int q = 0;
+        for (; q + kAhead <= ni; q += kAhead) {
+            double x[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) x[u] = pi[(size_t)(q + u) * istride];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) sm += x[u];
+        }
+        for (; q < ni; ++q) sm += pi[(size_t)q * istride];
+        int bb = 0;
+        for (; bb + kAhead <= b; bb += kAhead) {
+            double x[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) x[u] = pj[(size_t)(bb + u) * jstride];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) sm += x[u];
+        }
+        for (; bb < b; ++bb) sm += pj[(size_t)bb * jstride];
+        v = sm;
+    }
+    v *= kfac[s];
+    // separate outputs: particle o + i of each; a Lanczos vector with angular
+    // rows: system s's linear entries from 6 o, its angular ones from 6 o + 3 n
+    if (c < 3)
+        lin[3 * ((vec_layout ? 2 * o : o) + i) + c] = (Tout)v;
+    else
+        ang[3 * ((vec_layout ? o + off[s + 1] : o) + i) + (c - 3)] = (Tout)v;
 }
 
 // ---------------------------------------------------------------------------
@@ -532,7 +699,7 @@ template <typename Tout>
 __global__ void batch_combine(const double *__restrict__ V, int64_t ld, const double *__restrict__ s_cur,
                               const double *__restrict__ s_est, int64_t lstride, const double *__restrict__ status,
                               const int *__restrict__ fresh, const double *__restrict__ prefactor, SegMap m,
-                              Tout *__restrict__ out) {
+                              const int64_t *__restrict__ off, Tout *__restrict__ out, Tout *__restrict__ ang) {
     __shared__ double hs[kMaxK];
     const int s = m.sys[blockIdx.x];
     if (fresh[s] == 0) return;
@@ -546,7 +713,17 @@ __global__ void batch_combine(const double *__restrict__ V, int64_t ld, const do
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         double acc = 0.0;
         for (int j = 0; j < kf; ++j) acc = fma(V[(size_t)j * ld + i], hs[j], acc);
-        out[i] = (Tout)(scale * acc);
+        const Tout y = (Tout)(scale * acc);
+        if (!ang) {
+            out[i] = y;
+        } else {
+            // entries [6 o_s, 6 o_s + 3 n_s) are linear rows, the rest angular
+            const int64_t o = off[s], r = i - 6 * o, n3 = 3 * (off[s + 1] - o);
+            if (r < n3)
+                out[3 * o + r] = y;
+            else
+                ang[3 * o + (r - n3)] = y;
+        }
     }
 }
 
@@ -570,11 +747,21 @@ __global__ void batch_init_status(double *__restrict__ status, int *__restrict__
 }
 
 template <typename T>
-__global__ void seg_zero_inactive(T *__restrict__ out, SegMap m, const int *__restrict__ active,
-                                  const double *__restrict__ status) {
+__global__ void seg_zero_inactive(T *__restrict__ out, T *__restrict__ ang, const int64_t *__restrict__ off, SegMap m,
+                                  const int *__restrict__ active, const double *__restrict__ status) {
     const int s = m.sys[blockIdx.x];
     if (active[s] != 0 || status[(size_t)s * BS_SIZE + BS_BETA0] != 0.0) return;
-    for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < m.hi[blockIdx.x]; i += blockDim.x) out[i] = T(0);
+    for (int64_t i = m.lo[blockIdx.x] + threadIdx.x; i < m.hi[blockIdx.x]; i += blockDim.x) {
+        if (!ang) {
+            out[i] = T(0);
+        } else {
+            const int64_t o = off[s], r = i - 6 * o, n3 = 3 * (off[s + 1] - o);
+            if (r < n3)
+                out[3 * o + r] = T(0);
+            else
+                ang[3 * o + (r - n3)] = T(0);
+        }
+    }
 }
 
 }  // namespace
@@ -591,11 +778,21 @@ struct rpy_batch {
     bool have_pos = false;
     int ntasks = 0, nblk = 0;
     int max_sys_n = 0;
+    // angular blocks: records per particle (position, force[, torque]) and
+    // entries per particle of a Lanczos vector
+    bool angular = false;
+    int nrs = 2, vmul = 3;
     // pair-kernel configuration: targets per lane (tasks of 64 tm targets)
-    // and persistent workgroups per CU; systems longest first
-    int tm = 1, wg_per_cu = 8;
+    // and persistent workgroups per CU, or tm = 0: the block mode (each
+    // system's unordered pairs once); systems longest first
+    int tm = 0, wg_per_cu = 8;
     std::vector<int> order;
     DevBuf d_off, d_kfac, d_pc, d_tasks, d_counter, d_rec, d_flag;
+    // block mode: tasks (int4) and their systems, per-system offsets of the
+    // source-side partials and of the slot table, chunks of the reduction,
+    // particle -> system, and the partials
+    int nbtasks = 0, nchunks = 0;
+    DevBuf d_btask, d_bsys, d_joff, d_bslot0, d_soff, d_chunks, d_psys, d_ipart, d_jpart;
     DevBuf d_blk_sys, d_blk_lo, d_blk_hi, d_sys_b0, d_sys_b1, d_kmax;
     DevBuf V, w, lanc, red, Q, status, ints, pref, mon;
     unsigned *host_u = nullptr;
@@ -634,6 +831,10 @@ unsigned persistent_blocks(const rpy_batch *b) {
 // task list (system, tile of 64 tm targets) in b->order, uploaded to d_tasks
 hipError_t build_tasks(rpy_batch *b) {
     std::vector<int2> tasks;
+    if (b->tm == 0) {   // block mode: its task list is built once (build_block_tasks)
+        b->ntasks = 0;
+        return hipSuccess;
+    }
     const int tile = 64 * b->tm;
     for (int s : b->order) {
         const int64_t ns = b->off[s + 1] - b->off[s];
@@ -643,6 +844,82 @@ hipError_t build_tasks(rpy_batch *b) {
     hipError_t e = b->d_tasks.ensure(sizeof(int2) * tasks.size());
     if (e != hipSuccess) return e;
     return hipMemcpy(b->d_tasks.p, tasks.data(), sizeof(int2) * tasks.size(), hipMemcpyHostToDevice);
+}
+
+// Block-mode tasks: per system, target blocks of BLK = 512 particles, one
+// task per (target block I, source block J >= I); systems longest first,
+// tasks of a block contiguous (their slot = their index).  Also the
+// reduction's chunks and the particle -> system map.
+hipError_t build_block_tasks(rpy_batch *b) {
+    constexpr int BLK = kSymThreads * 2;
+    const int nc = b->angular ? 6 : 3;
+    std::vector<int4> tasks;
+    std::vector<int> tsys, slot0, soff(b->nsys), psys((size_t)b->ntot);
+    std::vector<int64_t> joff(b->nsys);
+    std::vector<int2> chunks;
+    int64_t jtot = 0;
+    for (int s : b->order) {
+        const int64_t n = b->off[s + 1] - b->off[s];
+        const int nb = (int)((n + BLK - 1) / BLK);
+        soff[s] = (int)slot0.size();
+        joff[s] = jtot;
+        jtot += (int64_t)nb * nc * n;
+        for (int bi = 0; bi < nb; ++bi) {
+            slot0.push_back((int)tasks.size());
+            for (int j = bi; j < nb; ++j) {
+                tasks.push_back(make_int4(bi, j, j + 1, (int)tasks.size()));
+                tsys.push_back(s);
+            }
+        }
+        slot0.push_back((int)tasks.size());
+        for (int64_t c = 0; c < n; c += 256) chunks.push_back(make_int2(s, (int)c));
+        for (int64_t i = b->off[s]; i < b->off[s + 1]; ++i) psys[(size_t)i] = s;
+    }
+    b->nbtasks = (int)tasks.size();
+    b->nchunks = (int)chunks.size();
+    const size_t pc = (size_t)nc * (b->dtype == RPY_F32 ? 2 : 1);
+    const size_t elt = b->dtype == RPY_F64 ? sizeof(double) : sizeof(float);
+    auto up = [&](DevBuf &d, const void *src, size_t bytes) -> hipError_t {
+        hipError_t e = d.ensure(bytes);
+        if (e != hipSuccess) return e;
+        return hipMemcpy(d.p, src, bytes, hipMemcpyHostToDevice);
+    };
+    hipError_t e = up(b->d_btask, tasks.data(), sizeof(int4) * tasks.size());
+    if (e == hipSuccess) e = up(b->d_bsys, tsys.data(), sizeof(int) * tsys.size());
+    if (e == hipSuccess) e = up(b->d_joff, joff.data(), sizeof(int64_t) * joff.size());
+    if (e == hipSuccess) e = up(b->d_bslot0, slot0.data(), sizeof(int) * slot0.size());
+    if (e == hipSuccess) e = up(b->d_soff, soff.data(), sizeof(int) * soff.size());
+    if (e == hipSuccess) e = up(b->d_chunks, chunks.data(), sizeof(int2) * chunks.size());
+    if (e == hipSuccess) e = up(b->d_psys, psys.data(), sizeof(int) * psys.size());
+    if (e == hipSuccess) e = b->d_ipart.ensure(elt * pc * BLK * tasks.size());
+    if (e == hipSuccess) e = b->d_jpart.ensure(elt * (size_t)std::max<int64_t>(jtot, 1));
+    return e;
+}
+
+// M [F; T] of every (active) system by the block mode into lin / ang (see
+// batch_block_reduce for the output layouts).
+template <typename Real, typename Tout>
+void launch_batch_block(rpy_batch *b, const int *active, Tout *lin, Tout *ang, int vec_layout, hipStream_t st) {
+    const dim3 rgrid((unsigned)b->nchunks, b->angular ? 6 : 3);
+    if (b->angular) {
+        hipLaunchKernelGGL((batch_block_kernel<Real, true>), dim3((unsigned)b->nbtasks), dim3(kSymThreads), 0, st,
+                           b->d_rec.as<vec4_t<Real>>(), b->d_off.as<int64_t>(), b->d_btask.as<int4>(),
+                           b->d_bsys.as<int>(), b->d_joff.as<int64_t>(), b->d_pc.as<PairConst<Real>>(), active,
+                           b->d_ipart.as<Real>(), b->d_jpart.as<Real>());
+        hipLaunchKernelGGL((batch_block_reduce<Real, Tout, 6>), rgrid, dim3(256), 0, st, b->d_ipart.as<Real>(),
+                           b->d_jpart.as<Real>(), b->d_joff.as<int64_t>(), b->d_bslot0.as<int>(), b->d_soff.as<int>(),
+                           b->d_chunks.as<int2>(), b->d_off.as<int64_t>(), b->d_kfac.as<double>(), active, vec_layout,
+                           lin, ang);
+    } else {
+        hipLaunchKernelGGL((batch_block_kernel<Real, false>), dim3((unsigned)b->nbtasks), dim3(kSymThreads), 0, st,
+                           b->d_rec.as<vec4_t<Real>>(), b->d_off.as<int64_t>(), b->d_btask.as<int4>(),
+                           b->d_bsys.as<int>(), b->d_joff.as<int64_t>(), b->d_pc.as<PairConst<Real>>(), active,
+                           b->d_ipart.as<Real>(), b->d_jpart.as<Real>());
+        hipLaunchKernelGGL((batch_block_reduce<Real, Tout, 3>), rgrid, dim3(256), 0, st, b->d_ipart.as<Real>(),
+                           b->d_jpart.as<Real>(), b->d_joff.as<int64_t>(), b->d_bslot0.as<int>(), b->d_soff.as<int>(),
+                           b->d_chunks.as<int2>(), b->d_off.as<int64_t>(), b->d_kfac.as<double>(), active, vec_layout,
+                           lin, (Tout *)nullptr);
+    }
 }
 
 template <typename Real, typename Tout>
@@ -659,11 +936,21 @@ void launch_batch_pair(rpy_batch *b, const int *active, Tout *out, hipStream_t s
 }
 
 template <typename Real>
-rpy_status batch_mdot_typed(rpy_batch *b, const Real *F, Real *out, hipStream_t st) {
-    hipLaunchKernelGGL((batch_stage_vec<Real, Real>), dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0, st, F,
-                       (const int *)nullptr, (int64_t)0, b->ntot, b->d_rec.as<vec4_t<Real>>());
-    BHIP(b, launch_fill_zero<unsigned>(b->d_counter.as<unsigned>(), 1, st));
-    launch_batch_pair<Real, Real>(b, nullptr, out, st);
+rpy_status batch_mdot_typed(rpy_batch *b, const Real *F, const Real *T, Real *out, Real *ang, hipStream_t st) {
+    const dim3 g((unsigned)((b->ntot + 255) / 256));
+    hipLaunchKernelGGL((batch_stage_vec<Real, Real>), g, dim3(256), 0, st, F, (const int *)nullptr, (int64_t)0,
+                       b->ntot, b->nrs, 1, 3, (const int *)nullptr, (const int64_t *)nullptr,
+                       b->d_rec.as<vec4_t<Real>>());
+    if (b->angular)
+        hipLaunchKernelGGL((batch_stage_vec<Real, Real>), g, dim3(256), 0, st, T, (const int *)nullptr, (int64_t)0,
+                           b->ntot, b->nrs, 2, 3, (const int *)nullptr, (const int64_t *)nullptr,
+                           b->d_rec.as<vec4_t<Real>>());
+    if (b->tm == 0) {
+        launch_batch_block<Real, Real>(b, nullptr, out, ang, 0, st);
+    } else {
+        BHIP(b, launch_fill_zero<unsigned>(b->d_counter.as<unsigned>(), 1, st));
+        launch_batch_pair<Real, Real>(b, nullptr, out, st);
+    }
     BHIP(b, hipGetLastError());
     return RPY_OK;
 }
@@ -671,8 +958,8 @@ rpy_status batch_mdot_typed(rpy_batch *b, const Real *F, Real *out, hipStream_t 
 // Enqueue one Lanczos iteration for all active systems, with its stopping
 // test, as one graph.
 template <typename Real>
-void enqueue_iteration(rpy_batch *b, int kcap, double tol, int every, Real *out, hipStream_t st) {
-    const int64_t n = 3 * b->ntot;
+void enqueue_iteration(rpy_batch *b, int kcap, double tol, int every, Real *out, Real *ang, hipStream_t st) {
+    const int64_t n = (int64_t)b->vmul * b->ntot;
     const int64_t ld = (n + 63) / 64 * 64;
     const int64_t L = kcap + 1;
     double *lan = b->lanc.as<double>();
@@ -684,10 +971,18 @@ void enqueue_iteration(rpy_batch *b, int kcap, double tol, int every, Real *out,
     const dim3 gs((unsigned)((b->nsys + 255) / 256));
     double *V = b->V.as<double>(), *w = b->w.as<double>(), *red = b->red.as<double>();
     // w = M v_k (only active systems' tasks do work)
-    hipLaunchKernelGGL((batch_stage_vec<double, Real>), dim3((unsigned)((b->ntot + 255) / 256)), dim3(256), 0, st, V,
-                       kdev, ld, b->ntot, b->d_rec.as<vec4_t<Real>>());
-    hipLaunchKernelGGL(clear_ints, dim3(1), dim3(64), 0, st, (int *)b->d_counter.p, 1);
-    launch_batch_pair<Real, double>(b, active, w, st);
+    const dim3 gp((unsigned)((b->ntot + 255) / 256));
+    hipLaunchKernelGGL((batch_stage_vec<double, Real>), gp, dim3(256), 0, st, V, kdev, ld, b->ntot, b->nrs, 1,
+                       b->vmul, b->d_psys.as<int>(), b->d_off.as<int64_t>(), b->d_rec.as<vec4_t<Real>>());
+    if (b->angular)
+        hipLaunchKernelGGL((batch_stage_vec<double, Real>), gp, dim3(256), 0, st, V, kdev, ld, b->ntot, b->nrs, 2,
+                           b->vmul, b->d_psys.as<int>(), b->d_off.as<int64_t>(), b->d_rec.as<vec4_t<Real>>());
+    if (b->tm == 0) {
+        launch_batch_block<Real, double>(b, active, w, w, b->angular ? 1 : 0, st);
+    } else {
+        hipLaunchKernelGGL(clear_ints, dim3(1), dim3(64), 0, st, (int *)b->d_counter.p, 1);
+        launch_batch_pair<Real, double>(b, active, w, st);
+    }
     // recurrence
     hipLaunchKernelGGL(seg_recur_dot, gb, tb, 0, st, w, V, ld, beta, L, m, active, kdev, red);
     hipLaunchKernelGGL(seg_sys_reduce, gs, dim3(256), 0, st, red, b->d_sys_b0.as<int>(), b->d_sys_b1.as<int>(),
@@ -726,16 +1021,16 @@ void enqueue_iteration(rpy_batch *b, int kcap, double tol, int every, Real *out,
     hipLaunchKernelGGL(batch_converge, dim3(1), dim3(kSegThreads), 0, st, b->status.as<double>(), active, fresh, need,
                        kcap, b->nsys, tol, kdev);
     hipLaunchKernelGGL((batch_combine<Real>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, V, ld, s_cur, e_cur,
-                       L, b->status.as<double>(), fresh, b->pref.as<double>(), m, out);
+                       L, b->status.as<double>(), fresh, b->pref.as<double>(), m, b->d_off.as<int64_t>(), out, ang);
     hipLaunchKernelGGL(clear_ints, dim3((unsigned)((b->nsys + 255) / 256)), dim3(256), 0, st, fresh, b->nsys);
 }
 
 template <typename Real>
 rpy_status batch_sqrt_typed(rpy_batch *b, const Real *w_in, double prefactor, double tol, int max_iter,
-                            int check_every, Real *out, int *iters_out, hipStream_t st) {
-    const int64_t n = 3 * b->ntot;
+                            int check_every, Real *out, Real *ang, int *iters_out, hipStream_t st) {
+    const int64_t n = (int64_t)b->vmul * b->ntot;
     const int64_t ld = (n + 63) / 64 * 64;
-    const int kcap = std::min({max_iter, kMaxK, 3 * b->max_sys_n});
+    const int kcap = std::min({max_iter, kMaxK, b->vmul * b->max_sys_n});
     const int64_t L = kcap + 1;
     BHIP(b, b->V.ensure((size_t)(kcap + 1) * ld * sizeof(double)));
     BHIP(b, b->w.ensure((size_t)ld * sizeof(double)));
@@ -752,7 +1047,7 @@ rpy_status batch_sqrt_typed(rpy_batch *b, const Real *w_in, double prefactor, do
     // per-system dimension 3 N_s (the Krylov space cannot grow beyond it)
     {
         std::vector<int> dims(b->nsys);
-        for (int s = 0; s < b->nsys; ++s) dims[s] = (int)(3 * (b->off[s + 1] - b->off[s]));
+        for (int s = 0; s < b->nsys; ++s) dims[s] = (int)(b->vmul * (b->off[s + 1] - b->off[s]));
         BHIP(b, b->d_kmax.ensure(sizeof(int) * b->nsys));
         BHIP(b, hipMemcpy(b->d_kmax.p, dims.data(), sizeof(int) * b->nsys, hipMemcpyHostToDevice));
     }
@@ -765,8 +1060,8 @@ rpy_status batch_sqrt_typed(rpy_batch *b, const Real *w_in, double prefactor, do
                        (const int *)nullptr, b->status.as<double>(), (int64_t)BS_SIZE, 1);
     hipLaunchKernelGGL(batch_init_status, dim3((unsigned)((b->nsys + 255) / 256)), dim3(256), 0, st,
                        b->status.as<double>(), active, fresh, b->nsys, kdev, nonfin);
-    hipLaunchKernelGGL((seg_zero_inactive<Real>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, out, m, active,
-                       b->status.as<double>());
+    hipLaunchKernelGGL((seg_zero_inactive<Real>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, out, ang,
+                       b->d_off.as<int64_t>(), m, active, b->status.as<double>());
     hipLaunchKernelGGL((seg_init_basis<Real>), dim3((unsigned)b->nblk), dim3(kSegThreads), 0, st, b->V.as<double>(),
                        w_in, m, b->status.as<double>(), active);
     BHIP(b, hipGetLastError());
@@ -788,7 +1083,7 @@ rpy_status batch_sqrt_typed(rpy_batch *b, const Real *w_in, double prefactor, do
     };
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        enqueue_iteration<Real>(b, kcap, tol, every, out, cap);
+        enqueue_iteration<Real>(b, kcap, tol, every, out, ang, cap);
         e = hipStreamEndCapture(cap, &g_iter);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&x_iter, g_iter, nullptr, nullptr, 0);
@@ -844,11 +1139,11 @@ __global__ void batch_fill_pattern(Real *__restrict__ out, int64_t n) {
 
 // milliseconds per batched product over `burst` back-to-back products
 template <typename Real>
-rpy_status batch_time(rpy_batch *b, const Real *F, Real *out, int burst, hipStream_t st, hipEvent_t e0,
-                      hipEvent_t e1, double *ms) {
+rpy_status batch_time(rpy_batch *b, const Real *F, const Real *T, Real *out, Real *ang, int burst, hipStream_t st,
+                      hipEvent_t e0, hipEvent_t e1, double *ms) {
     BHIP(b, hipEventRecord(e0, st));
     for (int r = 0; r < burst; ++r) {
-        rpy_status q = batch_mdot_typed<Real>(b, F, out, st);
+        rpy_status q = batch_mdot_typed<Real>(b, F, T, out, ang, st);
         if (q != RPY_OK) return q;
     }
     BHIP(b, hipEventRecord(e1, st));
@@ -859,11 +1154,17 @@ rpy_status batch_time(rpy_batch *b, const Real *F, Real *out, int burst, hipStre
     return RPY_OK;
 }
 
-// Screen every (targets per lane, workgroups per CU) with single products,
-// then re-time the best of each tile width in interleaved rounds of ~100 ms
-// bursts and keep the fastest (as the single-system tuner does).
+// Screen the block mode and every (targets per lane, workgroups per CU) of
+// the one-sided kernel with single products, then re-time the best of each
+// in interleaved rounds of ~100 ms bursts and keep the fastest (as the
+// single-system tuner does).  With angular blocks only the block mode
+// exists, and nothing is timed.
 template <typename Real>
 rpy_status batch_tune(rpy_batch *b, hipStream_t st) {
+    if (b->angular) {
+        b->tm = 0;
+        return RPY_OK;
+    }
     DevBuf data;
     const int64_t n3 = 3 * b->ntot;
     BHIP(b, data.ensure(2 * sizeof(Real) * (size_t)n3));
@@ -880,32 +1181,34 @@ rpy_status batch_tune(rpy_batch *b, hipStream_t st) {
         int tm, wg;
         double ms;
     };
+    std::vector<Cand> cands{{0, 8, 0.0}};
+    for (int tm : {1, 2})
+        for (int wg : {4, 8, 16}) cands.push_back({tm, wg, 0.0});
     std::vector<Cand> screen;
     rpy_status r = RPY_OK;
-    for (int tm : {1, 2})
-        for (int wg : {4, 8, 16}) {
-            if (r != RPY_OK) break;
-            b->tm = tm;
-            b->wg_per_cu = wg;
-            if (build_tasks(b) != hipSuccess) {
-                r = bfail(b, RPY_ERR_HIP, "task list upload failed");
-                break;
-            }
-            std::vector<double> t;
-            for (int q = 0; q < 4 && r == RPY_OK; ++q) {
-                double ms = 0.0;
-                r = batch_time<Real>(b, F, out, 1, st, e0, e1, &ms);
-                if (q > 0) t.push_back(ms);   // the first product is a warm-up
-            }
-            if (r == RPY_OK) {
-                std::sort(t.begin(), t.end());
-                screen.push_back({tm, wg, t[t.size() / 2]});
-            }
+    for (const Cand &cd : cands) {
+        if (r != RPY_OK) break;
+        b->tm = cd.tm;
+        b->wg_per_cu = cd.wg;
+        if (build_tasks(b) != hipSuccess) {
+            r = bfail(b, RPY_ERR_HIP, "task list upload failed");
+            break;
         }
-    Cand best{1, 8, 1e300};
+        std::vector<double> t;
+        for (int q = 0; q < 4 && r == RPY_OK; ++q) {
+            double ms = 0.0;
+            r = batch_time<Real>(b, F, nullptr, out, nullptr, 1, st, e0, e1, &ms);
+            if (q > 0) t.push_back(ms);   // the first product is a warm-up
+        }
+        if (r == RPY_OK) {
+            std::sort(t.begin(), t.end());
+            screen.push_back({cd.tm, cd.wg, t[t.size() / 2]});
+        }
+    }
+    Cand best{0, 8, 1e300};
     if (r == RPY_OK) {
         std::vector<Cand> fin;
-        for (int tm : {1, 2}) {
+        for (int tm : {0, 1, 2}) {
             Cand c{tm, 8, 1e300};
             for (const Cand &x : screen)
                 if (x.tm == tm && x.ms < c.ms) c = x;
@@ -922,7 +1225,7 @@ rpy_status batch_tune(rpy_batch *b, hipStream_t st) {
                     break;
                 }
                 double ms = 0.0;
-                r = batch_time<Real>(b, F, out, burst, st, e0, e1, &ms);
+                r = batch_time<Real>(b, F, nullptr, out, nullptr, burst, st, e0, e1, &ms);
                 t[i].push_back(ms);
             }
         for (size_t i = 0; i < fin.size() && r == RPY_OK; ++i) {
@@ -944,7 +1247,7 @@ rpy_status batch_tune(rpy_batch *b, hipStream_t st) {
 extern "C" {
 
 rpy_status rpy_batch_create(int32_t n_systems, const int64_t *offsets, const double *viscosity, const double *radius,
-                            rpy_dtype dtype, rpy_batch **out) {
+                            int include_angular, rpy_dtype dtype, rpy_batch **out) {
     if (!out) return RPY_ERR_INVALID_ARG;
     *out = nullptr;
     if (n_systems <= 0 || !offsets || !viscosity || !radius) return RPY_ERR_INVALID_ARG;
@@ -965,7 +1268,10 @@ rpy_status rpy_batch_create(int32_t n_systems, const int64_t *offsets, const dou
     b->eta.assign(viscosity, viscosity + n_systems);
     b->radius.assign(radius, radius + n_systems);
     b->ntot = offsets[n_systems];
-    // systems longest first (the task list is built from this order)
+    b->angular = include_angular != 0;
+    b->nrs = b->angular ? 3 : 2;
+    b->vmul = b->angular ? 6 : 3;
+    // systems longest first (the task lists are built from this order)
     b->order.resize(n_systems);
     std::iota(b->order.begin(), b->order.end(), 0);
     std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
@@ -977,10 +1283,10 @@ rpy_status rpy_batch_create(int32_t n_systems, const int64_t *offsets, const dou
     std::vector<int64_t> blo, bhi;
     for (int s = 0; s < n_systems; ++s) {
         b0[s] = (int)bsys.size();
-        for (int64_t lo = 3 * b->off[s]; lo < 3 * b->off[s + 1]; lo += kSegChunk) {
+        for (int64_t lo = b->vmul * b->off[s]; lo < b->vmul * b->off[s + 1]; lo += kSegChunk) {
             bsys.push_back(s);
             blo.push_back(lo);
-            bhi.push_back(std::min<int64_t>(lo + kSegChunk, 3 * b->off[s + 1]));
+            bhi.push_back(std::min<int64_t>(lo + kSegChunk, b->vmul * b->off[s + 1]));
         }
         b1[s] = (int)bsys.size();
     }
@@ -1004,6 +1310,7 @@ rpy_status rpy_batch_create(int32_t n_systems, const int64_t *offsets, const dou
         e = dtype == RPY_F64 ? up(b->d_pc, pcd.data(), sizeof(PairConst<double>) * n_systems)
                              : up(b->d_pc, pcf.data(), sizeof(PairConst<float>) * n_systems);
     if (e == hipSuccess) e = build_tasks(b);
+    if (e == hipSuccess) e = build_block_tasks(b);
     if (e == hipSuccess) e = up(b->d_blk_sys, bsys.data(), sizeof(int) * bsys.size());
     if (e == hipSuccess) e = up(b->d_blk_lo, blo.data(), sizeof(int64_t) * blo.size());
     if (e == hipSuccess) e = up(b->d_blk_hi, bhi.data(), sizeof(int64_t) * bhi.size());
@@ -1012,7 +1319,7 @@ rpy_status rpy_batch_create(int32_t n_systems, const int64_t *offsets, const dou
     if (e == hipSuccess) e = b->d_counter.ensure(sizeof(unsigned) * 4);
     if (e == hipSuccess) e = b->d_flag.ensure(sizeof(unsigned) * 4);
     const size_t elt = dtype == RPY_F64 ? sizeof(double4) : sizeof(float4);
-    if (e == hipSuccess) e = b->d_rec.ensure(2 * elt * b->ntot);
+    if (e == hipSuccess) e = b->d_rec.ensure((size_t)b->nrs * elt * b->ntot);
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->host_u, sizeof(unsigned) * 4, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->host_i, sizeof(int) * 4, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -1032,10 +1339,10 @@ rpy_status rpy_batch_set_positions(rpy_batch *b, const void *pos, void *hip_stre
     const dim3 g((unsigned)((b->ntot + 255) / 256));
     if (b->dtype == RPY_F64)
         hipLaunchKernelGGL((batch_stage_pos<double>), g, dim3(256), 0, st, static_cast<const double *>(pos), b->ntot,
-                           b->d_rec.as<double4>(), b->d_flag.as<unsigned>());
+                           b->nrs, b->d_rec.as<double4>(), b->d_flag.as<unsigned>());
     else
         hipLaunchKernelGGL((batch_stage_pos<float>), g, dim3(256), 0, st, static_cast<const float *>(pos), b->ntot,
-                           b->d_rec.as<float4>(), b->d_flag.as<unsigned>());
+                           b->nrs, b->d_rec.as<float4>(), b->d_flag.as<unsigned>());
     BHIP(b, hipGetLastError());
     BHIP(b, hipMemcpyAsync(b->host_u, b->d_flag.p, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     BHIP(b, hipStreamSynchronize(st));
@@ -1045,21 +1352,30 @@ rpy_status rpy_batch_set_positions(rpy_batch *b, const void *pos, void *hip_stre
     return RPY_OK;
 }
 
-rpy_status rpy_batch_mdot(rpy_batch *b, const void *forces, void *lin_out, void *hip_stream) {
+rpy_status rpy_batch_mdot(rpy_batch *b, const void *forces, const void *torques, void *lin_out, void *ang_out,
+                          void *hip_stream) {
     if (!b) return RPY_ERR_INVALID_ARG;
     if (!b->have_pos) return bfail(b, RPY_ERR_NO_POSITIONS, "rpy_batch_set_positions has not been called");
-    if (!forces || !lin_out) return bfail(b, RPY_ERR_INVALID_ARG, "forces and output must not be NULL");
+    if (!lin_out) return bfail(b, RPY_ERR_INVALID_ARG, "the linear output must not be NULL");
+    if (!b->angular && (torques || ang_out))
+        return bfail(b, RPY_ERR_ANGULAR_DISABLED, "torques / angular output need include_angular");
+    if (b->angular && !ang_out) return bfail(b, RPY_ERR_INVALID_ARG, "include_angular needs the angular output");
+    if (!forces && !torques) return bfail(b, RPY_ERR_INVALID_ARG, "need forces, torques or both");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (b->dtype == RPY_F64)
-        return batch_mdot_typed<double>(b, static_cast<const double *>(forces), static_cast<double *>(lin_out), st);
-    return batch_mdot_typed<float>(b, static_cast<const float *>(forces), static_cast<float *>(lin_out), st);
+        return batch_mdot_typed<double>(b, static_cast<const double *>(forces), static_cast<const double *>(torques),
+                                        static_cast<double *>(lin_out), static_cast<double *>(ang_out), st);
+    return batch_mdot_typed<float>(b, static_cast<const float *>(forces), static_cast<const float *>(torques),
+                                   static_cast<float *>(lin_out), static_cast<float *>(ang_out), st);
 }
 
 rpy_status rpy_batch_sqrt_mdot_w(rpy_batch *b, const void *w, double prefactor, double tol, int max_iter,
-                                 int check_every, void *lin_out, int *iters_out, void *hip_stream) {
+                                 int check_every, void *lin_out, void *ang_out, int *iters_out, void *hip_stream) {
     if (!b) return RPY_ERR_INVALID_ARG;
     if (!b->have_pos) return bfail(b, RPY_ERR_NO_POSITIONS, "rpy_batch_set_positions has not been called");
     if (!w || !lin_out) return bfail(b, RPY_ERR_INVALID_ARG, "W and the output must not be NULL");
+    if (!b->angular && ang_out) return bfail(b, RPY_ERR_ANGULAR_DISABLED, "angular output needs include_angular");
+    if (b->angular && !ang_out) return bfail(b, RPY_ERR_INVALID_ARG, "include_angular needs the angular output");
     if (!(tol > 0.0 && tol < 1.0)) return bfail(b, RPY_ERR_INVALID_ARG, "tol must be in (0, 1)");
     if (max_iter < 1 || max_iter > kMaxK)
         return bfail(b, RPY_ERR_INVALID_ARG, "max_iter must be in [1, 1024]");
@@ -1068,17 +1384,19 @@ rpy_status rpy_batch_sqrt_mdot_w(rpy_batch *b, const void *w, double prefactor, 
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (b->dtype == RPY_F64)
         return batch_sqrt_typed<double>(b, static_cast<const double *>(w), prefactor, tol, max_iter, check_every,
-                                        static_cast<double *>(lin_out), iters_out, st);
+                                        static_cast<double *>(lin_out), static_cast<double *>(ang_out), iters_out, st);
     return batch_sqrt_typed<float>(b, static_cast<const float *>(w), prefactor, tol, max_iter, check_every,
-                                   static_cast<float *>(lin_out), iters_out, st);
+                                   static_cast<float *>(lin_out), static_cast<float *>(ang_out), iters_out, st);
 }
 
 const char *rpy_batch_last_error(const rpy_batch *b) { return b ? b->err.c_str() : "null batch handle"; }
 
 rpy_status rpy_batch_set_tile_config(rpy_batch *b, int targets_per_lane, int workgroups_per_cu) {
     if (!b) return RPY_ERR_INVALID_ARG;
-    if (targets_per_lane != 1 && targets_per_lane != 2)
-        return bfail(b, RPY_ERR_INVALID_ARG, "targets per lane must be 1 or 2");
+    if (targets_per_lane != 0 && targets_per_lane != 1 && targets_per_lane != 2)
+        return bfail(b, RPY_ERR_INVALID_ARG, "targets per lane must be 0 (block mode), 1 or 2");
+    if (b->angular && targets_per_lane != 0)
+        return bfail(b, RPY_ERR_INVALID_ARG, "with angular blocks only the block mode (0) exists");
     if (workgroups_per_cu < 1 || workgroups_per_cu > 32)
         return bfail(b, RPY_ERR_INVALID_ARG, "workgroups per CU must be in [1, 32]");
     b->tm = targets_per_lane;
@@ -1103,6 +1421,9 @@ rpy_status rpy_batch_autotune(rpy_batch *b, void *hip_stream) {
 
 void rpy_batch_destroy(rpy_batch *b) {
     if (!b) return;
+    for (DevBuf *d : {&b->d_btask, &b->d_bsys, &b->d_joff, &b->d_bslot0, &b->d_soff, &b->d_chunks, &b->d_psys,
+                      &b->d_ipart, &b->d_jpart})
+        d->release();
     for (DevBuf *d : {&b->d_off, &b->d_kfac, &b->d_pc, &b->d_tasks, &b->d_counter, &b->d_rec, &b->d_flag,
                       &b->d_blk_sys, &b->d_blk_lo, &b->d_blk_hi, &b->d_sys_b0, &b->d_sys_b1, &b->d_kmax, &b->V,
                       &b->w, &b->lanc, &b->red, &b->Q, &b->status, &b->ints, &b->pref, &b->mon})

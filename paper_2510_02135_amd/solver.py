@@ -287,10 +287,12 @@ class Batch:
     """Many independent open-boundary systems solved together.
 
     System s owns rows offsets[s]:offsets[s+1] of the concatenated (total, 3)
-    positions / forces / outputs.  Translational blocks only.
+    positions / forces / torques / outputs; noise vectors give it entries
+    m*offsets[s]:m*offsets[s+1] (m = 3, or 6 with includeAngular: the
+    system's linear entries, then its angular ones).
     """
 
-    def __init__(self, offsets, viscosity, radius, dtype=torch.float32, device=None):
+    def __init__(self, offsets, viscosity, radius, dtype=torch.float32, device=None, includeAngular: bool = False):
         import numpy as np
         self.offsets = np.asarray(offsets, dtype=np.int64)
         self.n_systems = int(self.offsets.shape[0] - 1)
@@ -298,22 +300,32 @@ class Batch:
         vis = np.broadcast_to(np.asarray(viscosity, dtype=np.float64), (self.n_systems,))
         rad = np.broadcast_to(np.asarray(radius, dtype=np.float64), (self.n_systems,))
         self._dtype = dtype
+        self._angular = bool(includeAngular)
         self._device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
-        self._h = _lib.rpy_batch_create(self.offsets, vis, rad, dtype)
+        self._h = _lib.rpy_batch_create(self.offsets, vis, rad, dtype, self._angular)
         self.last_iterations = None
+
+    @property
+    def includeAngular(self) -> bool:
+        return self._angular
 
     def setPositions(self, positions: torch.Tensor):
         _lib.rpy_batch_set_positions(self._h, positions.reshape(-1, 3).contiguous(), self._dtype, self.total)
 
-    def Mdot(self, forces: torch.Tensor):
+    def _vec(self, t):
+        return None if t is None else t.reshape(-1, 3).contiguous()
+
+    def Mdot(self, forces: torch.Tensor | None = None, torques: torch.Tensor | None = None):
+        """Linear velocities (total, 3); with includeAngular, (linear, angular)."""
         out = torch.empty((self.total, 3), dtype=self._dtype, device=self._device)
-        _lib.rpy_batch_mdot(self._h, forces.reshape(-1, 3).contiguous(), out, self._dtype, self.total)
-        return out
+        ang = torch.empty_like(out) if self._angular else None
+        _lib.rpy_batch_mdot(self._h, self._vec(forces), self._vec(torques), out, ang, self._dtype, self.total)
+        return (out, ang) if self._angular else out
 
     def autotune(self):
-        """Time the batched pair kernel's configurations on the current
-        systems and keep the fastest; returns (targets per lane, workgroups
-        per CU)."""
+        """Time the batched product's configurations on the current systems
+        and keep the fastest; returns (targets per lane (0 = block mode),
+        workgroups per CU)."""
         _lib.rpy_batch_autotune(self._h)
         return self.tileConfig()
 
@@ -325,11 +337,14 @@ class Batch:
 
     def sqrtMdotW(self, W: torch.Tensor, prefactor: float = 1.0, tol: float = 1e-6, maxIter: int = 500,
                   checkEvery: int = 4):
+        """prefactor M_s^{1/2} W_s for every system: (total, 3), or (linear,
+        angular) with includeAngular."""
         out = torch.empty((self.total, 3), dtype=self._dtype, device=self._device)
+        ang = torch.empty_like(out) if self._angular else None
         self.last_iterations = _lib.rpy_batch_sqrt_mdot_w(self._h, W.reshape(-1).contiguous(), prefactor, tol,
-                                                          maxIter, checkEvery, out, self._dtype, self.total,
+                                                          maxIter, checkEvery, out, ang, self._dtype, self.total,
                                                           self.n_systems)
-        return out
+        return (out, ang) if self._angular else out
 
     def close(self):
         if getattr(self, "_h", None):

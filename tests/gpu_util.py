@@ -12,7 +12,10 @@ def emax(got, ref) -> float:
     got = np.asarray(got, dtype=np.float64).reshape(-1, 3)
     ref = np.asarray(ref, dtype=np.float64).reshape(-1, 3)
     den = np.linalg.norm(ref, axis=1).max()
-    return float(np.linalg.norm(got - ref, axis=1).max() / den)
+    num = np.linalg.norm(got - ref, axis=1).max()
+    if den == 0.0:   # an exactly zero reference must be matched exactly
+        return 0.0 if num == 0.0 else float("inf")
+    return float(num / den)
 
 
 def say(*args):

@@ -154,22 +154,21 @@ def test_batch_create_checks(lib):
     import numpy as np
     P = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))
     lib.rpy_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
-                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_void_p)]
     one = np.ones(2)
     out = ctypes.c_void_p()
+    create = lambda off, eta, rad, ang, dt: lib.rpy_batch_create(2, P(off, ctypes.c_int64), P(eta, ctypes.c_double),
+                                                                 P(rad, ctypes.c_double), ang, dt, ctypes.byref(out))
     bad_off = np.array([0, 3, 3], dtype=np.int64)
-    assert lib.rpy_batch_create(2, P(bad_off, ctypes.c_int64), P(one, ctypes.c_double), P(one, ctypes.c_double), 0,
-                                ctypes.byref(out)) == 5
+    assert create(bad_off, one, one, 0, 0) == 5
     off = np.array([1, 3, 4], dtype=np.int64)
-    assert lib.rpy_batch_create(2, P(off, ctypes.c_int64), P(one, ctypes.c_double), P(one, ctypes.c_double), 0,
-                                ctypes.byref(out)) == 5
+    assert create(off, one, one, 1, 0) == 5
     off = np.array([0, 3, 4], dtype=np.int64)
     neg = np.array([1.0, -1.0])
-    assert lib.rpy_batch_create(2, P(off, ctypes.c_int64), P(neg, ctypes.c_double), P(one, ctypes.c_double), 0,
-                                ctypes.byref(out)) == INVALID
-    assert lib.rpy_batch_create(2, P(off, ctypes.c_int64), P(one, ctypes.c_double), P(one, ctypes.c_double), 7,
-                                ctypes.byref(out)) == DTYPE
-    assert lib.rpy_batch_create(0, P(off, ctypes.c_int64), P(one, ctypes.c_double), P(one, ctypes.c_double), 0,
+    assert create(off, neg, one, 0, 0) == INVALID
+    assert create(off, one, one, 1, 7) == DTYPE
+    assert lib.rpy_batch_create(0, P(off, ctypes.c_int64), P(one, ctypes.c_double), P(one, ctypes.c_double), 0, 0,
                                 ctypes.byref(out)) == INVALID
 
 

@@ -1,6 +1,8 @@
 """GPU parity of the batched solver (many independent systems in one
-persistent launch; Lanczos replayed from captured HIP graphs) against the
-float64 oracle, per system, through the C interface."""
+launch: the block mode, each system's unordered pairs once, and the
+one-sided persistent kernel; Lanczos replayed from captured HIP graphs)
+against the float64 oracle, per system, through the C interface; with and
+without angular blocks."""
 import math
 
 import numpy as np
@@ -25,26 +27,29 @@ def _systems(sizes, seed, phi=0.15):
     return out
 
 
-def _batch(systems, dtype, eta=None, radius=None):
+def _batch(systems, dtype, eta=None, radius=None, angular=False, tm=None):
     import paper_2510_02135_amd as rpy
     ns = [len(s[0]) for s in systems]
     off = np.concatenate([[0], np.cumsum(ns)])
     eta = np.full(len(ns), 1 / (6 * math.pi)) if eta is None else eta
     radius = np.ones(len(ns)) if radius is None else radius
-    b = rpy.Batch(off, eta, radius, dtype)
+    b = rpy.Batch(off, eta, radius, dtype, includeAngular=angular)
+    if tm is not None:
+        b.setTileConfig(tm, 8)
     pos = torch.tensor(np.concatenate([s[0] for s in systems]), dtype=dtype, device="cuda")
     b.setPositions(pos)
     return b, off
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_batched_mdot_per_system(dtype):
-    sizes = [1, 2, 3, 64, 65, 130, 257, 300, 17, 511]
-    say(f"case batch mdot sizes={sizes} {dtype}")
+@pytest.mark.parametrize("tm", [0, 1])
+def test_batched_mdot_per_system(dtype, tm):
+    sizes = [1, 2, 3, 64, 65, 130, 257, 300, 17, 511, 512, 513, 1100, 1600]
+    say(f"case batch mdot sizes={sizes} tm={tm} {dtype}")
     systems = _systems(sizes, 11)
     eta = np.linspace(0.5, 1.5, len(sizes))
     rad = np.linspace(0.7, 1.4, len(sizes))
-    b, off = _batch(systems, dtype, eta, rad)
+    b, off = _batch(systems, dtype, eta, rad, tm=tm)
     F = torch.tensor(np.concatenate([s[1] for s in systems]), dtype=dtype, device="cuda")
     U = host(b.Mdot(F))
     worst = 0.0
@@ -52,6 +57,33 @@ def test_batched_mdot_per_system(dtype):
         u_ref, _ = mobility.mdot_dense(rounded(x, dtype), rounded(f, dtype), None, rad[k], eta[k])
         e = emax(U[off[k]:off[k + 1]], u_ref)
         worst = max(worst, e)
+    say(f"  worst system e_max {worst:.3e}")
+    assert worst <= tol_for(dtype)
+    # deterministic: a repeated product is bitwise equal
+    np.testing.assert_array_equal(U, host(b.Mdot(F)))
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batched_angular_mdot_per_system(dtype):
+    sizes = [1, 2, 70, 300, 511, 513, 1030, 40]
+    say(f"case batch angular mdot sizes={sizes} {dtype}")
+    systems = _systems(sizes, 21, phi=0.2)
+    rng = np.random.default_rng(22)
+    eta = np.linspace(0.6, 1.3, len(sizes))
+    rad = np.linspace(0.8, 1.2, len(sizes))
+    b, off = _batch(systems, dtype, eta, rad, angular=True)
+    F = np.concatenate([s[1] for s in systems])
+    T = rng.standard_normal(F.shape)
+    t = lambda v: torch.tensor(v, dtype=dtype, device="cuda")
+    U, Om = (host(v) for v in b.Mdot(t(F), t(T)))
+    Ut, Omt = (host(v) for v in b.Mdot(None, t(T)))
+    worst = 0.0
+    for k, (x, f, _) in enumerate(systems):
+        sl = slice(off[k], off[k + 1])
+        xr, fr, tr = rounded(x, dtype), rounded(f, dtype), rounded(T[sl], dtype)
+        u_ref, w_ref = mobility.mdot_dense(xr, fr, tr, rad[k], eta[k])
+        ut_ref, wt_ref = mobility.mdot_dense(xr, None, tr, rad[k], eta[k])
+        worst = max(worst, emax(U[sl], u_ref), emax(Om[sl], w_ref), emax(Ut[sl], ut_ref), emax(Omt[sl], wt_ref))
     say(f"  worst system e_max {worst:.3e}")
     assert worst <= tol_for(dtype)
 
@@ -76,22 +108,23 @@ def test_batched_mdot_every_tile_config_and_autotune(dtype):
         say(f"  {tag}: worst system e_max {worst:.3e}")
         assert worst <= tol_for(dtype)
 
-    for tm in (1, 2):
+    for tm in (0, 1, 2):
         for wg in (1, 4, 16, 32):
             b.setTileConfig(tm, wg)
             assert b.tileConfig() == (tm, wg)
             check(f"tm={tm} wg={wg}")
     chosen = b.autotune()
-    assert chosen[0] in (1, 2) and chosen[1] in (4, 8, 16)
+    assert chosen[0] in (0, 1, 2) and chosen[1] in (4, 8, 16)
     check(f"autotuned {chosen}")
-    for bad in ((0, 8), (3, 8), (1, 0), (1, 33)):
+    for bad in ((-1, 8), (3, 8), (1, 0), (1, 33)):
         with pytest.raises(rpy.RpyError):
             b.setTileConfig(*bad)
     assert b.tileConfig() == chosen
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-def test_batched_lanczos_matched_iterations_and_eager_replay(dtype, monkeypatch):
+@pytest.mark.parametrize("tm", [0, 1])
+def test_batched_lanczos_matched_iterations_and_eager_replay(dtype, tm, monkeypatch):
     """Each system stops where the oracle's Lanczos stops (float64; float32
     within one iteration, since float32 products can move an increment that
     lies within rounding of tol), matches the oracle's Lanczos at the
@@ -100,10 +133,10 @@ def test_batched_lanczos_matched_iterations_and_eager_replay(dtype, monkeypatch)
     contributes).  The host poll interval changes nothing; the exact test at
     every iteration changes nothing but the rounding of s_k."""
     import paper_2510_02135_amd as rpy
-    sizes = [1, 5, 40, 97, 200, 333]
-    say(f"case batch lanczos sizes={sizes} {dtype}")
+    sizes = [1, 5, 40, 97, 200, 333, 600]
+    say(f"case batch lanczos sizes={sizes} tm={tm} {dtype}")
     systems = _systems(sizes, 12, phi=0.2)
-    b, off = _batch(systems, dtype)
+    b, off = _batch(systems, dtype, tm=tm)
     W = torch.tensor(np.concatenate([s[2] for s in systems]), dtype=dtype, device="cuda")
     Y = host(b.sqrtMdotW(W, prefactor=0.7, tol=1e-6, checkEvery=3)).reshape(-1)
     iters = list(b.last_iterations)
@@ -218,3 +251,37 @@ def test_c4_512_systems_sampled():
             say(f"  system {k} N={s.n} it={iters[k]} (oracle stops at {info.iters}) mdot {e:.2e} lanczos {e2:.2e}")
             assert e2 <= 1e-5
             assert abs(int(iters[k]) - info.iters) <= 1
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_batched_angular_lanczos_matched_iterations(dtype):
+    """With angular blocks each system's noise vector holds its 3 n_s linear
+    entries, then its 3 n_s angular ones; each system stops where the
+    oracle's Lanczos on its 6 n_s x 6 n_s grand mobility stops and matches
+    it at that iteration."""
+    sizes = [3, 60, 250, 520]
+    say(f"case batch angular lanczos sizes={sizes} {dtype}")
+    systems = _systems(sizes, 31, phi=0.2)
+    b, off = _batch(systems, dtype, angular=True)
+    rng = np.random.default_rng(32)
+    Ws = [rng.standard_normal(6 * len(x)) for x, _, _ in systems]
+    W = torch.tensor(np.concatenate(Ws), dtype=dtype, device="cuda")
+    lin, ang = b.sqrtMdotW(W, prefactor=0.5, tol=1e-6, checkEvery=2)
+    lin, ang = host(lin), host(ang)
+    iters = list(b.last_iterations)
+    say(f"  iterations {iters}")
+    a, eta = 1.0, 1 / (6 * math.pi)
+    for k, (x, _, _) in enumerate(systems):
+        xr, wr = rounded(x, dtype), rounded(Ws[k], dtype)
+        m = mobility.grand_mobility(xr, a, eta, angular=True)
+        _, info = lanczos.lanczos_sqrt(lambda v: m @ v, wr, tol=1e-6)
+        if dtype == torch.float64:
+            assert iters[k] == info.iters
+        else:
+            assert abs(iters[k] - info.iters) <= 1
+        y_ref, _ = lanczos.lanczos_sqrt(lambda v: m @ v, wr, iters=iters[k], prefactor=0.5)
+        sl = slice(off[k], off[k + 1])
+        y = np.concatenate([lin[sl].reshape(-1), ang[sl].reshape(-1)])
+        e = float(np.abs(y - y_ref).max() / np.abs(y_ref).max())
+        say(f"  system {k}: N={len(x)} it={iters[k]} (oracle {info.iters}) max rel {e:.2e}")
+        assert e <= (1e-12 if dtype == torch.float64 else 1e-5)
