@@ -73,6 +73,9 @@ def parse():
     p.add_argument("--batch-only", nargs="?", const="all", default=None, choices=("all", "mdot"),
                    help="instead of the step: only the 512 batched systems (one launch against one per system); "
                         "'mdot' stops after the batched products")
+    p.add_argument("--chains-solve", action="store_true",
+                   help="instead of the step: the converged sqrtMdotW (tol 1e-6, float32 pairs, angular) of the "
+                        "4096 x 256-bead chains, plain and preconditioned with one chain per group")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     return p.parse_args()
@@ -334,6 +337,33 @@ def main():
                           "config": {"workload": "uniform cubes, N = 2^10 .. 2^20, number density 0.1 and 0.001 "
                                                  "per a^3, a = 1, eta = 1/(6 pi), seeds 2010 .. 2020"},
                           "sweep": sweep}), flush=True)
+        return
+    if args.chains_solve:
+        c5 = workloads.c5_chains()
+        sc = rpy.Solver()
+        sc.initialize(viscosity=c5.viscosity, hydrodynamicRadius=c5.radius, includeAngular=True)
+        sc.setPositions(torch.tensor(c5.pos, dtype=torch.float32, device=dev))
+        sc.setTileConfig(True, 0, 0)
+        Wc = torch.tensor(c5.w, dtype=torch.float32, device=dev)
+        res = {}
+        for name in ("preconditioned", "plain"):
+            print(f"bench: chains sqrtMdotW {name}", file=sys.stderr, flush=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "plain":
+                sc.sqrtMdotW(Wc, tol=1e-6, maxIter=1000)
+            else:
+                sc.sqrtMdotWPrecond(Wc, groupSize=256, tol=1e-6, maxIter=1000)
+            torch.cuda.synchronize()
+            res[name] = {"seconds": round(time.perf_counter() - t0, 2), "iterations": sc.last_iterations,
+                         "increment": sc.last_increment}
+            print(f"bench: {name} {res[name]}", file=sys.stderr, flush=True)
+        print(json.dumps({"metric": "sqrtMdotW of the bead chains, converged (tol 1e-6)", "unit": "s",
+                          "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": "4096 random-walk chains x 256 beads (N = 1,048,576), bond 2.1a, "
+                                                 "phi 0.05, seed 1005, torques, 6N noise; symmetric pair mode; "
+                                                 "preconditioner: one chain (256 beads) per group"},
+                          "chains_solve": res}), flush=True)
         return
     if args.batch_only:
         print(json.dumps({"metric": "batched systems: Mdot and sqrtMdotW time (float32)", "unit": "ms",

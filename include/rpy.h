@@ -215,6 +215,28 @@ rpy_status rpy_sqrt_mdot_w_multi(rpy_solver *s, const void *w, int nrhs, double 
                                  double *incr_out, void *hip_stream);
 
 /*
+ * Preconditioned fluctuations (Sec. 3.3 notes that a preconditioner can
+ * speed up the Lanczos iteration; an addition beside the paper's release):
+ *   y = prefactor * L (L^{-1} M L^{-T})^{1/2} w,
+ * with L block diagonal: particles form groups of group_size consecutive
+ * particles (1 <= group_size <= 512; the last group may be shorter; e.g. one
+ * polymer chain or rigid body per group), and for each group L holds the
+ * Cholesky factor of M restricted to the group's linear rows and,
+ * separately, to its angular rows.  y y^T has expectation M for w ~ N(0, I)
+ * (eq. (fdt) holds, as for the symmetric root), but y is not M^{1/2} w.  The
+ * Lanczos iteration, its stopping rule (on the iterate z of the
+ * preconditioned operator), tol, max_iter, the outputs and the status codes
+ * are those of rpy_sqrt_mdot_w.  The blocks are assembled in float64 from
+ * the stored positions (open or single-wall geometry) and factored once per
+ * positions and group size, then kept: about (6 G)^2 x N / G x 8 bytes
+ * (half without angular blocks) of device memory.  RPY_ERR_NOT_SPD when a
+ * block is not positive definite.  Synchronises hip_stream.
+ */
+rpy_status rpy_sqrt_mdot_w_precond(rpy_solver *s, const void *w, int64_t group_size, double prefactor,
+                                   double tol, int max_iter, void *lin_out, void *ang_out, int *iters_out,
+                                   double *incr_out, void *hip_stream);
+
+/*
  * Mobility solve by conjugate gradients (an addition beside the paper's
  * method: a Krylov consumer of the product): for r = 0 .. nrhs-1 finds
  * [F_r; T_r] with M [F_r; T_r] = [U_r; Omega_r], the forces (and torques)

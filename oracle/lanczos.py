@@ -124,3 +124,52 @@ def exact_inv_sqrt(m):
     """M^{-1/2} through the eigendecomposition (the FDT test of Sec. 4)."""
     lam, q = np.linalg.eigh(m)
     return (q / np.sqrt(lam)) @ q.T
+
+
+def group_cholesky(m, n_particles: int, group: int, angular: bool = False):
+    """Block-diagonal lower-triangular L for the preconditioned Lanczos.
+
+    Particles are split into groups of ``group`` consecutive particles (the
+    last one may be shorter).  For each group, L holds the lower Cholesky
+    factor of M restricted to the group's linear rows and columns (3 per
+    particle, in the vector's order) and, with ``angular``, separately of its
+    angular rows and columns; every other entry of L is zero.  Returns L as
+    a dense (3N or 6N) square matrix.
+    """
+    dim = (6 if angular else 3) * n_particles
+    L = np.zeros((dim, dim))
+    for g0 in range(0, n_particles, group):
+        p = np.arange(g0, min(n_particles, g0 + group))
+        lin = (3 * p[:, None] + np.arange(3)).reshape(-1)
+        for idx in ([lin, lin + 3 * n_particles] if angular else [lin]):
+            L[np.ix_(idx, idx)] = np.linalg.cholesky(m[np.ix_(idx, idx)])
+    return L
+
+
+def preconditioned_lanczos_sqrt(matvec, L, w, tol: float = 1e-6, maxit: int = 500, prefactor: float = 1.0,
+                                iters: int | None = None):
+    """prefactor * L (L^{-1} M L^{-T})^{1/2} w, the square root of the
+    preconditioned operator taken by ``lanczos_sqrt`` (same recurrence,
+    re-orthogonalisation and stopping rule, applied to the iterate z of the
+    preconditioned operator), then multiplied by L.
+
+    With y = L z and z = (L^{-1} M L^{-T})^{1/2} w, y y^T has expectation
+    L L^{-1} M L^{-T} L^T = M for w ~ N(0, I): a valid fluctuating term of
+    eq. (bdhi) (Sec. 3.3 notes that a preconditioner can speed up Lanczos),
+    though not the symmetric root M^{1/2} w.
+    """
+    from scipy.linalg import solve_triangular
+
+    def op(v):
+        t = solve_triangular(L, v, lower=True, trans="T")
+        return solve_triangular(L, np.asarray(matvec(t), dtype=np.float64), lower=True)
+
+    z, info = lanczos_sqrt(op, w, tol=tol, maxit=maxit, prefactor=1.0, iters=iters)
+    return prefactor * (L @ z), info
+
+
+def exact_preconditioned_sqrt(m, L, w, prefactor: float = 1.0):
+    """prefactor * L (L^{-1} M L^{-T})^{1/2} w from an eigendecomposition."""
+    from scipy.linalg import solve_triangular
+    li = solve_triangular(L, np.eye(L.shape[0]), lower=True)
+    return prefactor * (L @ exact_sqrt_mdot_w(li @ m @ li.T, w))

@@ -79,6 +79,7 @@ def load() -> ctypes.CDLL:
         "rpy_set_multi_config": ([vp, i], i),
         "rpy_sqrt_mdot_w": ([vp, vp, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_sqrt_mdot_w_multi": ([vp, vp, i, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
+        "rpy_sqrt_mdot_w_precond": ([vp, vp, i64, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_mobility_solve": ([vp, vp, vp, i, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_div_m": ([vp, vp, vp, vp], i),
         "rpy_div_m_rfd": ([vp, vp, d, vp, vp, vp], i),
@@ -201,6 +202,20 @@ def rpy_sqrt_mdot_w(h, w, prefactor, tol, max_iter, lin_out, ang_out, dtype, n, 
                                 float(tol), int(max_iter), _ptr(lin_out, dtype, 3 * n, "lin_out"),
                                 _ptr(ang_out, dtype, 3 * n, "ang_out"), ctypes.byref(iters),
                                 ctypes.byref(incr), _stream(lin_out))
+    if st == Status.NOT_CONVERGED:
+        raise NotConvergedError(st, load().rpy_last_error(h).decode(), (lin_out, ang_out),
+                                iters.value, incr.value)
+    _check(h, st)
+    return iters.value, incr.value
+
+
+def rpy_sqrt_mdot_w_precond(h, w, group_size, prefactor, tol, max_iter, lin_out, ang_out, dtype, n, angular):
+    iters = ctypes.c_int(0)
+    incr = ctypes.c_double(0.0)
+    st = load().rpy_sqrt_mdot_w_precond(h, _ptr(w, dtype, (6 if angular else 3) * n, "W"), int(group_size),
+                                        float(prefactor), float(tol), int(max_iter),
+                                        _ptr(lin_out, dtype, 3 * n, "lin_out"), _ptr(ang_out, dtype, 3 * n, "ang_out"),
+                                        ctypes.byref(iters), ctypes.byref(incr), _stream(lin_out))
     if st == Status.NOT_CONVERGED:
         raise NotConvergedError(st, load().rpy_last_error(h).decode(), (lin_out, ang_out),
                                 iters.value, incr.value)

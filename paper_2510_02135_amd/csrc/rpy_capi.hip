@@ -195,6 +195,7 @@ rpy_status rpy_set_positions(rpy_solver *s, const void *pos, int64_t n, rpy_dtyp
     s->n = n;
     s->dtype = dtype;
     s->have_pos = true;
+    ++s->pos_version;
     s->err.clear();
     return RPY_OK;
 }
@@ -276,6 +277,7 @@ void rpy_destroy(rpy_solver *s) {
             (void)hipEventDestroy(pr.first);
             (void)hipEventDestroy(pr.second);
         }
+    precond_release(s);
     if (s->host_flag) (void)hipHostFree(s->host_flag);
     if (s->host_stat) (void)hipHostFree(s->host_stat);
     delete s;

@@ -93,6 +93,13 @@ struct rpy_solver {
     // symmetric pair mode: task lists of the forward and adjoint kernels, source-side partials
     rpy::SymTasks sym_fwd, sym_adj;
     rpy::DevBuf sym_jpart, sym_state;
+    // preconditioned Lanczos: Cholesky blocks of groups of pc_group particles
+    // (pc_parts = 1, or 2 with angular rows), valid for positions pc_version
+    rpy::DevBuf pc_L, pc_tmp, pc_info;
+    int pc_group = 0, pc_parts = 0;
+    bool pc_valid = false;
+    uint64_t pos_version = 0, pc_version = 0;
+    void *blas = nullptr;   // library handle of the batched Cholesky
     int adjoint_mode = 0;     // rpy_set_adjoint_mode: 0 automatic, 1 one-sided, 2 symmetric
     // launch timing (rpy_enable_timing): event pairs and pair counts per kernel class
     bool timing = false;

@@ -275,9 +275,23 @@ int grid_for(int64_t n) { return (int)std::min<int64_t>(2048, std::max<int64_t>(
 // one multi-vector product for several.
 template <typename Real>
 rpy_status lanczos_products(rpy_solver *s, const std::vector<LzRec *> &act, int64_t ld, int col, double *W,
-                            hipStream_t st) {
+                            hipStream_t st, bool pre = false) {
     const int64_t np = s->n;
     const bool am = s->angular;
+    if (pre) {
+        // preconditioned operator L^{-1} M L^{-T} applied to the basis column
+        double *t = s->pc_tmp.as<double>();
+        rpy_status r = precond_solve_lt(s, act[0]->V + (size_t)col * ld, t, st);
+        if (r != RPY_OK) return r;
+        const size_t elt = sizeof(vec4_t<Real>);
+        HIP_TRY(s, s->f.ensure(elt * (size_t)np));
+        if (am) HIP_TRY(s, s->t.ensure(elt * (size_t)np));
+        HIP_TRY(s, (launch_stage_vec<double, Real>(t, np, s->f.as<vec4_t<Real>>(), st)));
+        if (am) HIP_TRY(s, (launch_stage_vec<double, Real>(t + 3 * np, np, s->t.as<vec4_t<Real>>(), st)));
+        r = apply_staged<Real, double>(s, am, W, am ? W + 3 * np : nullptr, st);
+        if (r != RPY_OK) return r;
+        return precond_solve_l(s, W, st);
+    }
     const int m = (int)act.size();
     const size_t elt = sizeof(vec4_t<Real>);
     HIP_TRY(s, s->f.ensure(elt * (size_t)m * np));
@@ -304,7 +318,8 @@ rpy_status lanczos_products(rpy_solver *s, const std::vector<LzRec *> &act, int6
 template <typename Tio>
 rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t wstride, double prefactor,
                              double tol, int max_iter, Tio *lin, Tio *ang, int64_t ostride, int *iters_out,
-                             double *incr_out, hipStream_t st, bool accumulate) {
+                             double *incr_out, hipStream_t st, bool accumulate, bool pre) {
+    if (pre && nrhs != 1) return fail(s, RPY_ERR_INVALID_ARG, "the preconditioned iteration takes one noise vector");
     const bool ang_mode = s->angular;
     const int64_t np = s->n;
     const int64_t n = (ang_mode ? 6 : 3) * np;
@@ -421,8 +436,8 @@ rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t w
             if (!R.done) act.push_back(&R);
         if (act.empty()) break;
         // w_j = M v_k for every running recurrence (slot j)
-        r = fp32 ? lanczos_products<float>(s, act, ld, k - 1, W, st)
-                 : lanczos_products<double>(s, act, ld, k - 1, W, st);
+        r = fp32 ? lanczos_products<float>(s, act, ld, k - 1, W, st, pre)
+                 : lanczos_products<double>(s, act, ld, k - 1, W, st, pre);
         if (r != RPY_OK) return r;
         for (size_t j = 0; j < act.size(); ++j) {
             LzRec &R = *act[j];
@@ -527,10 +542,19 @@ rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t w
     bool any_not_spd = false, any_not_conv = false;
     for (int q = 0; q < nrhs; ++q) {
         LzRec &R = rec[q];
-        if (R.kf > 0)
+        if (R.kf > 0 && pre) {
+            // z = beta0 V s, then y = prefactor L z
+            double *z = s->pc_tmp.as<double>();
+            hipLaunchKernelGGL((combine_out<double>), dim3(g), dim3(256), 0, st, R.V, ld, R.kf, R.s_final, R.status,
+                               1.0, n, 3 * np, 0, z, z + 3 * np);
+            HIP_TRY(s, hipGetLastError());
+            r = precond_mul_l<Tio>(s, z, prefactor, accumulate, lin, ang, st);
+            if (r != RPY_OK) return r;
+        } else if (R.kf > 0) {
             hipLaunchKernelGGL((combine_out<Tio>), dim3(g), dim3(256), 0, st, R.V, ld, R.kf, R.s_final, R.status,
                                prefactor, n, 3 * np, accumulate ? 1 : 0, lin + q * ostride,
                                ang ? ang + q * ostride : nullptr);
+        }
         if (iters_out) iters_out[q] = R.kf;
         if (incr_out) incr_out[q] = R.incr;
         any_not_spd |= R.not_spd;
@@ -549,7 +573,7 @@ template <typename Tio>
 rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double tol, int max_iter, Tio *lin,
                        Tio *ang, int *iters_out, double *incr_out, hipStream_t st, bool accumulate) {
     return lanczos_run_multi<Tio>(s, w_in, 1, 0, prefactor, tol, max_iter, lin, ang, 0, iters_out, incr_out, st,
-                                  accumulate);
+                                  accumulate, false);
 }
 
 template rpy_status lanczos_run<float>(rpy_solver *, const float *, double, double, int, float *, float *, int *,
@@ -557,9 +581,9 @@ template rpy_status lanczos_run<float>(rpy_solver *, const float *, double, doub
 template rpy_status lanczos_run<double>(rpy_solver *, const double *, double, double, int, double *, double *, int *,
                                         double *, hipStream_t, bool);
 template rpy_status lanczos_run_multi<float>(rpy_solver *, const float *, int, int64_t, double, double, int, float *,
-                                             float *, int64_t, int *, double *, hipStream_t, bool);
+                                             float *, int64_t, int *, double *, hipStream_t, bool, bool);
 template rpy_status lanczos_run_multi<double>(rpy_solver *, const double *, int, int64_t, double, double, int,
-                                              double *, double *, int64_t, int *, double *, hipStream_t, bool);
+                                              double *, double *, int64_t, int *, double *, hipStream_t, bool, bool);
 
 }  // namespace rpy
 

@@ -69,10 +69,24 @@ rpy_status lanczos_run(rpy_solver *s, const Tio *w_in, double prefactor, double 
 // w_in + r * wstride, outputs at lin / ang + r * ostride, iters_out and
 // incr_out (host, nrhs entries, may be NULL).  Every recurrence stops and
 // ends as it would alone.
+// With `pre` (nrhs = 1) the iteration runs on the preconditioned operator
+// L^{-1} M L^{-T} of precond_setup and the result is prefactor * L z.
 template <typename Tio>
 rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t wstride, double prefactor,
                              double tol, int max_iter, Tio *lin, Tio *ang, int64_t ostride, int *iters_out,
-                             double *incr_out, hipStream_t st, bool accumulate);
+                             double *incr_out, hipStream_t st, bool accumulate, bool pre = false);
+
+// Block-diagonal Lanczos preconditioner (rpy_precond.hip): setup for groups
+// of `group` consecutive particles at the stored positions (cached until
+// they change), out = L^{-T} v, w = L^{-1} w, and outputs = prefactor L z
+// (+ outputs when accumulating); vectors of 3N (6N) float64 entries.
+rpy_status precond_setup(rpy_solver *s, int64_t group, hipStream_t st);
+rpy_status precond_solve_lt(rpy_solver *s, const double *v, double *out, hipStream_t st);
+rpy_status precond_solve_l(rpy_solver *s, double *w, hipStream_t st);
+template <typename Tout>
+rpy_status precond_mul_l(rpy_solver *s, const double *z, double prefactor, bool accumulate, Tout *lin, Tout *ang,
+                         hipStream_t st);
+void precond_release(rpy_solver *s);
 
 }  // namespace rpy
 

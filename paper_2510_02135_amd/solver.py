@@ -137,6 +137,27 @@ class Solver:
         self.last_iterations, self.last_increment = it, inc
         return lin, ang
 
+    def sqrtMdotWPrecond(self, W: torch.Tensor | None = None, groupSize: int = 1, prefactor: float = 1.0,
+                         tol: float = 1e-6, maxIter: int = 500, generator: torch.Generator | None = None):
+        """prefactor * L (L^{-1} M L^{-T})^{1/2} W with L the block Cholesky factor
+        of M over groups of groupSize consecutive particles: a fluctuating
+        term with covariance M (not the symmetric root) that needs fewer
+        Lanczos iterations when the groups hold the stiff couplings (chains,
+        rigid bodies)."""
+        self._require_positions()
+        dim = (6 if self._angular else 3) * self._n
+        if W is None:
+            W = torch.randn(dim, dtype=self._dtype, device=self._device, generator=generator)
+        w = W.reshape(-1)
+        if w.dtype != self._dtype:
+            raise ValueError(f"DTYPE_MISMATCH: W is {w.dtype}, positions are {self._dtype}")
+        lin = self._empty()
+        ang = self._empty() if self._angular else None
+        it, inc = _lib.rpy_sqrt_mdot_w_precond(self._h, w.contiguous(), groupSize, prefactor, tol, maxIter, lin, ang,
+                                               self._dtype, self._n, self._angular)
+        self.last_iterations, self.last_increment = it, inc
+        return lin, ang
+
     def sqrtMdotWMulti(self, W: torch.Tensor, prefactor: float = 1.0, tol: float = 1e-6, maxIter: int = 500):
         """prefactor * M^{1/2} W_r for the rows of W (shape (nrhs, 3N), or
         (nrhs, 6N) with angular terms), one Lanczos recurrence per row

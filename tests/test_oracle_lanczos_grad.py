@@ -189,3 +189,70 @@ def test_rfd_sample_is_the_directional_derivative(angular):
     if angular:
         dom = np.imag(om) / h
         assert np.abs(ang - dom).max() <= 1e-7 * np.abs(dom).max()
+
+
+def _chain_matrix(n_chains=6, beads=20, angular=False):
+    import workloads
+    s = workloads.c5_chains(n_chains=n_chains, beads=beads)
+    return s.pos, mob.grand_mobility(s.pos, 1.0, 1.0 / (6.0 * math.pi), angular)
+
+
+@pytest.mark.parametrize("angular", [False, True])
+def test_preconditioned_root_covariance_is_the_mobility(angular):
+    """B = L (L^{-1} M L^{-T})^{1/2} satisfies B B^T = M (the fluctuation-
+    dissipation balance of eq. (fdt) holds for the preconditioned noise),
+    and Lanczos at k = n reproduces it (finite termination)."""
+    x, m = _chain_matrix(3, 8, angular)
+    n = x.shape[0]
+    L = lanczos.group_cholesky(m, n, 8, angular)
+    dim = m.shape[0]
+    li = scipy.linalg.solve_triangular(L, np.eye(dim), lower=True)
+    lam, q = np.linalg.eigh(li @ m @ li.T)
+    B = L @ (q * np.sqrt(lam)) @ q.T
+    assert np.abs(B @ B.T - m).max() <= 1e-12 * np.abs(m).max()
+    e = np.random.default_rng(2).standard_normal(dim)
+    assert np.abs(lanczos.exact_preconditioned_sqrt(m, L, e) - B @ e).max() <= 1e-12 * np.abs(B @ e).max()
+    assert np.abs(np.tril(L) - L).max() == 0.0
+    w = np.random.default_rng(3).standard_normal(dim)
+    y, info = lanczos.preconditioned_lanczos_sqrt(lambda v: m @ v, L, w, iters=dim)
+    ex = lanczos.exact_preconditioned_sqrt(m, L, w)
+    assert np.linalg.norm(y - ex) <= 1e-9 * np.linalg.norm(ex)
+
+
+def test_preconditioned_with_single_particle_groups_is_plain_lanczos():
+    """In open space every 3x3 self block is mu_t I, so groups of one particle
+    give L = sqrt(mu_t) I: the preconditioned iterate is the plain one at
+    every k and stops at the same iteration."""
+    x, m = _chain_matrix(4, 10)
+    L = lanczos.group_cholesky(m, x.shape[0], 1)
+    assert np.abs(L - np.sqrt(m[0, 0]) * np.eye(m.shape[0])).max() <= 1e-15
+    w = np.random.default_rng(4).standard_normal(m.shape[0])
+    y0, i0 = lanczos.lanczos_sqrt(lambda v: m @ v, w, tol=1e-6)
+    y1, i1 = lanczos.preconditioned_lanczos_sqrt(lambda v: m @ v, L, w, tol=1e-6)
+    assert i0.iters == i1.iters
+    assert np.abs(y1 - y0).max() <= 1e-12 * np.abs(y0).max()
+
+
+def test_group_preconditioner_cuts_iterations_on_chains():
+    x, m = _chain_matrix(8, 24)
+    w = np.random.default_rng(5).standard_normal(m.shape[0])
+    _, i0 = lanczos.lanczos_sqrt(lambda v: m @ v, w, tol=1e-6)
+    L = lanczos.group_cholesky(m, x.shape[0], 24)
+    _, i1 = lanczos.preconditioned_lanczos_sqrt(lambda v: m @ v, L, w, tol=1e-6)
+    assert i1.iters < 0.7 * i0.iters
+
+
+def test_preconditioned_noise_passes_the_fdt_ks_test():
+    """Sec. 4: M^{-1/2} y is standard normal for the preconditioned noise too
+    (the KS test is agnostic to which square root is used)."""
+    import scipy.stats
+    x, m = _chain_matrix(2, 12)
+    L = lanczos.group_cholesky(m, x.shape[0], 12)
+    minv = lanczos.exact_inv_sqrt(m)
+    rng = np.random.default_rng(6)
+    samples = []
+    for _ in range(300):
+        y, _ = lanczos.preconditioned_lanczos_sqrt(lambda v: m @ v, L, rng.standard_normal(m.shape[0]), tol=1e-8)
+        samples.append(minv @ y)
+    p = scipy.stats.kstest(np.concatenate(samples), "norm").pvalue
+    assert p > 1e-3
