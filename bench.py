@@ -73,6 +73,8 @@ def parse():
     p.add_argument("--batch-only", nargs="?", const="all", default=None, choices=("all", "mdot"),
                    help="instead of the step: only the 512 batched systems (one launch against one per system); "
                         "'mdot' stops after the batched products")
+    p.add_argument("--pse-only", action="store_true",
+                   help="only the triply periodic (PSE) products; one JSON line")
     p.add_argument("--chains-solve", action="store_true",
                    help="instead of the step: the converged sqrtMdotW (tol 1e-6, float32 pairs, angular) of the "
                         "4096 x 256-bead chains, plain and preconditioned with one chain per group")
@@ -272,6 +274,44 @@ def timed(fn, reps, stream, warmup=0):
     return times[len(times) // 2]
 
 
+def bench_pse(rpy, workloads, dev, stream, sizes=((1 << 20, 0.1), (1 << 17, 0.1), (1 << 17, 0.001)), tol=1e-4):
+    """Triply periodic products (PSE, forces only) on the paper's timing
+    workload: uniform random particles in a cubic box at number density
+    rho = N / V (0.1 and 0.001 / a^3), automatic splitting, tolerance 1e-4;
+    Mdot and the split fluctuations (Lanczos on the real part, tol 1e-6)."""
+    import torch
+    out = {"workload": "uniform random particles in a cubic periodic box, a = 1, eta = 1/(6 pi), forces N(0, 1); "
+                       "automatic psi, tolerance 1e-4", "tolerance": tol}
+    for n, rho in sizes:
+        s = workloads.periodic_box(n, 1010, density=rho, w=True, images=False)
+        res = {"n": n, "density": rho, "box": round(s.extra["box"][0], 3)}
+        for dt, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+            so = rpy.Solver("periodic", "periodic", "periodic")
+            L = s.extra["box"]
+            so.setParameters(Lx=L[0], Ly=L[1], Lz=L[2], tolerance=tol)
+            so.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius)
+            so.setPositions(torch.tensor(s.pos, dtype=dt, device=dev))
+            info = so.pseInfo()
+            Fd = torch.tensor(s.forces, dtype=dt, device=dev)
+            tf = timed(lambda: so.Mdot(forces=Fd), 10, stream, warmup=2)
+            r = {"mdot_ms": round(tf, 4), "particles_per_s": n / (tf * 1e-3)}
+            if name == "fp32":
+                res.update({"grid": list(info["grid"]), "xi": round(info["xi"], 4), "rc": round(info["rc"], 3),
+                            "support": info["support"]})
+                Wd = torch.tensor(s.w, dtype=dt, device=dev)
+                noise = torch.randn(so.waveNoiseShape(), dtype=dt, device=dev)
+                t0 = time.perf_counter()
+                so.sqrtMdotWSplit(Wd, noise, tol=1e-6)
+                torch.cuda.synchronize()
+                r.update({"sqrt_split_ms": round(1e3 * (time.perf_counter() - t0), 2),
+                          "sqrt_split_real_iterations": so.last_iterations})
+            res[name] = r
+            so.close()
+        out[f"n{n}_rho{rho:g}"] = res
+        print(f"bench: pse {res}", file=sys.stderr, flush=True)
+    return out
+
+
 def bench_sweep(rpy, workloads, dev, stream):
     """One translational float32 Mdot per size, N = 2^10 .. 2^20, uniform cubes
     at number density rho = 0.1 and 0.001 per a^3 (volume fractions 0.419 and
@@ -372,6 +412,13 @@ def main():
                                                  "seed 1004"},
                           "batched": bench_batched(rpy, workloads, dev, stream, timed,
                                                    mdot_only=args.batch_only == "mdot")}), flush=True)
+        return
+    if args.pse_only:
+        print(json.dumps({"metric": "periodic (PSE) Mdot throughput", "unit": "particles/s",
+                          "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": "uniform random particles, cubic periodic box, density 0.1 and "
+                                                 "0.001 / a^3, tolerance 1e-4, automatic psi"},
+                          "periodic_pse": bench_pse(rpy, workloads, dev, stream)}), flush=True)
         return
     s = workloads.c2_suspension(args.n)
     n = s.n
@@ -539,6 +586,12 @@ def main():
                     wall_res[key].update({"sqrt_ms": round(1e3 * (time.perf_counter() - t0), 1),
                                           "sqrt_iterations": so.last_iterations})
                 so.close()
+
+    # ---- triply periodic box (PSE) on the paper's timing workload ----------
+    pse = None
+    if not args.no_breakdown:
+        print("bench: periodic products", file=sys.stderr, flush=True)
+        pse = bench_pse(rpy, workloads, dev, stream)
 
     # ---- several vectors at one geometry (float32, 8 force sets; 4 noise
     # vectors) against one call per vector --------------------------------
@@ -734,6 +787,7 @@ def main():
         "breakdown": breakdown,
         "gradient_n16384": grad_c3,
         "single_wall_n32768": wall_res,
+        "periodic_pse": pse,
         "accuracy_vs_fp64_oracle": acc,
         "batched": batched,
         "chains": chains,

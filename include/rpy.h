@@ -75,22 +75,86 @@ typedef enum { RPY_F32 = 0, RPY_F64 = 1 } rpy_dtype;
  * damping that keeps M positive definite for particles overlapping the
  * wall (Sec. 3.5): heights h = z - wallHeight are raised to max(h, a) and
  * particle i's rows and columns are scaled by min(max(h_i / a, 0), 1).
+ * (periodic, periodic, periodic) gives the triply periodic RPY mobility
+ * (Sec. 3.5, "Positively Split Ewald (PSE)"; forces only): the lattice sum
+ * over wave vectors k != 0 of sinc^2(k a) (I - khat khat^T) / (eta k^2)
+ * e^{i k . r} / V, evaluated as a real-space sum of RPY - Wr over pairs
+ * closer than a cutoff (minimum image) plus a wave-space part on an FFT
+ * grid, split by Hasimoto's function with parameter psi (both parts
+ * positive definite); see rpy_set_parameter for the box and accuracy.
  * Anything else returns RPY_ERR_UNSUPPORTED_GEOMETRY and writes NULL.  The
  * caller owns *out and frees it with rpy_destroy.  Does not touch the GPU.
  * Above a wall, rpy_mdot, rpy_mdot_multi, rpy_sqrt_mdot_w(_multi),
  * rpy_div_m_rfd, rpy_mobility_solve and the deterministic (kbt = 0) time
  * steps work; rpy_div_m, rpy_mdot_backward, rpy_mdot_noalloc and the
  * stochastic (kbt > 0) time steps return RPY_ERR_UNSUPPORTED_GEOMETRY.
+ * In the periodic box, rpy_mdot, rpy_mdot_multi, rpy_sqrt_mdot_w(_multi)
+ * (Lanczos on the whole periodic M), rpy_pse_sqrt_mdot_w (the split
+ * fluctuations), rpy_div_m (zero: M depends on differences of positions
+ * and its kernel is divergence-free), rpy_div_m_rfd, rpy_mobility_solve and
+ * the time steps work; include_angular, rpy_mdot_backward, rpy_mdot_noalloc
+ * and rpy_sqrt_mdot_w_precond return RPY_ERR_UNSUPPORTED_GEOMETRY.  Results
+ * in the periodic box are reproducible to rounding, not bit for bit (the
+ * grid is accumulated with atomic additions).
  */
 rpy_status rpy_create(rpy_periodicity x, rpy_periodicity y, rpy_periodicity z, rpy_solver **out);
 
 /*
  * Domain-specific parameter by name (Sec. 3.2, setParameters).  The
  * single_wall geometry takes "wallHeight" (finite; default 0), the z of the
- * wall (particles live above it).  Open boundaries have none.  Any other key
- * or a non-finite value returns RPY_ERR_INVALID_ARG.
+ * wall (particles live above it).  The periodic geometry takes the box
+ * lengths "Lx", "Ly", "Lz" (> 0; "boxSize" sets all three; no default), the
+ * splitting parameter "psi" (xi > 0 in 1/length; 0, the default, chooses
+ * xi = (N/V)^{1/3}, raised until the cutoff fits the box) and "tolerance"
+ * (in [1e-14, 1e-2], default 1e-4): the relative accuracy each part aims
+ * at, which fixes the real-space cutoff rc (|RPY - Wr| < tolerance / (6 pi
+ * eta a) beyond it, and the root-mean-square sum of the pairs it drops, at
+ * the suspension's number density and unit random forces, below half of
+ * that), the wave cutoff kc ((1 + q) e^{-q} = tolerance, q =
+ * kc^2 / (4 xi^2)), the grid (Nyquist frequency 2 kc, sizes with factors
+ * 2, 3, 5, 7), the Gaussian width (aliasing of kc below tolerance) and its
+ * support (truncation below tolerance).  The first call that needs the
+ * configuration returns RPY_ERR_INVALID_ARG if rc reaches half the box
+ * (raise psi), the grid exceeds 4096 points per axis or the support 32.
+ * Open boundaries have none.  Any other key or a non-finite value returns
+ * RPY_ERR_INVALID_ARG.
  */
 rpy_status rpy_set_parameter(rpy_solver *s, const char *key, double value);
+
+/*
+ * Configuration of a periodic solver (Sec. 3.5, PSE) for the current
+ * parameters, computing it if needed (host quadrature of the real-space
+ * table, uploaded to the device; synchronous): grid_out = (Nx, Ny, Nz) of
+ * the Fourier grid, info_out = (xi, rc, sigma, support P, kc).  Needs
+ * rpy_initialize (and, with automatic psi, the particle count of
+ * rpy_set_positions).  RPY_ERR_UNSUPPORTED_GEOMETRY for other geometries.
+ * Either output may be NULL.
+ */
+rpy_status rpy_pse_info(rpy_solver *s, int64_t grid_out[3], double info_out[5]);
+
+/*
+ * Fluctuations of the periodic solver by the positive split (Sec. 3.5, PSE:
+ * the fluctuations are drawn in Fourier space):
+ *   lin_out = prefactor (M_real^{1/2} w + y_wave),
+ * M_real^{1/2} w by Lanczos on the real-space part alone (tol, max_iter and
+ * the stopping test of rpy_sqrt_mdot_w; w has 3N entries), y_wave a sample
+ * with covariance M_wave drawn from `wave_noise`: 3 x Nx x Ny x (Nz/2 + 1)
+ * x 2 independent N(0, 1) numbers of the solver's dtype (component, the
+ * half spectrum in FFT order, real and imaginary part), turned into unit
+ * complex normals zeta_k = (re + i im) / sqrt(2) with zeta_{-k} =
+ * conj(zeta_k): on the planes kz = 0 and kz = Nz/2, which hold both k and
+ * -k, the entry whose (kx, ky) index pair is lexicographically after its
+ * partner's (-kx mod Nx, -ky mod Ny) uses the conjugate of the partner's
+ * numbers (a self-conjugate entry its real number alone); k = 0 and the
+ * Nyquist entries are dropped.  Then y_wave,i = V^{-1/2} sum_k
+ * sqrt(Khat_w(k)) (I - khat khat^T) zeta_k e^{i k . x_i} up to the grid
+ * tolerance, Khat_w = sinc^2(k a) H(k, xi) / (eta k^2).  The covariance of
+ * lin_out is prefactor^2 (M_real + M_wave) = prefactor^2 M.  Synchronises
+ * hip_stream; iters_out / incr_out as for rpy_sqrt_mdot_w (may be NULL);
+ * RPY_ERR_NOT_CONVERGED leaves the last iterate plus the wave part.
+ */
+rpy_status rpy_pse_sqrt_mdot_w(rpy_solver *s, const void *w, const void *wave_noise, double prefactor, double tol,
+                               int max_iter, void *lin_out, int *iters_out, double *incr_out, void *hip_stream);
 
 /*
  * Shared physical parameters (Sec. 3.2, initialize): fluid viscosity eta > 0

@@ -42,7 +42,7 @@ from scipy.special import spherical_jn
 from .mobility import coefficients
 
 __all__ = ["hasimoto", "wave_radial", "real_blocks", "real_matrix", "wave_matrix", "grand_mobility_periodic",
-           "mdot_periodic", "wave_vectors", "wave_fluctuation"]
+           "mdot_periodic", "wave_vectors", "wave_fluctuation", "wave_rows", "mdot_periodic_rows"]
 
 
 def hasimoto(k, xi):
@@ -226,3 +226,38 @@ def wave_fluctuation(x, box, a: float, eta: float, xi: float, grid, noise):
     ph = np.exp(1j * (np.asarray(x) @ kv.T))                           # (N, K)
     y = ph @ (amp[:, None] * pz) / math.sqrt(L.prod())
     return y.real
+
+
+def wave_rows(x, rows, forces, box, a: float, eta: float, xi: float):
+    """Rows `rows` of M_wave F as the lattice sum applied to F directly:
+    Fhat(k) = sum_j F_j e^{-i k . x_j}, U_i = (1/(eta V)) sum_k sinc^2 H / k^2
+    (I - khat khat^T) Re(Fhat(k) e^{i k . x_i}), k != 0, |k| <= 14 xi."""
+    L = _box(box)
+    kmax = 14.0 * xi
+    nk = [int(math.floor(kmax * L[d] / (2 * math.pi))) for d in range(3)]
+    grids = np.meshgrid(*[np.arange(-m, m + 1) for m in nk], indexing="ij")
+    kv = np.stack([2 * math.pi * g.reshape(-1) / L[d] for d, g in enumerate(grids)], -1)
+    k2 = (kv * kv).sum(-1)
+    keep = (k2 > 0) & (k2 <= kmax * kmax)
+    kv, k2 = kv[keep], k2[keep]
+    kn = np.sqrt(k2)
+    coef = _sinc2(kn * a) * hasimoto(kn, xi) / (eta * L.prod() * k2)
+    khat = kv / kn[:, None]
+    x = np.asarray(x)
+    F = np.asarray(forces, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((len(rows), 3))
+    for s in range(0, kv.shape[0], 4096):
+        kk = kv[s:s + 4096]
+        fh = np.exp(-1j * (x @ kk.T)).T @ F                       # (K, 3)
+        kh = khat[s:s + 4096]
+        pf = fh - kh * (kh * fh).sum(-1, keepdims=True)           # (I - khat khat^T) Fhat
+        ph = np.exp(1j * (x[rows] @ kk.T))                        # (R, K)
+        out += (ph @ (coef[s:s + 4096, None] * pf)).real
+    return out
+
+
+def mdot_periodic_rows(x, rows, forces, box, a: float, eta: float, xi: float):
+    """Rows `rows` of M F (real part by blocks, wave part by ``wave_rows``)."""
+    F = np.asarray(forces, dtype=np.float64).reshape(-1, 3)
+    rb = real_blocks(np.asarray(x)[rows], x, box, a, eta, xi)          # (R, N, 3, 3)
+    return np.einsum("rjab,jb->ra", rb, F) + wave_rows(x, rows, F, box, a, eta, xi)

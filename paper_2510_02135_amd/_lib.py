@@ -80,6 +80,8 @@ def load() -> ctypes.CDLL:
         "rpy_sqrt_mdot_w": ([vp, vp, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_sqrt_mdot_w_multi": ([vp, vp, i, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_sqrt_mdot_w_precond": ([vp, vp, i64, d, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
+        "rpy_pse_info": ([vp, ctypes.POINTER(i64), ctypes.POINTER(d)], i),
+        "rpy_pse_sqrt_mdot_w": ([vp, vp, vp, d, d, i, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_mobility_solve": ([vp, vp, vp, i, d, i, vp, vp, ctypes.POINTER(i), ctypes.POINTER(d), vp], i),
         "rpy_div_m": ([vp, vp, vp, vp], i),
         "rpy_div_m_rfd": ([vp, vp, d, vp, vp, vp], i),
@@ -219,6 +221,26 @@ def rpy_sqrt_mdot_w_precond(h, w, group_size, prefactor, tol, max_iter, lin_out,
     if st == Status.NOT_CONVERGED:
         raise NotConvergedError(st, load().rpy_last_error(h).decode(), (lin_out, ang_out),
                                 iters.value, incr.value)
+    _check(h, st)
+    return iters.value, incr.value
+
+
+def rpy_pse_info(h):
+    """(grid (Nx, Ny, Nz), xi, rc, sigma, support P, wave cutoff kc) of a periodic solver."""
+    grid = (ctypes.c_int64 * 3)()
+    info = (ctypes.c_double * 5)()
+    _check(h, load().rpy_pse_info(h, grid, info))
+    return tuple(int(g) for g in grid), info[0], info[1], info[2], int(info[3]), info[4]
+
+
+def rpy_pse_sqrt_mdot_w(h, w, noise, noise_count, prefactor, tol, max_iter, lin_out, dtype, n):
+    iters = ctypes.c_int(0)
+    incr = ctypes.c_double(0.0)
+    st = load().rpy_pse_sqrt_mdot_w(h, _ptr(w, dtype, 3 * n, "W"), _ptr(noise, dtype, noise_count, "wave noise"),
+                                    float(prefactor), float(tol), int(max_iter), _ptr(lin_out, dtype, 3 * n, "lin_out"),
+                                    ctypes.byref(iters), ctypes.byref(incr), _stream(lin_out))
+    if st == Status.NOT_CONVERGED:
+        raise NotConvergedError(st, load().rpy_last_error(h).decode(), (lin_out, None), iters.value, incr.value)
     _check(h, st)
     return iters.value, incr.value
 

@@ -30,7 +30,7 @@ def build_library(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Wall", "-Wno-unused-command-line-argument", "-Wl,--no-undefined", *DEVICE_FLAGS,
-           f"-I{INCLUDE}", f"-I{CSRC}", "-o", tmp, *sources(), "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas",
+           f"-I{INCLUDE}", f"-I{CSRC}", "-o", tmp, *sources(), "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lhipfft",
            "-Wl,-rpath,/opt/rocm/lib"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -215,7 +215,8 @@ extern "C" rpy_status rpy_mdot_backward(rpy_solver *s, const void *forces, const
     if (!grad_pos && !grad_forces && !grad_torques) return fail(s, RPY_ERR_INVALID_ARG, "no gradient requested");
     if ((torques || grad_ang || grad_torques) && !s->angular)
         return fail(s, RPY_ERR_ANGULAR_DISABLED, "torques / angular cotangents need include_angular");
-    if (s->wall) return fail(s, RPY_ERR_UNSUPPORTED_GEOMETRY, "the adjoint is built for open boundaries only");
+    if (s->wall || s->pse)
+        return fail(s, RPY_ERR_UNSUPPORTED_GEOMETRY, "the adjoint is built for open boundaries only");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (s->dtype == RPY_F64)
         return backward_typed<double>(s, static_cast<const double *>(forces), static_cast<const double *>(torques),

@@ -291,8 +291,8 @@ rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_pe
 rpy_status rpy_autotune(rpy_solver *s, const char *cache_path, void *hip_stream) {
     rpy_status r = check_ready(s);
     if (r != RPY_OK) return r;
-    if (s->wall) {
-        // the wall kernel keeps its default tiles (the candidates timed here are the open-boundary kernels)
+    if (s->wall || s->pse) {
+        // the wall and periodic kernels keep their defaults (the candidates timed here are the open-boundary kernels)
         s->cfg[0] = TileConfig{};
         s->cfg[1] = TileConfig{};
         return RPY_OK;

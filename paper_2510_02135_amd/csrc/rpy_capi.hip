@@ -40,6 +40,7 @@ int splits_for(const rpy_solver *s, bool ang) {
 // Output type Tout: the caller's dtype, or double for Lanczos products.
 template <typename Real, typename Tout>
 rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *angout, hipStream_t st, const void *pos_in) {
+    if (s->pse) return apply_pse<Real, Tout>(s, s->f.as<vec4_t<Real>>(), lin, st, pos_in);
     if (s->wall)
         return apply_wall<Real, Tout>(s, ang, s->f.as<vec4_t<Real>>(), s->t.as<vec4_t<Real>>(), lin, angout, st,
                                       pos_in);
@@ -129,9 +130,15 @@ rpy_status rpy_create(rpy_periodicity x, rpy_periodicity y, rpy_periodicity z, r
     *out = nullptr;
     for (rpy_periodicity p : {x, y, z})
         if ((int)p < (int)RPY_PERIODIC || (int)p > (int)RPY_TWO_WALLS) return RPY_ERR_INVALID_ARG;
-    if (x != RPY_OPEN || y != RPY_OPEN || (z != RPY_OPEN && z != RPY_SINGLE_WALL)) return RPY_ERR_UNSUPPORTED_GEOMETRY;
+    const bool periodic = x == RPY_PERIODIC && y == RPY_PERIODIC && z == RPY_PERIODIC;
+    if (!periodic && (x != RPY_OPEN || y != RPY_OPEN || (z != RPY_OPEN && z != RPY_SINGLE_WALL)))
+        return RPY_ERR_UNSUPPORTED_GEOMETRY;
     rpy_solver *s = new (std::nothrow) rpy_solver();
     if (!s) return RPY_ERR_OUT_OF_MEMORY;
+    if (periodic && pse_create(s) != RPY_OK) {
+        delete s;
+        return RPY_ERR_OUT_OF_MEMORY;
+    }
     s->per[0] = x;
     s->per[1] = y;
     s->per[2] = z;
@@ -142,6 +149,7 @@ rpy_status rpy_create(rpy_periodicity x, rpy_periodicity y, rpy_periodicity z, r
 
 rpy_status rpy_set_parameter(rpy_solver *s, const char *key, double value) {
     if (!s || !key) return RPY_ERR_INVALID_ARG;
+    if (s->pse) return pse_set_parameter(s, key, value);
     if (s->wall && std::strcmp(key, "wallHeight") == 0) {
         if (!std::isfinite(value)) return fail(s, RPY_ERR_INVALID_ARG, "wallHeight must be finite");
         s->wall_height = value;
@@ -161,6 +169,8 @@ rpy_status rpy_initialize(rpy_solver *s, double viscosity, double hydrodynamic_r
         return fail(s, RPY_ERR_INVALID_ARG, "viscosity must be positive and finite");
     if (!(hydrodynamic_radius > 0.0) || !std::isfinite(hydrodynamic_radius))
         return fail(s, RPY_ERR_INVALID_ARG, "hydrodynamic radius must be positive and finite");
+    if (s->pse && include_angular)
+        return fail(s, RPY_ERR_UNSUPPORTED_GEOMETRY, "the periodic (PSE) solver takes forces only");
     s->eta = viscosity;
     s->radius = hydrodynamic_radius;
     s->angular = include_angular != 0;
@@ -225,7 +235,8 @@ rpy_status rpy_div_m(rpy_solver *s, void *lin_out, void *ang_out, void *hip_stre
         return fail(s, RPY_ERR_UNSUPPORTED_GEOMETRY,
                     "the drift above a wall is not zero: use rpy_div_m_rfd (random finite differences)");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    // open space: d_X . M = 0 for the linear and the angular rows
+    // open space and the periodic box (M depends on differences of positions
+    // and its kernel is divergence-free): d_X . M = 0
     if (s->dtype == RPY_F64) {
         HIP_TRY(s, launch_fill_zero<double>(static_cast<double *>(lin_out), 3 * s->n, st));
         if (ang_out) HIP_TRY(s, launch_fill_zero<double>(static_cast<double *>(ang_out), 3 * s->n, st));
@@ -278,6 +289,7 @@ void rpy_destroy(rpy_solver *s) {
             (void)hipEventDestroy(pr.second);
         }
     precond_release(s);
+    pse_release(s);
     if (s->host_flag) (void)hipHostFree(s->host_flag);
     if (s->host_stat) (void)hipHostFree(s->host_stat);
     delete s;

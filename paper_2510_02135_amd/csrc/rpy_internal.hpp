@@ -13,6 +13,8 @@
 
 namespace rpy {
 
+struct PseState;   // triply periodic solver state (rpy_pse.hip)
+
 constexpr int kKernelClasses = 4;   // rpy_kernel values
 constexpr int kMaxRhs = 1024;       // vectors per multi-vector product
 
@@ -77,6 +79,7 @@ struct rpy_solver {
     rpy_periodicity per[3] = {RPY_OPEN, RPY_OPEN, RPY_OPEN};
     bool wall = false;          // (open, open, single_wall): Swan-Brady kernel with damping
     double wall_height = 0.0;   // z of the wall (rpy_set_parameter "wallHeight")
+    rpy::PseState *pse = nullptr;   // (periodic, periodic, periodic): positively split Ewald
     bool initialized = false;
     double eta = 0.0, radius = 0.0;
     bool angular = false;

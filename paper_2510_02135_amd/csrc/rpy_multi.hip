@@ -404,6 +404,13 @@ template <typename Real, typename Tout>
 rpy_status apply_staged_multi(rpy_solver *s, bool ang, int nrhs, Tout *lin, Tout *ang_out, int64_t ostride,
                               hipStream_t st) {
     const int64_t n = s->n;
+    if (s->pse) {
+        for (int r = 0; r < nrhs; ++r) {
+            rpy_status rs = apply_pse<Real, Tout>(s, s->f.as<vec4_t<Real>>() + (size_t)r * n, lin + (size_t)r * ostride, st);
+            if (rs != RPY_OK) return rs;
+        }
+        return RPY_OK;
+    }
     if (s->wall) {
         // one wall product per vector
         for (int r = 0; r < nrhs; ++r) {

@@ -110,7 +110,8 @@ extern "C" rpy_status rpy_mdot_noalloc(rpy_solver *s, const void *forces, const 
     if (!lin_out) return fail(s, RPY_ERR_INVALID_ARG, "linear output pointer is NULL");
     if ((torques || ang_out) && !s->angular)
         return fail(s, RPY_ERR_ANGULAR_DISABLED, "torques / angular output need include_angular");
-    if (s->wall) return fail(s, RPY_ERR_UNSUPPORTED_GEOMETRY, "the no-allocation product is built for open boundaries");
+    if (s->wall || s->pse)
+        return fail(s, RPY_ERR_UNSUPPORTED_GEOMETRY, "the no-allocation product is built for open boundaries");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     if (s->dtype == RPY_F64)
         return mdot_noalloc_typed<double>(s, static_cast<const double *>(forces), static_cast<const double *>(torques),

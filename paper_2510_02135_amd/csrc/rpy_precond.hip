@@ -215,6 +215,7 @@ int block_count(const rpy_solver *s) {
 }  // namespace
 
 rpy_status precond_setup(rpy_solver *s, int64_t group, hipStream_t st) {
+    if (s->pse) return fail(s, RPY_ERR_UNSUPPORTED_GEOMETRY, "the preconditioner is built for open boundaries and the wall");
     if (group < 1 || group > kMaxBlockDim / 3)
         return fail(s, RPY_ERR_INVALID_ARG, "group size must be in [1, 512] particles");
     const int parts = s->angular ? 2 : 1;

@@ -33,6 +33,15 @@ rpy_status apply_wall(rpy_solver *s, bool ang, const vec4_t<Real> *f, const vec4
                       Tout *ang_out, hipStream_t st, const void *pos = nullptr);
 int wall_targets_per_lane(const rpy_solver *s, bool ang);
 
+// M F for the triply periodic geometry (rpy_pse.hip): F staged as vec4 at
+// f, lin (n x 3) overwritten; positions `pos` (vec4) or the stored ones.
+// While PseState::real_only is set, the real-space part alone.
+template <typename Real, typename Tout>
+rpy_status apply_pse(rpy_solver *s, const vec4_t<Real> *f, Tout *lin, hipStream_t st, const void *pos = nullptr);
+rpy_status pse_create(rpy_solver *s);
+void pse_release(rpy_solver *s);
+rpy_status pse_set_parameter(rpy_solver *s, const char *key, double value);
+
 // M [F; T] by the symmetric pair kernel (each unordered pair once), with
 // F, T staged as for apply_staged; `span` source blocks per task (0 =
 // automatic).  Large N runs in slabs of target blocks whose partials fit a

@@ -11,6 +11,8 @@ a ``torch.autograd.Function`` whose backward calls the library's adjoint.
 """
 from __future__ import annotations
 
+import math
+
 import torch
 
 from . import _lib
@@ -18,9 +20,12 @@ from ._lib import NotConvergedError
 
 
 class Solver:
-    """RPY N-body mobility solver on one HIP device: open boundaries, or
+    """RPY mobility solver on one HIP device: open boundaries;
     ("open", "open", "single_wall") for a no-slip wall at z = wallHeight
-    (setParameters(wallHeight=...), default 0)."""
+    (setParameters(wallHeight=...), default 0); or ("periodic", "periodic",
+    "periodic") for a periodic box by the positively split Ewald method
+    (setParameters(Lx=..., Ly=..., Lz=... or boxSize=..., psi=..., tolerance=...);
+    forces only)."""
 
     def __init__(self, periodicityX: str = "open", periodicityY: str = "open",
                  periodicityZ: str = "open"):
@@ -136,6 +141,40 @@ class Solver:
                                        self._n, self._angular)
         self.last_iterations, self.last_increment = it, inc
         return lin, ang
+
+    def pseInfo(self) -> dict:
+        """Configuration of a periodic solver: Fourier grid, splitting xi,
+        real-space cutoff rc, Gaussian width sigma and support, wave cutoff."""
+        grid, xi, rc, sigma, support, kc = _lib.rpy_pse_info(self._h)
+        return {"grid": grid, "xi": xi, "rc": rc, "sigma": sigma, "support": support, "kc": kc}
+
+    def waveNoiseShape(self):
+        """Shape of the Fourier-space noise of sqrtMdotWSplit: (3, Nx, Ny, Nz//2 + 1, 2)."""
+        g = self.pseInfo()["grid"]
+        return (3, g[0], g[1], g[2] // 2 + 1, 2)
+
+    def sqrtMdotWSplit(self, W: torch.Tensor | None = None, waveNoise: torch.Tensor | None = None,
+                       prefactor: float = 1.0, tol: float = 1e-6, maxIter: int = 500,
+                       generator: torch.Generator | None = None):
+        """Periodic box: prefactor * (M_real^{1/2} W + a wave-space sample drawn
+        from waveNoise), a fluctuating term with covariance M built from the
+        positive split (Lanczos on the near-field part only; the far field
+        from independent Fourier-space normals, one inverse FFT).  W (3N) and
+        waveNoise (waveNoiseShape()) ~ N(0, 1) are drawn when not given."""
+        self._require_positions()
+        w = self._noise(W, generator)
+        shape = self.waveNoiseShape()
+        if waveNoise is None:
+            waveNoise = torch.randn(shape, dtype=self._dtype, device=self._device, generator=generator)
+        if tuple(waveNoise.shape) != shape and waveNoise.numel() != math.prod(shape):
+            raise ValueError(f"SIZE_MISMATCH: wave noise needs {shape}, got {tuple(waveNoise.shape)}")
+        if waveNoise.dtype != self._dtype:
+            raise ValueError(f"DTYPE_MISMATCH: wave noise is {waveNoise.dtype}, positions are {self._dtype}")
+        lin = self._empty()
+        it, inc = _lib.rpy_pse_sqrt_mdot_w(self._h, w, waveNoise.contiguous().reshape(-1), math.prod(shape), prefactor,
+                                           tol, maxIter, lin, self._dtype, self._n)
+        self.last_iterations, self.last_increment = it, inc
+        return lin, None
 
     def sqrtMdotWPrecond(self, W: torch.Tensor | None = None, groupSize: int = 1, prefactor: float = 1.0,
                          tol: float = 1e-6, maxIter: int = 500, generator: torch.Generator | None = None):

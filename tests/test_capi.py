@@ -61,13 +61,33 @@ def test_geometry_checks(lib):
     lib.rpy_destroy(out)
     out = ctypes.c_void_p(123)
     assert lib.rpy_create(2, 1, 1, ctypes.byref(out)) == GEOM and not out.value
-    assert lib.rpy_create(0, 0, 0, ctypes.byref(out)) == GEOM
+    assert lib.rpy_create(0, 0, 1, ctypes.byref(out)) == GEOM and not out.value
+    assert lib.rpy_create(0, 1, 0, ctypes.byref(out)) == GEOM
     assert lib.rpy_create(1, 1, 3, ctypes.byref(out)) == GEOM
     assert lib.rpy_create(1, 1, 7, ctypes.byref(out)) == INVALID
     assert lib.rpy_create(1, 1, 1, None) == INVALID
     h = _solver(lib)
     lib.rpy_destroy(h)
     lib.rpy_destroy(None)
+
+
+def test_periodic_geometry_host_checks(lib):
+    """(periodic, periodic, periodic): parameters and initialize are host-side."""
+    out = ctypes.c_void_p(0)
+    assert lib.rpy_create(0, 0, 0, ctypes.byref(out)) == OK and out.value
+    h = out
+    try:
+        for key, val in ((b"Lx", 10.0), (b"Ly", 11.0), (b"Lz", 12.0), (b"boxSize", 9.0), (b"psi", 0.0),
+                         (b"psi", 1.5), (b"tolerance", 1e-6)):
+            assert lib.rpy_set_parameter(h, key, val) == OK
+        for key, val in ((b"Lx", 0.0), (b"Lz", -1.0), (b"psi", -0.1), (b"tolerance", 0.1), (b"tolerance", 1e-15),
+                         (b"wallHeight", 0.0), (b"Lx", float("nan"))):
+            assert lib.rpy_set_parameter(h, key, val) == INVALID
+        assert b"periodic" in lib.rpy_last_error(h) or b"finite" in lib.rpy_last_error(h)
+        assert lib.rpy_initialize(h, 1.0, 1.0, 1) == GEOM          # forces only
+        assert lib.rpy_initialize(h, 1.0, 1.0, 0) == OK
+    finally:
+        lib.rpy_destroy(h)
 
 
 def test_parameter_and_initialize_checks(lib):

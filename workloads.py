@@ -188,3 +188,33 @@ def wall_suspension(n: int, seed: int, *, hg: float = 1.5, phi2d: float = 0.11, 
     s = Suspension(f"wall_n{n}_hg{hg}_s{seed}", pos, forces, tq, wv, box=side)
     s.extra.update(wall_height=wall_height)
     return s
+
+
+def periodic_box(n: int, seed: int, *, box=None, density: float = 0.1, w: bool = False,
+                 images: bool = True, name: str = "") -> Suspension:
+    """Periodic suspension: positions uniform in the box [0, Lx) x [0, Ly) x
+    [0, Lz) (cubic with side (N / density)^(1/3) when `box` is not given,
+    the number density of the paper's timing benchmark, Sec. 5.5), then,
+    with `images`, every particle moved by a random whole number of box
+    lengths in -2..2 per axis (the same suspension, unwrapped); draw order
+    positions, image shifts, forces, W (3N)."""
+    rng = np.random.default_rng(seed)
+    if box is None:
+        side = (n / density) ** (1.0 / 3.0)
+        box = (side, side, side)
+    L = np.asarray(box, dtype=np.float64)
+    pos = rng.random((n, 3)) * L
+    shifts = rng.integers(-2, 3, (n, 3))
+    if images:
+        pos = pos + shifts * L
+    forces = rng.standard_normal((n, 3))
+    wv = rng.standard_normal(3 * n) if w else None
+    s = Suspension(name or f"periodic_n{n}_s{seed}", pos, forces, None, wv, box=float(L[0]))
+    s.extra["box"] = tuple(float(v) for v in L)
+    return s
+
+
+def wave_noise(shape, seed: int) -> np.ndarray:
+    """Standard normal Fourier-space noise of the given shape (the periodic
+    solver's split fluctuations), from its own generator."""
+    return np.random.default_rng(seed).standard_normal(tuple(shape))
