@@ -75,6 +75,8 @@ def parse():
                         "'mdot' stops after the batched products")
     p.add_argument("--pse-only", action="store_true",
                    help="only the triply periodic (PSE) products; one JSON line")
+    p.add_argument("--pse-size", default=None,
+                   help="N:density of the one periodic workload to run (default: all three)")
     p.add_argument("--chains-solve", action="store_true",
                    help="instead of the step: the converged sqrtMdotW (tol 1e-6, float32 pairs, angular) of the "
                         "4096 x 256-bead chains, plain and preconditioned with one chain per group")
@@ -413,12 +415,16 @@ def main():
                           "batched": bench_batched(rpy, workloads, dev, stream, timed,
                                                    mdot_only=args.batch_only == "mdot")}), flush=True)
         return
+    pse_kw = {}
+    if args.pse_size:
+        n_s, rho_s = args.pse_size.split(":")
+        pse_kw["sizes"] = ((int(n_s), float(rho_s)),)
     if args.pse_only:
         print(json.dumps({"metric": "periodic (PSE) Mdot throughput", "unit": "particles/s",
                           "higher_is_better": True, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
                           "config": {"workload": "uniform random particles, cubic periodic box, density 0.1 and "
                                                  "0.001 / a^3, tolerance 1e-4, automatic psi"},
-                          "periodic_pse": bench_pse(rpy, workloads, dev, stream)}), flush=True)
+                          "periodic_pse": bench_pse(rpy, workloads, dev, stream, **pse_kw)}), flush=True)
         return
     s = workloads.c2_suspension(args.n)
     n = s.n

@@ -93,9 +93,7 @@ typedef enum { RPY_F32 = 0, RPY_F64 = 1 } rpy_dtype;
  * fluctuations), rpy_div_m (zero: M depends on differences of positions
  * and its kernel is divergence-free), rpy_div_m_rfd, rpy_mobility_solve and
  * the time steps work; include_angular, rpy_mdot_backward, rpy_mdot_noalloc
- * and rpy_sqrt_mdot_w_precond return RPY_ERR_UNSUPPORTED_GEOMETRY.  Results
- * in the periodic box are reproducible to rounding, not bit for bit (the
- * grid is accumulated with atomic additions).
+ * and rpy_sqrt_mdot_w_precond return RPY_ERR_UNSUPPORTED_GEOMETRY.
  */
 rpy_status rpy_create(rpy_periodicity x, rpy_periodicity y, rpy_periodicity z, rpy_solver **out);
 
@@ -111,8 +109,8 @@ rpy_status rpy_create(rpy_periodicity x, rpy_periodicity y, rpy_periodicity z, r
  * eta a) beyond it, and the root-mean-square sum of the pairs it drops, at
  * the suspension's number density and unit random forces, below half of
  * that), the wave cutoff kc ((1 + q) e^{-q} = tolerance, q =
- * kc^2 / (4 xi^2)), the grid (Nyquist frequency 2 kc, sizes with factors
- * 2, 3, 5, 7), the Gaussian width (aliasing of kc below tolerance) and its
+ * kc^2 / (4 xi^2)), the grid (Nyquist frequency 2 kc, sizes multiples of 8
+ * with factors 2, 3, 5, 7), the Gaussian width (aliasing of kc below tolerance) and its
  * support (truncation below tolerance).  The first call that needs the
  * configuration returns RPY_ERR_INVALID_ARG if rc reaches half the box
  * (raise psi), the grid exceeds 4096 points per axis or the support 32.

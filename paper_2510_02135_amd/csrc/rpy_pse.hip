@@ -20,12 +20,16 @@
 // q = kc^2/(4 xi^2)), the grid (Nyquist at 2 kc), the Gaussian width
 // (aliasing of kc below tol) and its support P (truncation below tol).
 //
-// Data layout: the cell list sorts particles by cell (deterministic order:
-// by cell, then by index); spreading and interpolation run one wavefront per
-// particle in that order, lanes over the (y, z) support points so that
-// neighbouring lanes touch neighbouring grid words; the grid is three real
-// Nx x Ny x Nz arrays (z fastest), the spectrum three Nx x Ny x (Nz/2 + 1)
-// complex arrays.
+// Data layout: particles are binned by tiles of 8^3 grid points (a counting
+// sort; deterministic order: by tile, then by index).  The tiles serve both
+// parts: the real-space sum scans the tiles within rc of a target's tile;
+// spreading runs one workgroup per tile that gathers the particles whose
+// Gaussian support reaches it (every grid point written once, no atomics);
+// interpolation runs one wavefront per particle in tile order, lanes over
+// the (y, z) support points so that neighbouring lanes read neighbouring
+// grid words.  The grid is three real Nx x Ny x Nz arrays (z fastest), the
+// spectrum three Nx x Ny x (Nz/2 + 1) complex arrays.  With these fixed
+// orders a product is reproducible bit for bit.
 #include "rpy_device.hpp"
 #include "rpy_internal.hpp"
 #include "rpy_solver_ops.hpp"
@@ -46,8 +50,9 @@ namespace {
 constexpr int kTable = 4096;         // table intervals on [0, rc]
 constexpr int kMaxSupport = 32;      // Gaussian support points per axis
 constexpr int kMaxGridAxis = 4096;   // grid points per axis
-constexpr int64_t kMaxCells = int64_t(1) << 24;
 constexpr int kScanBlock = 1024;     // threads of the scan kernels (4 items each)
+constexpr int kTile = 8;             // grid points per tile side (tiles bin the particles)
+constexpr int kMaxTileNbr = 343;     // neighbour tiles scanned by a tile (reach <= 3)
 
 template <typename Real> struct V2;
 template <> struct V2<float> { using type = float2; };
@@ -64,9 +69,10 @@ template <> struct FftTypes<double> { using complex_t = hipfftDoubleComplex; };
 template <typename Real>
 struct PseConst {
     Real L[3], invL[3];
-    int ncell[3];
-    Real cell_scale[3];       // ncell / L
-    int nbr_lo[3], nbr_cnt[3];  // neighbour cell offsets lo .. lo + cnt - 1 per axis
+    int ncell[3];               // tiles of kTile^3 grid points per axis (the last may be partial)
+    Real cell_scale[3];         // 1 / (kTile h): position -> tile
+    int nbr_lo[3], nbr_cnt[3];  // tiles within rc of a tile: offsets lo .. lo + cnt - 1 per axis
+    int sp_lo[3], sp_cnt[3];    // tiles whose particles' supports can reach a tile
     Real rc2, inv_dr;
     int grid[3];
     Real h[3], invh[3];
@@ -88,7 +94,7 @@ struct PseState {
     double key[8] = {};
     double xi = 0.0, rc = 0.0, sigma = 0.0, dr = 0.0;
     double h[3] = {}, qc = 0.0;
-    int P = 0, grid[3] = {}, ncell[3] = {};
+    int P = 0, grid[3] = {}, ncell[3] = {}, reach_real[3] = {}, reach_spread = 0;
     std::vector<double> table;   // (f, g) pairs, kTable + 4 entries, in units of 1/(8 pi eta)
     DevBuf tab32, tab64;
     // cell list and sorted particles
@@ -207,10 +213,12 @@ inline void rpy_coeffs(double r, double a, double &A, double &Br2) {
     }
 }
 
+// Smallest grid size >= n that is a multiple of the tile (so that every tile
+// is whole and the tile reaches below hold) with prime factors 2, 3, 5, 7.
 int nice_fft_size(int n) {
     if (n < 8) n = 8;
     for (;; ++n) {
-        if (n % 2) continue;
+        if (n % kTile) continue;
         int m = n;
         for (int p : {2, 3, 5, 7})
             while (m % p == 0) m /= p;
@@ -504,38 +512,141 @@ __device__ __forceinline__ void support_weights(const vec4_t<Real> &p, const Pse
     }
 }
 
-// Spreading: one wavefront per particle (slot order), lanes over the
-// (y, z) support points, a loop over x; hardware float atomics.
+// Spreading by gathering: one workgroup per tile of kTile^3 grid points
+// writes every point of its tile once (no atomics, no prior clearing, a
+// fixed order of terms).  The particles of the tiles whose supports can
+// reach it are scanned in rounds of 256; those whose P-point window
+// (periodic) meets the tile on all three axes are compacted into LDS in a
+// fixed order with their Gaussian weights at the tile's 8 points per axis
+// (zero outside the window) and their force; each thread then sums its two
+// points' terms, grid[m] = gnorm3 sum_j wx wy wz F_j.
 template <typename Real>
-__global__ void __launch_bounds__(256) pse_spread(int n, const vec4_t<Real> *__restrict__ spos,
-                                                  const vec4_t<Real> *__restrict__ sfrc, PseConst<Real> c,
-                                                  Real *__restrict__ grid) {
-    __shared__ Real wsh[4][3 * kMaxSupport];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int s = blockIdx.x * 4 + wv;
-    const bool active = s < n;   // uniform over the wavefront
-    const vec4_t<Real> p = spos[active ? s : 0];
-    const vec4_t<Real> F = sfrc[active ? s : 0];
-    int i0[3];
-    Real *w = wsh[wv];
-    support_weights(p, c, w, i0);
+__device__ __forceinline__ bool window_meets_tile(Real u, int P, int g0, int npts, int N, int &i0) {
+    Real u0;
+    support_axis(u, Real(1), P, i0, u0);
+    int d0 = (g0 - i0) % N;
+    if (d0 < 0) d0 += N;
+    // points g0 .. g0 + npts - 1 meet the window [i0, i0 + P) mod N
+    return d0 < P || d0 + npts > N;
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(256) pse_spread_tiles(const vec4_t<Real> *__restrict__ spos,
+                                                        const vec4_t<Real> *__restrict__ sfrc,
+                                                        const int *__restrict__ start, PseConst<Real> c,
+                                                        Real *__restrict__ grid) {
+    __shared__ Real sw[3][kTile][256];
+    __shared__ vec4_t<Real> sf[256];
+    __shared__ int nb_first[kMaxTileNbr], nb_pref[kMaxTileNbr + 1];
+    __shared__ int wave_hits[4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tile = blockIdx.x;
+    const int t2 = tile % c.ncell[2];
+    const int t1 = (tile / c.ncell[2]) % c.ncell[1];
+    const int t0 = tile / (c.ncell[2] * c.ncell[1]);
+    const int g0[3] = {t0 * kTile, t1 * kTile, t2 * kTile};
+    int npts[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) npts[d] = min(kTile, c.grid[d] - g0[d]);
+    // neighbour tiles and the prefix sums of their particle counts
+    const int nnb = c.sp_cnt[0] * c.sp_cnt[1] * c.sp_cnt[2];
+    for (int k = tid; k < nnb; k += 256) {
+        const int oz = k % c.sp_cnt[2], oy = (k / c.sp_cnt[2]) % c.sp_cnt[1], ox = k / (c.sp_cnt[2] * c.sp_cnt[1]);
+        int a = t0 + c.sp_lo[0] + ox, b = t1 + c.sp_lo[1] + oy, e = t2 + c.sp_lo[2] + oz;
+        a += a < 0 ? c.ncell[0] : (a >= c.ncell[0] ? -c.ncell[0] : 0);
+        b += b < 0 ? c.ncell[1] : (b >= c.ncell[1] ? -c.ncell[1] : 0);
+        e += e < 0 ? c.ncell[2] : (e >= c.ncell[2] ? -c.ncell[2] : 0);
+        const int cell = (a * c.ncell[1] + b) * c.ncell[2] + e;
+        nb_first[k] = start[cell];
+        nb_pref[k + 1] = start[cell + 1] - start[cell];
+    }
     __syncthreads();
-    if (!active) return;
-    const int P = c.P, P2 = P * P;
+    if (tid == 0) {
+        nb_pref[0] = 0;
+        for (int k = 0; k < nnb; ++k) nb_pref[k + 1] += nb_pref[k];
+    }
+    __syncthreads();
+    const int total = nb_pref[nnb];
+    // this thread's points: (lx, ly, lz) and (lx + 4, ly, lz)
+    const int lz = tid & 7, ly = (tid >> 3) & 7, lx = tid >> 6;
+    Real a0 = Real(0), a1 = Real(0), a2 = Real(0), b0 = Real(0), b1 = Real(0), b2 = Real(0);
+    for (int base = 0; base < total; base += 256) {
+        const int v = base + tid;
+        bool hit = false;
+        int j = 0, i0[3] = {0, 0, 0};
+        Real u[3] = {Real(0), Real(0), Real(0)};
+        if (v < total) {
+            int lo = 0, hi = nnb - 1;   // last k with nb_pref[k] <= v
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (nb_pref[mid] <= v) lo = mid; else hi = mid - 1;
+            }
+            j = nb_first[lo] + (v - nb_pref[lo]);
+            const vec4_t<Real> p = spos[j];
+            u[0] = p.x * c.invh[0];
+            u[1] = p.y * c.invh[1];
+            u[2] = p.z * c.invh[2];
+            hit = window_meets_tile(u[0], c.P, g0[0], npts[0], c.grid[0], i0[0]) &&
+                  window_meets_tile(u[1], c.P, g0[1], npts[1], c.grid[1], i0[1]) &&
+                  window_meets_tile(u[2], c.P, g0[2], npts[2], c.grid[2], i0[2]);
+        }
+        // fixed-order compaction: wave prefix by ballot, waves in order
+        const unsigned long long mask = __ballot(hit);
+        const int rank = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) wave_hits[wv] = __popcll(mask);
+        __syncthreads();
+        int off = 0;
+        for (int w = 0; w < wv; ++w) off += wave_hits[w];
+        const int m = wave_hits[0] + wave_hits[1] + wave_hits[2] + wave_hits[3];
+        if (hit) {
+            const int slot = off + rank;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+#pragma unroll
+                for (int l = 0; l < kTile; ++l) {
+                    Real w = Real(0);
+                    const int g = g0[d] + l;
+                    if (l < npts[d]) {
+                        int dd = (g - i0[d]) % c.grid[d];
+                        if (dd < 0) dd += c.grid[d];
+                        if (dd < c.P) {
+                            const Real x = (Real(i0[d] + dd) - u[d]) * c.h[d];
+                            w = exp(-x * x * c.inv_2s2);
+                        }
+                    }
+                    sw[d][l][slot] = w;
+                }
+            }
+            sf[slot] = sfrc[j];
+        }
+        __syncthreads();
+        for (int k = 0; k < m; ++k) {
+            const Real wyz = sw[1][ly][k] * sw[2][lz][k];
+            const Real p0 = sw[0][lx][k] * wyz, p1 = sw[0][lx + 4][k] * wyz;
+            const vec4_t<Real> F = sf[k];
+            a0 = fma(p0, F.x, a0);
+            a1 = fma(p0, F.y, a1);
+            a2 = fma(p0, F.z, a2);
+            b0 = fma(p1, F.x, b0);
+            b1 = fma(p1, F.y, b1);
+            b2 = fma(p1, F.z, b2);
+        }
+        __syncthreads();
+    }
     const size_t ng = (size_t)c.grid[0] * c.grid[1] * c.grid[2];
-    for (int e = lane; e < P2; e += 64) {
-        const int iy = e / P, iz = e - iy * P;
-        const int gy = wrap_index(i0[1] + iy, c.grid[1]);
-        const int gz = wrap_index(i0[2] + iz, c.grid[2]);
-        const Real wyz = c.gnorm3 * w[kMaxSupport + iy] * w[2 * kMaxSupport + iz];
-        const Real fx = F.x * wyz, fy = F.y * wyz, fz = F.z * wyz;
-        for (int ix = 0; ix < P; ++ix) {
-            const int gx = wrap_index(i0[0] + ix, c.grid[0]);
-            const size_t idx = ((size_t)gx * c.grid[1] + gy) * c.grid[2] + gz;
-            const Real wx = w[ix];
-            unsafeAtomicAdd(grid + idx, fx * wx);
-            unsafeAtomicAdd(grid + ng + idx, fy * wx);
-            unsafeAtomicAdd(grid + 2 * ng + idx, fz * wx);
+    if (ly < npts[1] && lz < npts[2]) {
+        const size_t gyz = (size_t)(g0[1] + ly) * c.grid[2] + (g0[2] + lz);
+        if (lx < npts[0]) {
+            const size_t idx = (size_t)(g0[0] + lx) * c.grid[1] * c.grid[2] + gyz;
+            grid[idx] = c.gnorm3 * a0;
+            grid[ng + idx] = c.gnorm3 * a1;
+            grid[2 * ng + idx] = c.gnorm3 * a2;
+        }
+        if (lx + 4 < npts[0]) {
+            const size_t idx = (size_t)(g0[0] + lx + 4) * c.grid[1] * c.grid[2] + gyz;
+            grid[idx] = c.gnorm3 * b0;
+            grid[ng + idx] = c.gnorm3 * b1;
+            grid[2 * ng + idx] = c.gnorm3 * b2;
         }
     }
 }
@@ -778,9 +889,12 @@ PseConst<Real> make_const(const rpy_solver *s) {
         c.L[d] = Real(p.box[d]);
         c.invL[d] = Real(1.0 / p.box[d]);
         c.ncell[d] = p.ncell[d];
-        c.cell_scale[d] = Real(p.ncell[d] / p.box[d]);
-        c.nbr_cnt[d] = std::min(3, p.ncell[d]);
-        c.nbr_lo[d] = p.ncell[d] >= 3 ? -1 : 0;
+        c.cell_scale[d] = Real(1.0 / (kTile * p.h[d]));
+        const int wr = 2 * p.reach_real[d] + 1, ws = 2 * p.reach_spread + 1;
+        c.nbr_cnt[d] = std::min(wr, p.ncell[d]);
+        c.nbr_lo[d] = p.ncell[d] >= wr ? -p.reach_real[d] : 0;
+        c.sp_cnt[d] = std::min(ws, p.ncell[d]);
+        c.sp_lo[d] = p.ncell[d] >= ws ? -p.reach_spread : 0;
         c.grid[d] = p.grid[d];
         c.h[d] = Real(p.h[d]);
         c.invh[d] = Real(1.0 / p.h[d]);
@@ -854,11 +968,17 @@ rpy_status configure(rpy_solver *s) {
         return fail(s, RPY_ERR_INVALID_ARG, "tolerance too small: the Gaussian support exceeds 32 points");
     for (int d = 0; d < 3; ++d)
         if (P > grid[d]) return fail(s, RPY_ERR_INVALID_ARG, "the Gaussian support exceeds the grid");
-    // cells of size >= rc, at most 2^24 of them
-    int nc[3];
-    for (int d = 0; d < 3; ++d) nc[d] = std::max(1, std::min(1024, (int)std::floor(p.box[d] / rc)));
-    while ((int64_t)nc[0] * nc[1] * nc[2] > kMaxCells)
-        for (int d = 0; d < 3; ++d) nc[d] = std::max(1, nc[d] * 7 / 8);
+    // particles are binned by tiles of kTile^3 grid points; a tile's real-space
+    // neighbours lie within ceil(rc / (kTile h)) tiles, the supports that can
+    // reach it within ceil((P/2 + 1) / kTile)
+    int nc[3], reach[3];
+    for (int d = 0; d < 3; ++d) {
+        nc[d] = (grid[d] + kTile - 1) / kTile;
+        reach[d] = (int)std::ceil(rc / (kTile * h[d]));
+    }
+    const int reach_sp = (int)std::ceil((0.5 * P + 1.0) / kTile);
+    if (std::pow(std::min(2 * reach_sp + 1, std::max(nc[0], std::max(nc[1], nc[2]))), 3) > kMaxTileNbr)
+        return fail(s, RPY_ERR_INVALID_ARG, "tolerance too small: the Gaussian support reaches too many tiles");
     // table of Wr on [-dr, rc + 2 dr]
     const double dr = rc / kTable;
     const WaveQuad wq = make_quad(xi, a, rc + 3.0 * dr);
@@ -884,7 +1004,9 @@ rpy_status configure(rpy_solver *s) {
         p.grid[d] = grid[d];
         p.h[d] = h[d];
         p.ncell[d] = nc[d];
+        p.reach_real[d] = reach[d];
     }
+    p.reach_spread = reach_sp;
     std::memcpy(p.key, key, sizeof(key));
     p.ready = true;
     return RPY_OK;
@@ -1020,9 +1142,9 @@ rpy_status apply_pse(rpy_solver *s, const vec4_t<Real> *f, Tout *lin, hipStream_
     const int64_t nr = (int64_t)p.grid[0] * p.grid[1] * p.grid[2];
     const int nzh = p.grid[2] / 2 + 1;
     const int64_t nh = (int64_t)p.grid[0] * p.grid[1] * nzh;
-    HIP_TRY(s, fill_zero<Real>(p.rgrid.as<Real>(), 3 * nr, st));
-    hipLaunchKernelGGL((pse_spread<Real>), dim3(blocks_for(n, 4)), dim3(256), 0, st, (int)n, p.spos.as<vec4_t<Real>>(),
-                       p.sfrc.as<vec4_t<Real>>(), c, p.rgrid.as<Real>());
+    const int64_t ntiles = (int64_t)p.ncell[0] * p.ncell[1] * p.ncell[2];
+    hipLaunchKernelGGL((pse_spread_tiles<Real>), dim3((unsigned)ntiles), dim3(256), 0, st, p.spos.as<vec4_t<Real>>(),
+                       p.sfrc.as<vec4_t<Real>>(), p.start.as<int>(), c, p.rgrid.as<Real>());
     HIP_TRY(s, hipGetLastError());
     r = fft_forward<Real>(s, st);
     if (r != RPY_OK) return r;
