@@ -224,7 +224,7 @@ def test_error_paths_through_the_binding():
         sol.Mdot()
     assert ei.value.status == rpy.Status.INVALID_ARG
     with pytest.raises(rpy.RpyError) as ei:
-        rpy.Solver("open", "open", "single_wall")
+        rpy.Solver("open", "open", "two_walls")
     assert ei.value.status == rpy.Status.UNSUPPORTED_GEOMETRY
     with pytest.raises(rpy.RpyError):
         sol.setParameters(wallHeight=0.0)
