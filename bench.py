@@ -73,6 +73,8 @@ def parse():
     p.add_argument("--batch-only", nargs="?", const="all", default=None, choices=("all", "mdot"),
                    help="instead of the step: only the 512 batched systems (one launch against one per system); "
                         "'mdot' stops after the batched products")
+    p.add_argument("--breakdown-only", action="store_true",
+                   help="only the float32/float64 Mdot and backward timings at N (tiles from --tiles, else autotuned)")
     p.add_argument("--pse-only", action="store_true",
                    help="only the triply periodic (PSE) products; one JSON line")
     p.add_argument("--pse-size", default=None,
@@ -276,6 +278,39 @@ def timed(fn, reps, stream, warmup=0):
     return times[len(times) // 2]
 
 
+def run_breakdown(args, rpy, s, g_u, g_w, dev_t, stream):
+    """float32 and float64 Mdot and backward, translational and angular, on
+    suspension s (tiles from --tiles, else autotuned); timings and results."""
+    import torch
+    n = s.n
+    breakdown, results = {}, {}
+    for dt, name in (() if args.no_breakdown else ((torch.float32, "fp32"), (torch.float64, "fp64"))):
+        Xd, Fd, Td = dev_t(s.pos, dt), dev_t(s.forces, dt), dev_t(s.torques, dt)
+        GUd, GWd = dev_t(g_u, dt), dev_t(g_w, dt)
+        for ang in (False, True):
+            so = rpy.Solver()
+            so.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius, includeAngular=ang)
+            so.setPositions(Xd)
+            if args.tiles:
+                so.setTileConfig(ang, *(int(v) for v in args.tiles.split(",")))
+            else:
+                so.autotune(args.tile_cache)
+            key = f"{name}_{'angular' if ang else 'linear'}"
+            fwd = lambda: so.Mdot(forces=Fd, torques=Td if ang else None)
+            bwd = lambda: so.Mdot_backward(Fd, Td if ang else None, GUd, GWd if ang else None)
+            tf = timed(fwd, 10, stream, warmup=3)
+            tb = timed(bwd, 10, stream, warmup=3)
+            breakdown[key] = {"mdot_ms": round(tf, 4), "pairs_per_s": float(n) * n / (tf * 1e-3),
+                              "backward_ms": round(tb, 4), "backward_over_forward": round(tb / tf, 3),
+                              "tiles": list(so.tileConfig(ang))}
+            lin, angv = fwd()
+            gp, gf, gt = bwd()
+            results[key] = (lin.double().cpu().numpy(), None if angv is None else angv.double().cpu().numpy(),
+                            gp.double().cpu().numpy(), gf.double().cpu().numpy())
+            so.close()
+    return breakdown, results
+
+
 def bench_pse(rpy, workloads, dev, stream, sizes=((1 << 20, 0.1), (1 << 17, 0.1), (1 << 17, 0.001)), tol=1e-4):
     """Triply periodic products (PSE, forces only) on the paper's timing
     workload: uniform random particles in a cubic box at number density
@@ -434,6 +469,14 @@ def main():
     def dev_t(x, dt):
         return torch.tensor(np.asarray(x), dtype=dt, device=dev)
 
+    if args.breakdown_only:
+        bd, _ = run_breakdown(args, rpy, s, g_u, g_w, dev_t, stream)
+        print(json.dumps({"metric": "Mdot and backward times, float32 and float64", "unit": "ms",
+                          "higher_is_better": False, "n_gpus": 1, "dtype": "f32+f64", "data": "synthetic",
+                          "config": {"workload": f"uniform-cube suspension N={n}, phi=0.1, seed 1002",
+                                     "tiles": args.tiles or "autotuned"},
+                          "breakdown": bd}), flush=True)
+        return
     f32 = torch.float32
     X, F, T, W = (dev_t(v, f32) for v in (s.pos, s.forces, s.torques, s.w))
     GU, GW = dev_t(g_u, f32), dev_t(g_w, f32)
@@ -517,28 +560,7 @@ def main():
 
     # ---- breakdown outside the timed steps -------------------------------
     print("bench: breakdown (fp32/fp64 Mdot, backward)", file=sys.stderr, flush=True)
-    breakdown = {}
-    results = {}
-    for dt, name in (() if args.no_breakdown else ((torch.float32, "fp32"), (torch.float64, "fp64"))):
-        Xd, Fd, Td = dev_t(s.pos, dt), dev_t(s.forces, dt), dev_t(s.torques, dt)
-        GUd, GWd = dev_t(g_u, dt), dev_t(g_w, dt)
-        for ang in (False, True):
-            so = rpy.Solver()
-            so.initialize(viscosity=s.viscosity, hydrodynamicRadius=s.radius, includeAngular=ang)
-            so.setPositions(Xd)
-            so.autotune(args.tile_cache)
-            key = f"{name}_{'angular' if ang else 'linear'}"
-            fwd = lambda: so.Mdot(forces=Fd, torques=Td if ang else None)
-            bwd = lambda: so.Mdot_backward(Fd, Td if ang else None, GUd, GWd if ang else None)
-            tf = timed(fwd, 10, stream, warmup=3)
-            tb = timed(bwd, 10, stream, warmup=3)
-            breakdown[key] = {"mdot_ms": round(tf, 4), "pairs_per_s": float(n) * n / (tf * 1e-3),
-                              "backward_ms": round(tb, 4), "backward_over_forward": round(tb / tf, 3)}
-            lin, angv = fwd()
-            gp, gf, gt = bwd()
-            results[key] = (lin.double().cpu().numpy(), None if angv is None else angv.double().cpu().numpy(),
-                            gp.double().cpu().numpy(), gf.double().cpu().numpy())
-            so.close()
+    breakdown, results = run_breakdown(args, rpy, s, g_u, g_w, dev_t, stream)
 
     # ---- the N = 16,384, phi = 0.2 gradient workload: loss
     # 0.5 |M(X) F - M(X + delta) F|^2, its backward against the forward

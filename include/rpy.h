@@ -527,8 +527,12 @@ void rpy_batch_destroy(rpy_batch *b);
  * partials ((N/512) x 6 x N source-side values plus the target-side ones)
  * are produced and reduced in slabs of target blocks of at most about
  * 8 GiB of workspace each (the environment variable RPY_SYM_SLAB_BLOCKS=m
- * also caps a slab at m blocks, for testing).  Results do not depend on
- * the configuration beyond float rounding order.
+ * also caps a slab at m blocks, for testing).  targets_per_lane = 3 selects
+ * the fused small-N kernel: one launch per product that reads the caller's
+ * N x 3 forces and torques directly and writes the outputs (workgroups of
+ * 16 wavefronts per 64 targets, each wavefront a sixteenth of the sources;
+ * source_splits ignored); the autotuner tries it up to N = 8192.  Results
+ * do not depend on the configuration beyond float rounding order.
  */
 rpy_status rpy_set_tile_config(rpy_solver *s, int angular, int targets_per_lane, int source_splits);
 rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_per_lane, int *source_splits);

@@ -32,6 +32,8 @@ using namespace rpy;
 
 namespace {
 
+constexpr int64_t kFusedMaxTuneN = 8192;   // largest N at which the fused kernel is a candidate
+
 // v[i] = (h(i, 0), h(i, 1), h(i, 2), 0) with h a 32-bit integer hash mapped to [-1, 1)
 template <typename Real>
 __global__ void fill_pattern_kernel(vec4_t<Real> *__restrict__ v, int64_t n, unsigned salt) {
@@ -113,6 +115,9 @@ template <typename Real>
 rpy_status run_config(rpy_solver *s, bool ang, const TileConfig &c, hipStream_t st, Real *out) {
     const int64_t n = s->n;
     if (c.tm == 0) return apply_sym<Real, Real>(s, ang, c.n_split, out, ang ? out + 3 * n : nullptr, st);
+    if (c.tm == 3)
+        return apply_fused<Real, Real>(s, ang, s->f.as<Real>(), ang ? s->t.as<Real>() : nullptr, 4, out,
+                                       ang ? out + 3 * n : nullptr, st);
     const PairConst<Real> pc = make_pair_const<Real>(s->radius);
     const auto *pos = s->pos.as<vec4_t<Real>>();
     const auto *f = s->f.as<vec4_t<Real>>();
@@ -201,6 +206,15 @@ rpy_status tune_mode(rpy_solver *s, bool ang, hipStream_t st, Entry *best) {
         }
         if (r != RPY_OK) break;
     }
+    // the fused small-N kernel (one launch, no split partials)
+    if (r == RPY_OK && n <= kFusedMaxTuneN) {
+        TileConfig c;
+        c.tm = 3;
+        c.n_split = 0;
+        double ms = 0.0;
+        r = time_config<Real>(s, ang, c, 3, st, a, b, out.as<Real>(), &ms);
+        if (r == RPY_OK) screened.push_back({ms, c});
+    }
     // the symmetric pair mode, spans of 1 and 2 source blocks per task, where
     // its source-side partials stay modest and there are blocks to pair
     if (r == RPY_OK && n >= 4096 && n <= sym_max_n()) {
@@ -271,8 +285,9 @@ extern "C" {
 
 rpy_status rpy_set_tile_config(rpy_solver *s, int angular, int targets_per_lane, int source_splits) {
     if (!s) return RPY_ERR_INVALID_ARG;
-    if (targets_per_lane != 0 && targets_per_lane != 1 && targets_per_lane != 2 && targets_per_lane != 4)
-        return fail(s, RPY_ERR_INVALID_ARG, "targets per lane must be 1, 2 or 4 (0: symmetric pair mode)");
+    if (targets_per_lane < 0 || targets_per_lane > 4)
+        return fail(s, RPY_ERR_INVALID_ARG,
+                    "targets per lane must be 1, 2 or 4 (0: symmetric pair mode, 3: fused small-N kernel)");
     if (source_splits < 0) return fail(s, RPY_ERR_INVALID_ARG, "source splits must be >= 0");
     TileConfig &c = s->cfg[angular ? 1 : 0];
     c.tm = targets_per_lane;

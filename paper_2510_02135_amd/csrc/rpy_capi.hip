@@ -29,9 +29,10 @@ double k_factor(const rpy_solver *s) { return 1.0 / (8.0 * M_PI * s->eta); }
 
 int splits_for(const rpy_solver *s, bool ang) {
     const TileConfig &c = s->cfg[ang ? 1 : 0];
-    // in the symmetric mode n_split is a task span; other kernels that share
-    // the split layout (multi-vector products) then choose their own
-    if (c.tm == 0) return choose_splits(s->n, 2, s->dtype == RPY_F64, ang);
+    // in the symmetric and fused modes n_split is not a split count; other
+    // kernels that share the split layout (multi-vector products) then choose
+    // their own
+    if (c.tm == 0 || c.tm == 3) return choose_splits(s->n, 2, s->dtype == RPY_F64, ang);
     if (c.n_split > 0) return std::min(c.n_split, max_splits(s->n));
     return choose_splits(s->n, c.tm, s->dtype == RPY_F64, ang);
 }
@@ -45,6 +46,9 @@ rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *angout, hipStr
         return apply_wall<Real, Tout>(s, ang, s->f.as<vec4_t<Real>>(), s->t.as<vec4_t<Real>>(), lin, angout, st,
                                       pos_in);
     if (s->cfg[ang ? 1 : 0].tm == 0) return apply_sym<Real, Tout>(s, ang, s->cfg[ang ? 1 : 0].n_split, lin, angout, st, pos_in);
+    if (s->cfg[ang ? 1 : 0].tm == 3)
+        return apply_fused<Real, Tout>(s, ang, s->f.as<Real>(), ang ? s->t.as<Real>() : nullptr, 4, lin, angout, st,
+                                       pos_in);
     const int64_t n = s->n;
     const int splits = splits_for(s, ang);
     const int nc = (ang ? 6 : 3) * (std::is_same<Real, float>::value ? 2 : 1);
@@ -114,6 +118,8 @@ namespace {
 template <typename Real>
 rpy_status mdot_typed(rpy_solver *s, const Real *F, const Real *T, Real *lin, Real *ang, hipStream_t st) {
     const bool angmode = (T != nullptr) || (ang != nullptr);
+    if (s->cfg[angmode ? 1 : 0].tm == 3 && !s->wall && !s->pse)   // one launch, no staging
+        return apply_fused<Real, Real>(s, angmode, F, T, 3, lin, ang, st);
     rpy_status r = ensure_vec_buffers(s, angmode);
     if (r != RPY_OK) return r;
     HIP_TRY(s, (launch_stage_vec<Real, Real>(F, s->n, s->f.as<vec4_t<Real>>(), st)));

@@ -67,9 +67,9 @@ rpy_status mdot_noalloc_typed(rpy_solver *s, const Real *F, const Real *T, Real 
     const int fit = (int)std::min<size_t>((kScratchBytes - staged) / split_bytes, (size_t)max_splits(n));
     TileConfig cfg = s->cfg[angmode ? 1 : 0];
     int splits;
-    if (cfg.tm == 0) {
-        // the symmetric mode needs workspace that grows as N^2: use the
-        // ordinary kernel with its default tiles instead
+    if (cfg.tm == 0 || cfg.tm == 3) {
+        // the symmetric mode needs workspace that grows as N^2, the fused
+        // kernel is another kernel: use the ordinary one with its default tiles
         cfg.tm = 2;
         cfg.n_split = 0;
         splits = choose_splits(n, 2, std::is_same<Real, double>::value, angmode);

@@ -26,6 +26,14 @@ template <typename Real, typename Tout>
 rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *ang_out, hipStream_t st,
                         const void *pos = nullptr);
 
+// M [F; T] by the fused small-N kernel (tile mode 3, rpy_fused.hip): forces
+// f and torques t (either may be NULL) with `stride` Reals per particle (3
+// for the caller's N x 3 arrays, 4 for staged vec4 records); outputs as
+// apply_staged (ang_out may be NULL).
+template <typename Real, typename Tout>
+rpy_status apply_fused(rpy_solver *s, bool ang, const Real *f, const Real *t, int stride, Tout *lin, Tout *ang_out,
+                       hipStream_t st, const void *pos = nullptr);
+
 // M [F; T] above the wall of a single_wall solver (rpy_wall.hip), with the
 // staged vectors f (and t) given explicitly; otherwise as apply_staged.
 template <typename Real, typename Tout>

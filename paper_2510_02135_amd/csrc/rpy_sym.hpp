@@ -275,8 +275,30 @@ __device__ __forceinline__ void sym_block_task(const typename P::Args &args, int
     // plus a constant per step.  Source-side sums travel with their source
     // through the lanes (registers rotated by one lane per step) and land in
     // jl[bf][wave][k][q] at the end of the chunk
-    __shared__ R4 rec[2][NR][2 * kSymChunk];
+    // float64 records are kept as two 16-byte planes (x, y) and (z, w): lanes
+    // reading consecutive 32-byte records would put lanes l and l + 4 on the
+    // same LDS banks; with 16-byte planes each group of 8 lanes covers the 32
+    // banks once
+    constexpr int HP = std::is_same<Real, double>::value ? 2 : 1;
+    using H = typename std::conditional<HP == 2, double2, R4>::type;
+    __shared__ H rec[2][NR][HP][2 * kSymChunk];
     __shared__ Real jl[2][kWaves][NC][kSymChunk];
+    auto put_rec = [&](int bf, int r, int col, const R4 &v) {
+        if constexpr (HP == 2) {
+            rec[bf][r][0][col] = H{v.x, v.y};
+            rec[bf][r][1][col] = H{v.z, v.w};
+        } else {
+            rec[bf][r][0][col] = v;
+        }
+    };
+    auto get_rec = [&](int bf, int r, int col) -> R4 {
+        if constexpr (HP == 2) {
+            const H a = rec[bf][r][0][col], b = rec[bf][r][1][col];
+            return R4{a.x, a.y, b.x, b.y};
+        } else {
+            return rec[bf][r][0][col];
+        }
+    };
 
     const int bi = task.x;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -326,8 +348,8 @@ __device__ __forceinline__ void sym_block_task(const typename P::Args &args, int
         for (int u = 0; u < RPW; ++u) {
             const int r = wv + u * kWaves;
             if (r < NR) {
-                rec[bf][r][lane] = nxt[u];
-                rec[bf][r][lane + kSymChunk] = nxt[u];
+                put_rec(bf, r, lane, nxt[u]);
+                put_rec(bf, r, lane + kSymChunk, nxt[u]);
             }
         }
         // rec[bf] complete; every wave has finished chunk ci - 1
@@ -344,7 +366,7 @@ __device__ __forceinline__ void sym_block_task(const typename P::Args &args, int
             for (int q = 0; q < kSymChunk; ++q) {
                 R4 rq[NR];
 #pragma unroll
-                for (int r = 0; r < NR; ++r) rq[r] = rec[bf][r][q];
+                for (int r = 0; r < NR; ++r) rq[r] = get_rec(bf, r, q);
 #pragma unroll
                 for (int m = 0; m < TM; ++m) P::one_sided(tg[m], rq, c, acc[m]);
             }
@@ -360,7 +382,7 @@ __device__ __forceinline__ void sym_block_task(const typename P::Args &args, int
                 const int q = lane + st;
                 R4 rq[NR];
 #pragma unroll
-                for (int r = 0; r < NR; ++r) rq[r] = rec[bf][r][q];
+                for (int r = 0; r < NR; ++r) rq[r] = get_rec(bf, r, q);
 #pragma unroll
                 for (int m = 0; m < TM; ++m) P::both(tg[m], rq, c, acc[m], sj);
 #pragma unroll

@@ -142,7 +142,7 @@ def test_tile_config_accessors(lib):
         assert lib.rpy_get_tile_config(h, 0, ctypes.byref(tm), ctypes.byref(sp)) == OK and (tm.value, sp.value) == (2, 0)
         assert lib.rpy_set_tile_config(h, 1, 4, 9) == OK
         assert lib.rpy_get_tile_config(h, 1, ctypes.byref(tm), ctypes.byref(sp)) == OK and (tm.value, sp.value) == (4, 9)
-        assert lib.rpy_set_tile_config(h, 0, 3, 0) == INVALID
+        assert lib.rpy_set_tile_config(h, 0, 5, 0) == INVALID and lib.rpy_set_tile_config(h, 0, 3, 0) == OK
         assert lib.rpy_set_tile_config(h, 0, 0, 2) == OK and lib.rpy_set_tile_config(h, 0, -1, 0) == INVALID
         assert lib.rpy_set_tile_config(h, 0, 2, -1) == INVALID
         assert lib.rpy_autotune(h, None, None) == NOT_INIT

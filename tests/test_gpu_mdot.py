@@ -176,8 +176,8 @@ def test_every_tile_config_and_autotune_keep_parity(dtype, tmp_path):
     F, T = to_dev(s.forces, dtype), to_dev(s.torques, dtype)
     sol_lin = _solver(False)
     sol_lin.setPositions(to_dev(s.pos, dtype))
-    for tm in (1, 2, 4):
-        for sp in (0, 1, 3, 6):
+    for tm in (1, 2, 3, 4):
+        for sp in ((0,) if tm == 3 else (0, 1, 3, 6)):
             sol.setTileConfig(True, tm, sp)
             lin, ang = sol.Mdot(F, T)
             assert max(emax(host(lin), u_ref), emax(host(ang), w_ref)) <= tol_for(dtype), (tm, sp)
@@ -188,14 +188,65 @@ def test_every_tile_config_and_autotune_keep_parity(dtype, tmp_path):
     cfg_lin, cfg_ang = sol.autotune(str(cache))
     lines = cache.read_text().strip().splitlines()
     say(f"  tuned lin {cfg_lin} ang {cfg_ang}; cache {lines}")
-    assert len(lines) == 2 and cfg_lin[1] >= 1 and cfg_ang[1] >= 1
+    assert len(lines) == 2
+    for cfg in (cfg_lin, cfg_ang):           # a split count, or the fused kernel (no splits)
+        assert cfg[1] >= 1 or cfg[0] == 3
     lin, ang = sol.Mdot(F, T)
     assert max(emax(host(lin), u_ref), emax(host(ang), w_ref)) <= tol_for(dtype)
     other = _solver(True)
     other.setPositions(to_dev(s.pos, dtype))
     assert other.autotune(str(cache)) == (cfg_lin, cfg_ang)
-    with pytest.raises(rpy.RpyError):
-        sol.setTileConfig(False, 3, 0)
+    for bad in (5, -1):
+        with pytest.raises(rpy.RpyError):
+            sol.setTileConfig(False, bad, 0)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("angular", [False, True])
+@pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 63, 64, 65, 1000, 4097])
+def test_fused_small_n_kernel(dtype, angular, n):
+    """Tile mode 3 (one launch reading the caller's arrays): every size from
+    one particle through partial workgroups and uneven source sixteenths."""
+    say(f"case fused n={n} angular={angular} {dtype}")
+    rng = np.random.default_rng(700 + n)
+    x = (rng.random((n, 3)) - 0.5) * workloads.cube_side(n, 0.2)
+    F = rng.standard_normal((n, 3))
+    T = rng.standard_normal((n, 3)) if angular else None
+    a, eta = 1.1, 0.7
+    sol = _solver(angular, a, eta)
+    sol.setTileConfig(angular, 3, 0)
+    e = _check(sol, x, F, T, dtype, a, eta, angular)
+    say(f"  e_max {e:.3e}")
+    assert e <= tol_for(dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_fused_kernel_lanczos_torque_only_and_missing_angular_output(dtype):
+    from oracle import lanczos
+    from paper_2510_02135_amd import _lib
+    say(f"case fused lanczos / torque only {dtype}")
+    s = workloads.uniform_cube(400, 0.15, 78, torques=True, w=True, angular_w=True)
+    sol = _solver(True)
+    sol.setTileConfig(True, 3, 0)
+    sol.setTileConfig(False, 3, 0)
+    sol.setPositions(to_dev(s.pos, dtype))
+    xr, wr = rounded(s.pos, dtype), rounded(s.w, dtype)
+    lin, ang = sol.sqrtMdotW(to_dev(s.w, dtype), tol=1e-6)
+    k = sol.last_iterations
+    m = mobility.grand_mobility(xr, s.radius, s.viscosity, True)
+    y_ref, _ = lanczos.lanczos_sqrt(lambda v: m @ v, wr, iters=k)
+    y = np.concatenate([host(lin).reshape(-1), host(ang).reshape(-1)])
+    e = float(np.abs(y - y_ref).max() / np.abs(y_ref).max())
+    say(f"  lanczos {k} iterations, matched max rel {e:.3e}")
+    assert e <= (1e-12 if dtype == torch.float64 else 1e-5)
+    # torques with no angular output through the C call: linear rows only
+    T = to_dev(s.torques, dtype)
+    out = torch.empty((s.n, 3), dtype=dtype, device="cuda")
+    _lib.rpy_mdot(sol._h, None, T, out, None, dtype, s.n)
+    u, _ = mobility.mdot_dense(xr, None, rounded(s.torques, dtype), s.radius, s.viscosity)
+    assert emax(host(out), u) <= tol_for(dtype)
+    # fixed summation order: repeated calls agree bit for bit
+    assert torch.equal(sol.Mdot(None, T)[0], sol.Mdot(None, T)[0])
 
 
 def test_error_paths_through_the_binding():
