@@ -583,7 +583,9 @@ rpy_status rpy_enable_timing(rpy_solver *s, int enable);
  * RPY_KERNEL_PAIR_MULTI; algorithmic HBM bytes for
  * RPY_KERNEL_LANCZOS_CGS (per pass at iteration k with basis vectors of n
  * doubles: (k + 1) n reads for V^T w, (k + 1) n reads and n writes for the
- * update, times 8 bytes).  Waits for the recorded events (host blocking).
+ * update, times 8 bytes; the second pass counts only where it ran: it is
+ * skipped when the first removed at most half of |w|^2).  Waits for the
+ * recorded events (host blocking).
  * Any output pointer may be NULL.
  */
 rpy_status rpy_kernel_time(rpy_solver *s, rpy_kernel kernel, double *ms_total, int64_t *launches,

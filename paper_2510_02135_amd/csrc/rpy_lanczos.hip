@@ -44,7 +44,11 @@ constexpr int kRedThreads = 256;
 // status block (double): [0] beta0, [1] relative increment, [2] flags,
 // [3] running max(|alpha|, beta), [4] first breakdown iteration (0 = none),
 // [5] estimated relative increment (monitor)
-enum { ST_BETA0 = 0, ST_INCR = 1, ST_FLAGS = 2, ST_TSCALE = 3, ST_BREAK = 4, ST_EST = 5, ST_SIZE = 8 };
+// status block: beta0, increment, flags, scale of T, breakdown step, stopping
+// estimate, |w|^2 before Gram-Schmidt, skip flag of the second pass, bytes
+// of skipped passes
+enum { ST_BETA0 = 0, ST_INCR = 1, ST_FLAGS = 2, ST_TSCALE = 3, ST_BREAK = 4, ST_EST = 5, ST_NW = 6, ST_SKIP = 7,
+       ST_SKIPPED = 8, ST_SIZE = 10 };
 enum { FLAG_NOT_SPD = 1, FLAG_NONFINITE = 2 };
 
 // partial[b] = sum over the b-th strided slice of a[i] * b[i]
@@ -56,6 +60,49 @@ __global__ void dot_partial(const double *__restrict__ a, const double *__restri
         acc = fma(a[i], b[i], acc);
     const double r = block_sum(acc, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
+}
+
+// Breakdown bookkeeping after beta_k: running max(|alpha|, beta) and the
+// first k with beta_k <= 1e-14 of it.
+__device__ __forceinline__ void finish_iter(const double *__restrict__ alpha, const double *__restrict__ beta, int k,
+                                            double *__restrict__ status) {
+    const double a = fabs(alpha[k - 1]), b = beta[k - 1];
+    const double sc = fmax(status[ST_TSCALE], fmax(a, b));
+    status[ST_TSCALE] = sc;
+    if (status[ST_BREAK] == 0.0 && !(b > 1e-14 * sc)) status[ST_BREAK] = (double)k;
+}
+
+// *out = a . b (or its square root) in one launch: every block stores its
+// partial sum, and the block that finishes last (a counter, reset by it)
+// adds the partials in the fixed order of reduce_scalar, so the result is
+// that of dot_partial + reduce_scalar bit for bit.  With `status` the last
+// block then runs the breakdown bookkeeping of iteration k.
+__global__ void __launch_bounds__(kRedThreads)
+dot_reduce(const double *__restrict__ a, const double *__restrict__ b, int64_t n, double *__restrict__ partial,
+           unsigned *__restrict__ counter, double *out, int take_sqrt, const double *alpha, const double *beta,
+           int k, double *status) {
+    __shared__ double sh[kRedThreads];
+    __shared__ bool last;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc = fma(a[i], b[i], acc);
+    const double r = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = r;
+        __threadfence();
+        last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double t = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) t += partial[i];
+    const double tot = block_sum(t, sh);
+    if (threadIdx.x == 0) {
+        *out = take_sqrt ? sqrt(tot) : tot;
+        *counter = 0u;
+        if (status) finish_iter(alpha, beta, k, status);
+    }
 }
 
 // out = sum(partial) (or its square root); optional second copy
@@ -128,10 +175,13 @@ __device__ __forceinline__ void gemv_t_tile(const double *__restrict__ V, int64_
     }
 }
 
+// The kernels of a Gram-Schmidt pass take `skip` (NULL for the first pass):
+// the second pass does nothing when *skip is set (see cgs_decide).
 __global__ void __launch_bounds__(kRedThreads)
 gemv_t_partial(const double *__restrict__ V, int64_t ld, int k, const double *__restrict__ w, int64_t n,
-               double *__restrict__ partial) {
+               double *__restrict__ partial, const double *skip) {
     static_assert(kRedThreads == 256 && kGtCols * 16 == kRedThreads, "tile reduction layout");
+    if (skip && *skip != 0.0) return;
     __shared__ double sh[kGtCols][kRedThreads];
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kGtChunk + tid;
@@ -155,8 +205,10 @@ gemv_t_partial(const double *__restrict__ V, int64_t ld, int k, const double *__
 }
 
 // h[j] = sum_b partial[b * k + j]   (one block per j)
-__global__ void gemv_t_final(const double *__restrict__ partial, int nb, int k, double *__restrict__ h) {
+__global__ void gemv_t_final(const double *__restrict__ partial, int nb, int k, double *__restrict__ h,
+                             const double *skip) {
     __shared__ double sh[kRedThreads];
+    if (skip && *skip != 0.0) return;
     const int j = blockIdx.x;
     double acc = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += partial[(size_t)b * k + j];
@@ -166,14 +218,34 @@ __global__ void gemv_t_final(const double *__restrict__ partial, int nb, int k, 
 
 // w[i] -= sum_j V[j][i] h[j]
 __global__ void gemv_n_sub(const double *__restrict__ V, int64_t ld, int k, const double *__restrict__ h,
-                           double *__restrict__ w, int64_t n) {
+                           double *__restrict__ w, int64_t n, const double *skip) {
     __shared__ double hs[kMaxK];
+    if (skip && *skip != 0.0) return;
     for (int j = threadIdx.x; j < k; j += blockDim.x) hs[j] = h[j];
     __syncthreads();
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double acc = 0.0;
         for (int j = 0; j < k; ++j) acc = fma(V[(size_t)j * ld + i], hs[j], acc);
         w[i] -= acc;
+    }
+}
+
+// After the first Gram-Schmidt pass, with h its coefficients: the removed
+// part has squared norm |h|^2 (V orthonormal), so the second pass is needed
+// only when |h|^2 > |w|^2 / 2, i.e. when the first pass cut |w| below
+// 1/sqrt(2) of itself (Kahan and Parlett's "twice is enough" test, as in
+// Daniel, Gragg, Kaufman and Stewart's reorthogonalisation).  Otherwise w is
+// already orthogonal to V to working precision; the skip flag is set and the
+// skipped pass's bytes are counted.  NaN never skips.
+__global__ void cgs_decide(const double *__restrict__ h, int k, double *__restrict__ status, double pass_bytes) {
+    __shared__ double sh[kRedThreads];
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < k; j += blockDim.x) acc = fma(h[j], h[j], acc);
+    const double hh = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        const bool skip = hh <= 0.5 * status[ST_NW];
+        status[ST_SKIP] = skip ? 1.0 : 0.0;
+        if (skip) status[ST_SKIPPED] += pass_bytes;
     }
 }
 
@@ -238,15 +310,6 @@ __global__ void increment_kernel(const double *__restrict__ s0, const double *__
 
 // After beta_k: track max(|alpha|, beta) and record the first breakdown
 // beta_k <= 1e-14 max(|alpha|, beta) (the Krylov space is invariant).
-__global__ void finish_iter_kernel(const double *__restrict__ alpha, const double *__restrict__ beta, int k,
-                                   double *__restrict__ status) {
-    if (threadIdx.x != 0) return;
-    const double a = fabs(alpha[k - 1]), b = beta[k - 1];
-    const double sc = fmax(status[ST_TSCALE], fmax(a, b));
-    status[ST_TSCALE] = sc;
-    if (status[ST_BREAK] == 0.0 && !(b > 1e-14 * sc)) status[ST_BREAK] = (double)k;
-}
-
 // v_{k+1} = w / beta_k, or zeros once a breakdown has been recorded.
 __global__ void next_basis_kernel(double *__restrict__ dst, const double *__restrict__ src,
                                   const double *__restrict__ beta, const double *__restrict__ status, int64_t n) {
@@ -338,7 +401,10 @@ rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t w
     HIP_TRY(s, s->lz_red.ensure(sizeof(double) * red_rows * (kMaxK + 1)));
     HIP_TRY(s, s->lz_q.ensure(sizeof(double) * 2 * (size_t)kmax * kmax));
     const int64_t mon_stride = (int64_t)kmax * kMonNodes;
-    HIP_TRY(s, s->lz_mon.ensure(sizeof(double) * 2 * (size_t)mon_stride));
+    // monitor scratch, then one word for the counter of dot_reduce
+    HIP_TRY(s, s->lz_mon.ensure(sizeof(double) * (2 * (size_t)mon_stride + 1)));
+    unsigned *const cnt = reinterpret_cast<unsigned *>(s->lz_mon.as<double>() + 2 * (size_t)mon_stride);
+    HIP_TRY(s, launch_fill_zero<unsigned>(cnt, 1, st));
     if (s->host_stat_cap < (size_t)nrhs * ST_SIZE) {
         if (s->host_stat) (void)hipHostFree(s->host_stat);
         s->host_stat = nullptr;
@@ -447,23 +513,29 @@ rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t w
             if (k > 1)
                 hipLaunchKernelGGL(axpy_dev, dim3(g), dim3(256), 0, st, w, R.V + (size_t)(k - 2) * ld, R.beta + (k - 2),
                                    -1.0, n);
-            hipLaunchKernelGGL(dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, vk, w, n, red);
-            hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, red, kRedBlocks, R.alpha + (k - 1), 0);
+            hipLaunchKernelGGL(dot_reduce, dim3(kRedBlocks), dim3(kRedThreads), 0, st, vk, w, n, red, cnt,
+                               R.alpha + (k - 1), 0, nullptr, nullptr, 0, nullptr);
             hipLaunchKernelGGL(axpy_dev, dim3(g), dim3(256), 0, st, w, vk, R.alpha + (k - 1), -1.0, n);
-            // classical Gram-Schmidt against V_k, twice
-            hipEvent_t cgs0 = timing_begin(s, RPY_KERNEL_LANCZOS_CGS, 2.0 * (2.0 * k + 3.0) * (double)n * 8.0);
+            // classical Gram-Schmidt against V_k, the second pass only when
+            // the first removed a sizeable part of w (cgs_decide)
+            const double pass_bytes = (2.0 * k + 3.0) * (double)n * 8.0;
+            hipLaunchKernelGGL(dot_reduce, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, w, n, red, cnt,
+                               R.status + ST_NW, 0, nullptr, nullptr, 0, nullptr);
+            hipEvent_t cgs0 = timing_begin(s, RPY_KERNEL_LANCZOS_CGS, 2.0 * pass_bytes);
             if (cgs0) HIP_TRY(s, hipEventRecord(cgs0, st));
             for (int pass = 0; pass < 2; ++pass) {
+                const double *skip = pass == 0 ? nullptr : R.status + ST_SKIP;
                 hipLaunchKernelGGL(gemv_t_partial, dim3(gt_blocks, (k + kGtCols - 1) / kGtCols), dim3(kRedThreads), 0,
-                                   st, R.V, ld, k, w, n, red);
-                hipLaunchKernelGGL(gemv_t_final, dim3(k), dim3(kRedThreads), 0, st, red, gt_blocks, k, R.h);
-                hipLaunchKernelGGL(gemv_n_sub, dim3(g), dim3(256), 0, st, R.V, ld, k, R.h, w, n);
+                                   st, R.V, ld, k, w, n, red, skip);
+                hipLaunchKernelGGL(gemv_t_final, dim3(k), dim3(kRedThreads), 0, st, red, gt_blocks, k, R.h, skip);
+                if (pass == 0)
+                    hipLaunchKernelGGL(cgs_decide, dim3(1), dim3(kRedThreads), 0, st, R.h, k, R.status, pass_bytes);
+                hipLaunchKernelGGL(gemv_n_sub, dim3(g), dim3(256), 0, st, R.V, ld, k, R.h, w, n, skip);
             }
             if (hipEvent_t cgs1 = timing_end(s, RPY_KERNEL_LANCZOS_CGS)) HIP_TRY(s, hipEventRecord(cgs1, st));
             // beta_k = |w|, breakdown bookkeeping
-            hipLaunchKernelGGL(dot_partial, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, w, n, red);
-            hipLaunchKernelGGL(reduce_scalar, dim3(1), dim3(kRedThreads), 0, st, red, kRedBlocks, R.beta + (k - 1), 1);
-            hipLaunchKernelGGL(finish_iter_kernel, dim3(1), dim3(64), 0, st, R.alpha, R.beta, k, R.status);
+            hipLaunchKernelGGL(dot_reduce, dim3(kRedBlocks), dim3(kRedThreads), 0, st, w, w, n, red, cnt,
+                               R.beta + (k - 1), 1, R.alpha, R.beta, k, R.status);
             HIP_TRY(s, hipGetLastError());
             R.exact = (k == kmax) || check_every;
         }
@@ -562,6 +634,12 @@ rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t w
     }
     HIP_TRY(s, hipGetLastError());
     HIP_TRY(s, hipStreamSynchronize(st));
+    if (s->timing) {
+        // the Gram-Schmidt timing counted two passes per iteration; take off
+        // the bytes of the second passes that were skipped
+        if ((r = copy_status()) != RPY_OK) return r;
+        for (int q = 0; q < nrhs; ++q) s->ev_pairs[RPY_KERNEL_LANCZOS_CGS] -= hstat[(size_t)q * ST_SIZE + ST_SKIPPED];
+    }
     if (any_not_spd)
         return fail(s, RPY_ERR_NOT_SPD, "the mobility matrix is not positive definite (negative Ritz value)");
     if (any_not_conv)
