@@ -412,11 +412,175 @@ __device__ __forceinline__ void table_lookup(const vec2_t<Real> *__restrict__ ta
     g = w0 * a.y + w1 * b.y + w2 * c.y + w3 * d.y;
 }
 
-// Real-space part: one thread per target slot, the 27 (or fewer distinct)
-// neighbour cells, minimum image, pairs closer than rc.  Writes (ADD =
+template <typename Real>
+__device__ __forceinline__ Real wave_reduce(Real v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Real part of one pair in k-units: (A - f) F + (B - g / r^2)(d.F) d, with
+// the RPY coefficients A, B (overlap branch and r = 0 included) and Wr's
+// (f, g) from the table.
+template <typename Real>
+__device__ __forceinline__ void real_pair(Real dx, Real dy, Real dz, Real r2, const vec4_t<Real> &F,
+                                          const PairConst<Real> &pc, const vec2_t<Real> *__restrict__ tab,
+                                          Real inv_dr, Real &u0, Real &u1, Real &u2) {
+    Real A, B, r;
+    if (r2 < pc.four_a2) {
+        const Real rs = r2 > Real(0) ? rsq(r2) : Real(0);
+        r = r2 * rs;
+        A = fma(pc.nA1, r, pc.nA0);
+        B = pc.nB * rs;
+    } else {
+        const Real ri = rsq(r2);
+        const Real ri2 = ri * ri, ri3 = ri * ri2;
+        r = r2 * ri;
+        A = fma(pc.two_a2_3, ri3, ri);
+        B = fma(pc.m_two_a2, ri3 * ri2, ri3);
+    }
+    Real f, g;
+    table_lookup<Real>(tab, r * inv_dr, f, g);
+    A -= f;
+    if (r2 > Real(0)) B -= g / r2;
+    const Real sdf = B * fma(dx, F.x, fma(dy, F.y, dz * F.z));
+    u0 = fma(A, F.x, fma(sdf, dx, u0));
+    u1 = fma(A, F.y, fma(sdf, dy, u1));
+    u2 = fma(A, F.z, fma(sdf, dz, u2));
+}
+
+// Real-space part, one wavefront per tile.  The wavefront loads the particle
+// ranges of the tiles within rc (at most kRealNbr of them) into LDS at once
+// and scans their counts; the particles of those tiles then form one virtual
+// list that the lanes take 64 at a time (virtual index -> tile by binary
+// search), every loop uniform over the wavefront.  Each lane evaluates its
+// source against the tile's targets, kRealTargets at a time held in
+// registers (nearest image, pairs closer than rc); the per-target sums are
+// reduced over the lanes in a fixed order and lane 0 writes (ADD = false) or
+// adds k * sum into out[original index].
+constexpr int kRealTargets = 8;
+constexpr int kRealNbr = 343;                        // tiles within rc (reach <= 3)
+constexpr int kRealPer = (kRealNbr + 63) / 64;       // neighbour entries per lane in the scan
+
+template <typename Real, typename Tout, bool ADD>
+__global__ void __launch_bounds__(256) pse_real_tiles(int ntiles, const vec4_t<Real> *__restrict__ spos,
+                                                      const vec4_t<Real> *__restrict__ sfrc,
+                                                      const int *__restrict__ order, const int *__restrict__ start,
+                                                      PseConst<Real> c, PairConst<Real> pc,
+                                                      const vec2_t<Real> *__restrict__ tab, Real kf,
+                                                      Tout *__restrict__ out) {
+    __shared__ int nb_first[4][kRealNbr], nb_pref[4][kRealNbr + 1];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tile = blockIdx.x * 4 + wv;
+    if (tile >= ntiles) return;   // whole wavefront; no workgroup barrier below
+    const int ts = start[tile], te = start[tile + 1];
+    if (ts == te) return;
+    const int t2 = tile % c.ncell[2];
+    const int t1 = (tile / c.ncell[2]) % c.ncell[1];
+    const int t0 = tile / (c.ncell[2] * c.ncell[1]);
+    int *nf = nb_first[wv], *np = nb_pref[wv];
+    const int nnb = c.nbr_cnt[0] * c.nbr_cnt[1] * c.nbr_cnt[2];
+    // lane l owns neighbour entries kRealPer l .. kRealPer l + kRealPer - 1
+    int cnt[kRealPer], run = 0;
+#pragma unroll
+    for (int u = 0; u < kRealPer; ++u) {
+        const int k = lane * kRealPer + u;
+        cnt[u] = 0;
+        if (k < nnb) {
+            const int oz = k % c.nbr_cnt[2], oy = (k / c.nbr_cnt[2]) % c.nbr_cnt[1];
+            const int ox = k / (c.nbr_cnt[2] * c.nbr_cnt[1]);
+            int a = t0 + c.nbr_lo[0] + ox, b = t1 + c.nbr_lo[1] + oy, e = t2 + c.nbr_lo[2] + oz;
+            a += a < 0 ? c.ncell[0] : (a >= c.ncell[0] ? -c.ncell[0] : 0);
+            b += b < 0 ? c.ncell[1] : (b >= c.ncell[1] ? -c.ncell[1] : 0);
+            e += e < 0 ? c.ncell[2] : (e >= c.ncell[2] ? -c.ncell[2] : 0);
+            const int cell = (a * c.ncell[1] + b) * c.ncell[2] + e;
+            const int s0 = start[cell];
+            nf[k] = s0;
+            cnt[u] = start[cell + 1] - s0;
+        }
+        run += cnt[u];
+    }
+    // exclusive scan of the lanes' totals, then each lane's entries
+    int incl = run;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    int pre = incl - run;
+#pragma unroll
+    for (int u = 0; u < kRealPer; ++u) {
+        const int k = lane * kRealPer + u;
+        if (k < nnb) np[k] = pre;
+        pre += cnt[u];
+    }
+    const int total = __shfl(incl, 63, 64);
+    if (lane == 0) np[nnb] = total;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int tb = ts; tb < te; tb += kRealTargets) {
+        const int nt = min(kRealTargets, te - tb);
+        Real tx[kRealTargets], ty[kRealTargets], tz[kRealTargets];
+        Real a0[kRealTargets], a1[kRealTargets], a2[kRealTargets];
+#pragma unroll
+        for (int t = 0; t < kRealTargets; ++t) {
+            const vec4_t<Real> p = spos[tb + min(t, nt - 1)];
+            tx[t] = p.x;
+            ty[t] = p.y;
+            tz[t] = p.z;
+            a0[t] = a1[t] = a2[t] = Real(0);
+        }
+        for (int base = 0; base < total; base += 64) {
+            const int v = base + lane;
+            if (v < total) {
+                int lo = 0, hi = nnb - 1;   // last k with np[k] <= v
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (np[mid] <= v) lo = mid; else hi = mid - 1;
+                }
+                const int j = nf[lo] + (v - np[lo]);
+                const vec4_t<Real> sp = spos[j];
+                const vec4_t<Real> F = sfrc[j];
+#pragma unroll
+                for (int t = 0; t < kRealTargets; ++t) {
+                    if (t < nt) {
+                        Real dx = tx[t] - sp.x, dy = ty[t] - sp.y, dz = tz[t] - sp.z;
+                        dx -= c.L[0] * rint(dx * c.invL[0]);
+                        dy -= c.L[1] * rint(dy * c.invL[1]);
+                        dz -= c.L[2] * rint(dz * c.invL[2]);
+                        const Real r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                        if (r2 < c.rc2) real_pair<Real>(dx, dy, dz, r2, F, pc, tab, c.inv_dr, a0[t], a1[t], a2[t]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kRealTargets; ++t) {
+            if (t < nt) {
+                const Real s0 = wave_reduce(a0[t]), s1 = wave_reduce(a1[t]), s2 = wave_reduce(a2[t]);
+                if (lane == 0) {
+                    const size_t o = (size_t)order[tb + t] * 3;
+                    if (ADD) {
+                        out[o + 0] = (Tout)((Tout)out[o + 0] + (Tout)(kf * s0));
+                        out[o + 1] = (Tout)((Tout)out[o + 1] + (Tout)(kf * s1));
+                        out[o + 2] = (Tout)((Tout)out[o + 2] + (Tout)(kf * s2));
+                    } else {
+                        out[o + 0] = (Tout)(kf * s0);
+                        out[o + 1] = (Tout)(kf * s1);
+                        out[o + 2] = (Tout)(kf * s2);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Real-space part, fallback for cutoffs spanning more than kRealNbr tiles:
+// one thread per target slot, the minimum image, pairs closer than rc.  Writes (ADD =
 // false) or adds k * sum into out[original index].
 template <typename Real, typename Tout, bool ADD>
-__global__ void __launch_bounds__(256) pse_real(int n, const vec4_t<Real> *__restrict__ spos,
+__global__ void __launch_bounds__(256) pse_real_threads(int n, const vec4_t<Real> *__restrict__ spos,
                                                 const vec4_t<Real> *__restrict__ sfrc, const int *__restrict__ order,
                                                 const int *__restrict__ start, PseConst<Real> c, PairConst<Real> pc,
                                                 const vec2_t<Real> *__restrict__ tab, Real kf, Tout *__restrict__ out) {
@@ -649,13 +813,6 @@ __global__ void __launch_bounds__(256) pse_spread_tiles(const vec4_t<Real> *__re
             grid[2 * ng + idx] = c.gnorm3 * b2;
         }
     }
-}
-
-template <typename Real>
-__device__ __forceinline__ Real wave_reduce(Real v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
 }
 
 // Interpolation: one wavefront per particle, out[i] (+)= scale * sum_m
@@ -977,6 +1134,7 @@ rpy_status configure(rpy_solver *s) {
         reach[d] = (int)std::ceil(rc / (kTile * h[d]));
     }
     const int reach_sp = (int)std::ceil((0.5 * P + 1.0) / kTile);
+
     if (std::pow(std::min(2 * reach_sp + 1, std::max(nc[0], std::max(nc[1], nc[2]))), 3) > kMaxTileNbr)
         return fail(s, RPY_ERR_INVALID_ARG, "tolerance too small: the Gaussian support reaches too many tiles");
     // table of Wr on [-dr, rc + 2 dr]
@@ -1115,6 +1273,24 @@ const vec2_t<Real> *table_of(const PseState &p) {
 
 }  // namespace
 
+// The real-space part: the wavefront-per-tile kernel where at most kRealNbr
+// tiles lie within rc, else the thread-per-target kernel.
+template <typename Real, typename Tout, bool ADD>
+hipError_t launch_real(const PseState &p, const PseConst<Real> &c, const PairConst<Real> &pc, int64_t n, Real kf,
+                       Tout *out, hipStream_t st) {
+    const int nnb = c.nbr_cnt[0] * c.nbr_cnt[1] * c.nbr_cnt[2];
+    const int64_t ntiles = (int64_t)p.ncell[0] * p.ncell[1] * p.ncell[2];
+    if (nnb <= kRealNbr)
+        hipLaunchKernelGGL((pse_real_tiles<Real, Tout, ADD>), dim3(blocks_for(ntiles, 4)), dim3(256), 0, st,
+                           (int)ntiles, p.spos.as<vec4_t<Real>>(), p.sfrc.as<vec4_t<Real>>(), p.order.as<int>(),
+                           p.start.as<int>(), c, pc, table_of<Real>(p), kf, out);
+    else
+        hipLaunchKernelGGL((pse_real_threads<Real, Tout, ADD>), dim3(blocks_for(n, 256)), dim3(256), 0, st, (int)n,
+                           p.spos.as<vec4_t<Real>>(), p.sfrc.as<vec4_t<Real>>(), p.order.as<int>(), p.start.as<int>(),
+                           c, pc, table_of<Real>(p), kf, out);
+    return hipGetLastError();
+}
+
 // M F for the periodic suspension with F staged in s->f (vec4), positions
 // `pos_in` (vec4) or the stored ones; lin (n x 3, Tout) is overwritten.
 // With real_only set, the real-space part alone.
@@ -1131,10 +1307,7 @@ rpy_status apply_pse(rpy_solver *s, const vec4_t<Real> *f, Tout *lin, hipStream_
     const PairConst<Real> pc = make_pair_const<Real>(s->radius);
     const Real kf = Real(k_factor(s));
     if (p.real_only) {
-        hipLaunchKernelGGL((pse_real<Real, Tout, false>), dim3(blocks_for(n, 256)), dim3(256), 0, st, (int)n,
-                           p.spos.as<vec4_t<Real>>(), p.sfrc.as<vec4_t<Real>>(), p.order.as<int>(), p.start.as<int>(),
-                           c, pc, table_of<Real>(p), kf, lin);
-        HIP_TRY(s, hipGetLastError());
+        HIP_TRY(s, (launch_real<Real, Tout, false>(p, c, pc, n, kf, lin, st)));
         return RPY_OK;
     }
     r = ensure_grids<Real>(s);
@@ -1157,10 +1330,7 @@ rpy_status apply_pse(rpy_solver *s, const vec4_t<Real> *f, Tout *lin, hipStream_
     hipLaunchKernelGGL((pse_interp<Real, Tout, false>), dim3(blocks_for(n, 4)), dim3(256), 0, st, (int)n,
                        p.spos.as<vec4_t<Real>>(), p.order.as<int>(), c, p.rgrid.as<Real>(), vol, lin);
     HIP_TRY(s, hipGetLastError());
-    hipLaunchKernelGGL((pse_real<Real, Tout, true>), dim3(blocks_for(n, 256)), dim3(256), 0, st, (int)n,
-                       p.spos.as<vec4_t<Real>>(), p.sfrc.as<vec4_t<Real>>(), p.order.as<int>(), p.start.as<int>(), c,
-                       pc, table_of<Real>(p), kf, lin);
-    HIP_TRY(s, hipGetLastError());
+    HIP_TRY(s, (launch_real<Real, Tout, true>(p, c, pc, n, kf, lin, st)));
     return RPY_OK;
 }
 
