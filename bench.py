@@ -73,6 +73,8 @@ def parse():
     p.add_argument("--batch-only", nargs="?", const="all", default=None, choices=("all", "mdot"),
                    help="instead of the step: only the 512 batched systems (one launch against one per system); "
                         "'mdot' stops after the batched products")
+    p.add_argument("--sweep-sizes", default=None,
+                   help="comma-separated particle counts for --sweep (default: 2^10 .. 2^20)")
     p.add_argument("--breakdown-only", action="store_true",
                    help="only the float32/float64 Mdot and backward timings at N (tiles from --tiles, else autotuned)")
     p.add_argument("--pse-only", action="store_true",
@@ -349,7 +351,7 @@ def bench_pse(rpy, workloads, dev, stream, sizes=((1 << 20, 0.1), (1 << 17, 0.1)
     return out
 
 
-def bench_sweep(rpy, workloads, dev, stream):
+def bench_sweep(rpy, workloads, dev, stream, sizes=None):
     """One translational float32 Mdot per size, N = 2^10 .. 2^20, uniform cubes
     at number density rho = 0.1 and 0.001 per a^3 (volume fractions 0.419 and
     0.0042), forces N(0, 1): median of timed products (at least 3, about
@@ -361,8 +363,8 @@ def bench_sweep(rpy, workloads, dev, stream):
     out = []
     for rho in (0.1, 0.001):
         phi = rho * 4.0 / 3.0 * math.pi
-        for e in range(10, 21):
-            n = 1 << e
+        for n in (sizes or [1 << e for e in range(10, 21)]):
+            e = max(0, int(n).bit_length() - 1)
             c = workloads.uniform_cube(n, phi, 2000 + e)
             sol = rpy.Solver()
             sol.initialize(viscosity=c.viscosity, hydrodynamicRadius=c.radius, includeAngular=False)
@@ -408,7 +410,8 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     if args.sweep:
-        sweep = bench_sweep(rpy, workloads, dev, stream)
+        sweep = bench_sweep(rpy, workloads, dev, stream,
+                            [int(v) for v in args.sweep_sizes.split(",")] if args.sweep_sizes else None)
         print(json.dumps({"metric": "Mdot time against N (translational, float32)", "unit": "ms",
                           "higher_is_better": False, "n_gpus": 1, "dtype": "f32", "data": "synthetic",
                           "config": {"workload": "uniform cubes, N = 2^10 .. 2^20, number density 0.1 and 0.001 "
