@@ -530,9 +530,13 @@ void rpy_batch_destroy(rpy_batch *b);
  * also caps a slab at m blocks, for testing).  targets_per_lane = 3 selects
  * the fused small-N kernel: one launch per product that reads the caller's
  * N x 3 forces and torques directly and writes the outputs (workgroups of
- * 16 wavefronts per 64 targets, each wavefront a sixteenth of the sources;
- * source_splits ignored); the autotuner tries it up to N = 8192.  Results
- * do not depend on the configuration beyond float rounding order.
+ * 16 wavefronts per 4, 8 or 16 targets, each wavefront a sixteenth of the
+ * sources; source_splits ignored); the autotuner tries it up to N = 8192.
+ * Until a configuration is set or tuned, an open-boundary solver uses two
+ * targets per lane below N = 32768 and the symmetric mode (automatic span)
+ * from N = 32768 on; rpy_get_tile_config reports the configuration the
+ * products use.  Results do not depend on the configuration beyond float
+ * rounding order.
  */
 rpy_status rpy_set_tile_config(rpy_solver *s, int angular, int targets_per_lane, int source_splits);
 rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_per_lane, int *source_splits);
@@ -541,7 +545,8 @@ rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_pe
  * Autotuner (an addition beside the paper's method): for the stored
  * positions' N and dtype, times every candidate (targets per lane x source
  * splits, and for 4096 <= N <= 2^18 the symmetric mode with 1 or 2 source
- * blocks per task) of the pair kernel with HIP events on hip_stream, for the
+ * blocks per task, and up to N = 8192 the fused kernel) of the pair kernel
+ * with HIP events on hip_stream, for the
  * translational product and, with include_angular, the angular one: a
  * screen of single products, then the fastest split of each targets-per-lane
  * value re-timed in interleaved rounds of back-to-back bursts (about 100 ms
@@ -550,7 +555,10 @@ rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_pe
  * configuration (<ms> below is its time per product).  With cache_path
  * != NULL the choice is looked up in / added to a text file of lines
  *   <arch>|<f32|f64>|<lin|ang>|<round(log2 N)> <targets_per_lane> <splits> <ms>
- * (a cached entry is used without timing).  Synchronises hip_stream.  A
+ * (a cached entry is used without timing).  Above N = 2^18, where every
+ * candidate costs a product of order N^2, nothing is timed: the symmetric
+ * mode with its automatic span is chosen (the faster one in the measured
+ * sweeps of N = 2^17 to 2^20).  Synchronises hip_stream.  A
  * single_wall solver is not timed: its tile configuration is reset to the
  * defaults of the wall kernel (two targets per lane, one with the angular
  * blocks; splits from N).

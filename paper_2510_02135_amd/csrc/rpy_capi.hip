@@ -45,7 +45,9 @@ rpy_status apply_staged(rpy_solver *s, bool ang, Tout *lin, Tout *angout, hipStr
     if (s->wall)
         return apply_wall<Real, Tout>(s, ang, s->f.as<vec4_t<Real>>(), s->t.as<vec4_t<Real>>(), lin, angout, st,
                                       pos_in);
-    if (s->cfg[ang ? 1 : 0].tm == 0) return apply_sym<Real, Tout>(s, ang, s->cfg[ang ? 1 : 0].n_split, lin, angout, st, pos_in);
+    const TileConfig &cf = s->cfg[ang ? 1 : 0];
+    if (cf.tm == 0 || (cf.automatic && s->n >= kAutoSymN))
+        return apply_sym<Real, Tout>(s, ang, cf.tm == 0 ? cf.n_split : 0, lin, angout, st, pos_in);
     if (s->cfg[ang ? 1 : 0].tm == 3)
         return apply_fused<Real, Tout>(s, ang, s->f.as<Real>(), ang ? s->t.as<Real>() : nullptr, 4, lin, angout, st,
                                        pos_in);

@@ -20,9 +20,11 @@ constexpr int kMaxRhs = 1024;       // vectors per multi-vector product
 
 // Tile configuration of the pair kernels.
 struct TileConfig {
-    int tm = 2;          // targets per lane (1, 2 or 4), or 0: symmetric pair mode (rpy_sym.hip)
+    int tm = 2;          // targets per lane (1, 2 or 4), 0: symmetric pair mode (rpy_sym.hip), 3: fused small-N kernel
     int n_split = 0;     // source splits (0 = choose from N); symmetric mode: source blocks per task
+    bool automatic = true;   // neither set nor tuned: the symmetric mode from kAutoSymN particles on
 };
+constexpr int64_t kAutoSymN = 32768;
 
 // Plain device buffer that only grows.
 struct DevBuf {

@@ -201,6 +201,29 @@ def test_every_tile_config_and_autotune_keep_parity(dtype, tmp_path):
             sol.setTileConfig(False, bad, 0)
 
 
+def test_untuned_default_and_untimed_choice_above_2_18(tmp_path):
+    """An untouched configuration reports two targets per lane below
+    N = 32768 and the symmetric mode from there on, and its products are
+    those of that mode bit for bit; above N = 2^18 the autotuner takes the
+    symmetric mode without timing anything (no cache line is written)."""
+    say("case untuned default / untimed choice above 2^18")
+    for n, want in ((32767, (2, 0)), (32768, (0, 0))):
+        s = workloads.uniform_cube(n, 0.1, 57, torques=True)
+        sol = _solver(True)
+        sol.setPositions(to_dev(s.pos, torch.float32))
+        assert sol.tileConfig(False) == want and sol.tileConfig(True) == want, n
+        F, T = to_dev(s.forces, torch.float32), to_dev(s.torques, torch.float32)
+        lin0, ang0 = sol.Mdot(F, T)
+        sol.setTileConfig(True, *want)
+        lin1, ang1 = sol.Mdot(F, T)
+        assert torch.equal(lin0, lin1) and torch.equal(ang0, ang1), n
+    big = _solver(True)
+    big.setPositions(to_dev(workloads.uniform_cube((1 << 18) + 1, 0.1, 58).pos, torch.float32))
+    cache = tmp_path / "tiles.txt"
+    assert big.autotune(str(cache)) == ((0, 0), (0, 0))
+    assert not cache.exists() or not cache.read_text().strip()
+
+
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("angular", [False, True])
 @pytest.mark.parametrize("n", [1, 2, 15, 16, 17, 63, 64, 65, 1000, 4097])
