@@ -77,9 +77,11 @@ hipEvent_t timing_begin(rpy_solver *s, int kind, double pairs) {
     if (!s->timing) return nullptr;
     auto &v = s->ev[kind];
     if (s->ev_used[kind] == v.size()) {
+        // timing only: no system-scope cache writeback and invalidation at
+        // each record, which would stall the work that follows it
         hipEvent_t a = nullptr, b = nullptr;
-        if (hipEventCreate(&a) != hipSuccess) return nullptr;
-        if (hipEventCreate(&b) != hipSuccess) {
+        if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return nullptr;
+        if (hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess) {
             (void)hipEventDestroy(a);
             return nullptr;
         }
@@ -300,6 +302,7 @@ void rpy_destroy(rpy_solver *s) {
     pse_release(s);
     if (s->host_flag) (void)hipHostFree(s->host_flag);
     if (s->host_stat) (void)hipHostFree(s->host_stat);
+    if (s->lz_event) (void)hipEventDestroy(s->lz_event);
     delete s;
 }
 

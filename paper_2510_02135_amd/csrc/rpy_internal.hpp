@@ -114,5 +114,6 @@ struct rpy_solver {
     unsigned *host_flag = nullptr;   // pinned host word for flags
     double *host_stat = nullptr;     // pinned host copy of the Lanczos status blocks
     size_t host_stat_cap = 0;        // doubles in host_stat
+    hipEvent_t lz_event = nullptr;   // Lanczos: end of an iteration's stopping test (host waits on it)
     std::string err;
 };

@@ -220,6 +220,7 @@ __device__ __noinline__ void tridiag_sqrt_block(const double *__restrict__ alpha
 constexpr int kMonNodes = 128;
 constexpr int kMonThreads = kMonNodes + 64;
 constexpr int kMonChunk = 16;  // scratch rows fetched together in the forward pass
+constexpr int kMonRows = 8;    // rows of the node sums per wavefront at a time
 
 // 1/x from the hardware estimate and two Newton steps y <- y + y (1 - x y)
 // (within an ulp or two; the serial recurrences below run on its latency).
@@ -312,20 +313,24 @@ __device__ __noinline__ void monitor_block(const double *__restrict__ alpha, con
         scratch[(size_t)(kk - 1) * kMonNodes + l] = wl * y;
     }
     __syncthreads();
-    // q_i = sum_l w_l y_{l,i}: one wavefront per row, coalesced, two rows at a time
-    for (int i = 2 * wv; i < kk; i += 2 * kWaves) {
-        const double *r0 = scratch + (size_t)i * kMonNodes;
-        const bool two = i + 1 < kk;
-        double s0 = 0.0, s1 = 0.0;
-        for (int n = lane; n < kMonNodes; n += 64) {
-            s0 += r0[n];
-            if (two) s1 += r0[kMonNodes + n];
+    // q_i = sum_l w_l y_{l,i}: each wavefront takes kMonRows rows at a time,
+    // all their loads issued together (coalesced along l), then one
+    // butterfly per row
+    static_assert(kMonNodes == 128, "two nodes per lane");
+    for (int i0 = kMonRows * wv; i0 < kk; i0 += kMonRows * kWaves) {
+        double sr[kMonRows];
+#pragma unroll
+        for (int u = 0; u < kMonRows; ++u) {
+            const double *row = scratch + (size_t)(i0 + u) * kMonNodes;
+            sr[u] = i0 + u < kk ? row[lane] + row[lane + 64] : 0.0;
         }
-        s0 = wave_sum(s0);
-        s1 = wave_sum(s1);
-        if (lane == 0) {
-            q[i] = s0;
-            if (two) q[i + 1] = s1;
+#pragma unroll
+        for (int u = 0; u < kMonRows; ++u) sr[u] = wave_sum(sr[u]);
+        if (lane < kMonRows && i0 + lane < kk) {
+            double mine = sr[0];
+#pragma unroll
+            for (int u = 1; u < kMonRows; ++u) mine = lane == u ? sr[u] : mine;
+            q[i0 + lane] = mine;
         }
     }
     __syncthreads();
