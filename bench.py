@@ -70,9 +70,9 @@ def parse():
     p.add_argument("--sweep", action="store_true",
                    help="instead of the step: Mdot time against N = 2^10 .. 2^20 at number densities 0.1 and "
                         "0.001 per a^3 (translational, float32), the axes of the paper's timing figure")
-    p.add_argument("--batch-only", nargs="?", const="all", default=None, choices=("all", "mdot"),
+    p.add_argument("--batch-only", nargs="?", const="all", default=None, choices=("all", "mdot", "batched"),
                    help="instead of the step: only the 512 batched systems (one launch against one per system); "
-                        "'mdot' stops after the batched products")
+                        "'mdot' stops after the batched products, 'batched' skips the per-system calls")
     p.add_argument("--sweep-sizes", default=None,
                    help="comma-separated particle counts for --sweep (default: 2^10 .. 2^20)")
     p.add_argument("--breakdown-only", action="store_true",
@@ -127,10 +127,11 @@ def hbm_traffic(kernel: str, n: int, tile):
     return None
 
 
-def bench_batched(rpy, workloads, dev, stream, timed, mdot_only=False):
+def bench_batched(rpy, workloads, dev, stream, timed, mdot_only=False, batched_only=False):
     """512 independent systems (N log-uniform in [64, 8192], phi in [0.05, 0.3],
     seed 1004), float32: Mdot and sqrtMdotW (tol 1e-6) for all systems in one
-    batched call vs one single-system solver call per system."""
+    batched call vs one single-system solver call per system (batched_only:
+    without the per-system calls)."""
     import numpy as np
     import torch
     syss = workloads.c4_systems()
@@ -178,6 +179,14 @@ def bench_batched(rpy, workloads, dev, stream, timed, mdot_only=False):
     torch.cuda.synchronize()
     t_sqrt = 1e3 * (time.perf_counter() - t0)
     iters = np.array(b.last_iterations)
+    if batched_only:
+        b.close()
+        return {"systems": len(syss), "total_particles": int(off[-1]), "sum_n2": pairs,
+                "tile_config": {"targets_per_lane": batch_tiles[0], "workgroups_per_cu": batch_tiles[1]},
+                "mdot_ms": round(t_mdot, 4), "mdot_pairs_per_s": pairs / (t_mdot * 1e-3),
+                "sqrt_ms": round(t_sqrt, 3),
+                "lanczos_iterations": {"min": int(iters.min()), "median": float(np.median(iters)),
+                                       "max": int(iters.max())}, "angular": angular}
     # one solver call per system (each system's arrays already on the device)
     sols = []
     for k, s in enumerate(syss):
@@ -451,7 +460,8 @@ def main():
                           "config": {"workload": "512 systems, N log-uniform in [64, 8192], phi in [0.05, 0.3], "
                                                  "seed 1004"},
                           "batched": bench_batched(rpy, workloads, dev, stream, timed,
-                                                   mdot_only=args.batch_only == "mdot")}), flush=True)
+                                                   mdot_only=args.batch_only == "mdot",
+                                                   batched_only=args.batch_only == "batched")}), flush=True)
         return
     pse_kw = {}
     if args.pse_size:

@@ -436,43 +436,61 @@ __global__ void seg_sub_alpha(double *__restrict__ w, const double *__restrict__
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) w[i] = fma(-a, vk[i], w[i]);
 }
 
-// partial[b * kcap + j] = V[j][block] . w[block], j < k (eight columns per barrier)
+// partial[b * kcap + j] = V[j][block] . w[block], j < k.  Each thread keeps
+// its kSegChunk / kSegThreads entries of w in registers and, per group of
+// eight columns, issues all its loads of the group before the first
+// multiply-add (enough loads in flight to stream V near the HBM rate); the
+// columns' sums are then added by wavefront butterflies and the wavefronts'
+// values in order (one barrier pair per group).
 __global__ void __launch_bounds__(kSegThreads)
 seg_gemv_t_partial(const double *__restrict__ V, int64_t ld, const double *__restrict__ w, SegMap m,
                    const int *__restrict__ active, const int *__restrict__ kdev, int kcap,
                    double *__restrict__ partial) {
     constexpr int kCols = 8;
+    constexpr int kRows = kSegChunk / kSegThreads;
     constexpr int kWaves = kSegThreads / 64;
-    __shared__ double sh[kCols][kWaves];
+    static_assert(kSegChunk % kSegThreads == 0, "whole rows per thread");
+    __shared__ double sh[kWaves][kCols];
     int s;
     int64_t lo, hi;
     if (seg_skip(m, active, s, lo, hi)) return;
     const int k = kdev[0];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double wr[kRows];
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+        const int64_t i = lo + tid + (int64_t)q * kSegThreads;
+        wr[q] = i < hi ? w[i] : 0.0;
+    }
     for (int j0 = 0; j0 < k; j0 += kCols) {
-        const int nc = min(kCols, k - j0);
+        double x[kCols][kRows];
+#pragma unroll
+        for (int c = 0; c < kCols; ++c)
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) {
+                const int64_t i = lo + tid + (int64_t)q * kSegThreads;
+                x[c][q] = (j0 + c < k && i < hi) ? V[(size_t)(j0 + c) * ld + i] : 0.0;
+            }
         double acc[kCols];
 #pragma unroll
-        for (int c = 0; c < kCols; ++c) acc[c] = 0.0;
-        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-            const double wi = w[i];
-#pragma unroll
-            for (int c = 0; c < kCols; ++c)
-                if (c < nc) acc[c] = fma(V[(size_t)(j0 + c) * ld + i], wi, acc[c]);
-        }
-#pragma unroll
         for (int c = 0; c < kCols; ++c) {
-            const double v = wave_sum(acc[c]);
-            if (lane == 0) sh[c][wv] = v;
+            acc[c] = 0.0;
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) acc[c] = fma(x[c][q], wr[q], acc[c]);
+            acc[c] = wave_sum(acc[c]);
+        }
+        __syncthreads();   // the previous group's values have been read
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < kCols; ++c) sh[wv][c] = acc[c];
         }
         __syncthreads();
-        if (threadIdx.x < nc) {
+        if (tid < kCols && j0 + tid < k) {
             double t = 0.0;
 #pragma unroll
-            for (int q = 0; q < kWaves; ++q) t += sh[threadIdx.x][q];
-            partial[(size_t)blockIdx.x * kcap + j0 + threadIdx.x] = t;
+            for (int q = 0; q < kWaves; ++q) t += sh[q][tid];
+            partial[(size_t)blockIdx.x * kcap + j0 + tid] = t;
         }
-        __syncthreads();
     }
 }
 
@@ -490,10 +508,14 @@ __global__ void seg_gemv_t_final(const double *__restrict__ partial, const int *
     }
 }
 
-// w -= V_k h_s over the block
-__global__ void seg_gemv_n_sub(const double *__restrict__ V, int64_t ld, const double *__restrict__ h,
-                               int64_t lstride, double *__restrict__ w, SegMap m, const int *__restrict__ active,
-                               const int *__restrict__ kdev) {
+// w -= V_k h_s over the block: each thread takes its kSegChunk / kSegThreads
+// rows at once and, per group of eight columns, issues all the group's
+// loads before its multiply-adds (each row's sum in column order).
+__global__ void __launch_bounds__(kSegThreads)
+seg_gemv_n_sub(const double *__restrict__ V, int64_t ld, const double *__restrict__ h, int64_t lstride,
+               double *__restrict__ w, SegMap m, const int *__restrict__ active, const int *__restrict__ kdev) {
+    constexpr int kCols = 8;
+    constexpr int kRows = kSegChunk / kSegThreads;
     __shared__ double hs[kMaxK];
     int s;
     int64_t lo, hi;
@@ -501,10 +523,28 @@ __global__ void seg_gemv_n_sub(const double *__restrict__ V, int64_t ld, const d
     const int k = kdev[0];
     for (int j = threadIdx.x; j < k; j += blockDim.x) hs[j] = h[(size_t)s * lstride + j];
     __syncthreads();
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
-        double acc = 0.0;
-        for (int j = 0; j < k; ++j) acc = fma(V[(size_t)j * ld + i], hs[j], acc);
-        w[i] -= acc;
+    double acc[kRows];
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) acc[q] = 0.0;
+    for (int j0 = 0; j0 < k; j0 += kCols) {
+        double x[kCols][kRows];
+#pragma unroll
+        for (int c = 0; c < kCols; ++c)
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) {
+                const int64_t i = lo + threadIdx.x + (int64_t)q * kSegThreads;
+                x[c][q] = (j0 + c < k && i < hi) ? V[(size_t)(j0 + c) * ld + i] : 0.0;
+            }
+#pragma unroll
+        for (int c = 0; c < kCols; ++c)
+            if (j0 + c < k)
+#pragma unroll
+                for (int q = 0; q < kRows; ++q) acc[q] = fma(x[c][q], hs[j0 + c], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < kRows; ++q) {
+        const int64_t i = lo + threadIdx.x + (int64_t)q * kSegThreads;
+        if (i < hi) w[i] -= acc[q];
     }
 }
 
