@@ -222,12 +222,11 @@ struct BatchPairs : FwdPairs<Real, ANG> {
         if constexpr (ANG) k.t = idx < n ? a.rec[NRS * idx + 2] : zero4;
         return k;
     }
+    // record r of source js as stored (a padding source js >= n reads
+    // particle n - 1; sym_block_task zeroes its records r > 0)
     __device__ static R4 record(const Args &a, const PairConst<Real> &c, int r, int js, int n) {
         (void)c;
-        const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
-        if (r == 0) return a.rec[NRS * min(js, n - 1)];
-        if (js >= n) return zero4;
-        return a.rec[NRS * js + r];
+        return a.rec[NRS * min(js, n - 1) + r];
     }
 };
 

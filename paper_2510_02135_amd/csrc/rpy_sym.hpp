@@ -160,13 +160,14 @@ struct FwdPairs {
         k.t = (ANG && idx < n) ? a.trq[idx] : zero4;
         return k;
     }
-    // records of source js: position, force (, torque)
+    // record r of source js (position, force (, torque)) as stored; a
+    // padding source js >= n reads particle n - 1, and sym_block_task zeroes
+    // its records r > 0 when it stores them.  One load from a base chosen per
+    // record (r is uniform over the wavefront)
     __device__ static R4 record(const Args &a, const PairConst<Real> &c, int r, int js, int n) {
         (void)c;
-        const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
-        if (r == 0) return a.pos[min(js, n - 1)];
-        if (js >= n) return zero4;
-        return r == 1 ? a.frc[js] : a.trq[js];
+        const R4 *src = r == 0 ? a.pos : (r == 1 ? a.frc : a.trq);
+        return src[min(js, n - 1)];
     }
     __device__ static void one_sided(const Tgt &k, const R4 *q, const PairConst<Real> &c, Real *acc) {
         if constexpr (ANG) {
@@ -231,15 +232,12 @@ struct AdjPairs {
         }
         return k;
     }
+    // as FwdPairs::record: records r > 0 of padding sources are zeroed by
+    // the caller
     __device__ static R4 record(const Args &a, const PairConst<Real> &c, int r, int js, int n) {
         (void)c;
-        const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
-        if (r == 0) return a.pos[min(js, n - 1)];
-        if (js >= n) return zero4;
-        if (r == 1) return a.frc[js];
-        if (r == 2) return a.gu[js];
-        if (r == 3) return a.trq[js];
-        return a.gw[js];
+        const R4 *src = r == 0 ? a.pos : r == 1 ? a.frc : r == 2 ? a.gu : r == 3 ? a.trq : a.gw;
+        return src[min(js, n - 1)];
     }
     __device__ static void one_sided(const Tgt &k, const R4 *q, const PairConst<Real> &c, Real *acc) {
         const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
@@ -261,6 +259,10 @@ struct AdjPairs {
 //   ipart: [slot - slot_base][PC][BLK]  target-side partials (float32: sums,
 //          then compensations; PC = 2 NC, float64: NC)
 //   jpart: [I - jbase][NC][n]           source-side partials
+// s_waitcnt immediate of the GFX9 family: vmcnt(0), expcnt and lgkmcnt not
+// waited for (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kWaitVmcnt0 = 0x0F70;
+
 template <typename Real, typename P>
 __device__ __forceinline__ void sym_block_task(const typename P::Args &args, int n, const int4 task, int slot_base,
                                                int jbase, const PairConst<Real> &c, Real *__restrict__ ipart,
@@ -312,6 +314,11 @@ __device__ __forceinline__ void sym_block_task(const typename P::Args &args, int
     typename P::Tgt tg[TM];
 #pragma unroll
     for (int m = 0; m < TM; ++m) tg[m] = P::target(args, c, bi * BLK + m * kSymThreads + tid, n);
+    // the targets' loads complete here, before the first prefetch of source
+    // records: the compiler then knows them complete inside the step loop,
+    // which otherwise waits there for every outstanding load (the prefetch
+    // included) at the first step of each chunk
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     Real acc[TM][NC];
     Real sum[TM][COMP ? NC : 1], cmp[TM][COMP ? NC : 1];
 #pragma unroll
@@ -348,12 +355,19 @@ __device__ __forceinline__ void sym_block_task(const typename P::Args &args, int
     for (int ci = 0; ci < nchunks; ++ci) {
         const int bf = ci & 1;
         const bool diag = task.y + ci / CHUNKS == bi;
+        // the prefetched records have arrived (in every wavefront, also those
+        // that load none: the compiler then knows the prefetch registers free
+        // when the next prefetch is set up after the partials' stores)
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
 #pragma unroll
         for (int u = 0; u < RPW; ++u) {
             const int r = wv + u * kWaves;
             if (r < NR) {
-                put_rec(bf, r, lane, nxt[u]);
-                put_rec(bf, r, lane + kSymChunk, nxt[u]);
+                // records r > 0 (vectors) of padding sources vanish
+                const R4 zero4 = {Real(0), Real(0), Real(0), Real(0)};
+                const R4 v = (r > 0 && chunk_base(ci) + lane >= n) ? zero4 : nxt[u];
+                put_rec(bf, r, lane, v);
+                put_rec(bf, r, lane + kSymChunk, v);
             }
         }
         // rec[bf] complete; every wave has finished chunk ci - 1
