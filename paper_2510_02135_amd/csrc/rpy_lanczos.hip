@@ -670,7 +670,12 @@ rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t w
     // on an event after the monitor instead of the stream), so the device
     // does not idle through the host's round trip.  Should iteration k stop
     // after all, that product is discarded (its result is never read).
+    // RPY_LANCZOS_AHEAD=always enqueues the next product at every monitored
+    // iteration from k = 3 on (=never: at none), for testing that a discarded
+    // product changes nothing
     constexpr double kAheadFactor = 10.0;
+    const char *ahead_env = std::getenv("RPY_LANCZOS_AHEAD");
+    const int ahead_mode = !ahead_env ? 0 : std::string(ahead_env) == "always" ? 1 : std::string(ahead_env) == "never" ? 2 : 0;
     const bool lookahead = nrhs == 1 && !check_every;
     hipEvent_t mon_done = nullptr;
     if (lookahead) {
@@ -759,7 +764,8 @@ rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t w
                 HIP_TRY(s, hipEventRecord(mon_done, st));
                 enqueue_next_basis(R, 0, k);
                 basis_ahead = true;
-                if (k >= 3 && k < kmax && prev_est > kAheadFactor * tol) {
+                const bool ahead = ahead_mode == 1 || (ahead_mode == 0 && prev_est > kAheadFactor * tol);
+                if (k >= 3 && k < kmax && ahead) {
                     r = fp32 ? lanczos_products<float>(s, act, ld, k, W, st, pre, stage_next)
                              : lanczos_products<double>(s, act, ld, k, W, st, pre, stage_next);
                     if (r != RPY_OK) return r;

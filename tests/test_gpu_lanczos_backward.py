@@ -88,6 +88,43 @@ def test_lanczos_stopping_iteration_against_oracle(monkeypatch, angular, tol):
         assert e <= 1e-12
 
 
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("case", ["estimate", "breakdown"])
+def test_lanczos_lookahead_changes_nothing(monkeypatch, dtype, case):
+    """The next product enqueued ahead of the stopping test (and discarded at
+    the iteration that stops) leaves the result and the iteration count
+    exactly as without it: RPY_LANCZOS_AHEAD=always against =never, bit for
+    bit, on a solve that stops by the quadrature estimate (N = 300 with
+    torques) and on one that ends in a breakdown (two distant particles,
+    a Krylov space of dimension 4); the forced case matches the oracle."""
+    say(f"case lanczos lookahead {case} {dtype}")
+    rng = np.random.default_rng(78)
+    if case == "estimate":
+        s = workloads.uniform_cube(300, 0.2, 42, w=True, angular_w=True)
+        x, w, angular = s.pos, s.w, True
+    else:
+        x = np.array([[0.0, 0.0, 0.0], [300.0, 10.0, -5.0]])
+        w, angular = rng.standard_normal(6), False
+    m = mobility.grand_mobility(rounded(x, dtype), workloads.RADIUS, workloads.VISCOSITY, angular)
+    y_ref, info = lanczos.lanczos_sqrt(lambda v: m @ v, rounded(w, dtype), tol=1e-6)
+    sol = _solver(angular)
+    sol.setPositions(to_dev(x, dtype))
+    res = {}
+    for mode in ("never", "always"):
+        monkeypatch.setenv("RPY_LANCZOS_AHEAD", mode)
+        lin, ang = sol.sqrtMdotW(to_dev(w, dtype), tol=1e-6)
+        res[mode] = (lin.clone(), None if ang is None else ang.clone(), sol.last_iterations)
+    monkeypatch.delenv("RPY_LANCZOS_AHEAD")
+    (l0, a0, k0), (l1, a1, k1) = res["never"], res["always"]
+    say(f"  iterations {k0} / {k1} (oracle {info.iters})")
+    assert k0 == k1
+    assert torch.equal(l0, l1) and (a0 is None or torch.equal(a0, a1))
+    if dtype == torch.float64:
+        assert k1 == info.iters
+        y = _flat(l1, a1)
+        assert float(np.abs(y - y_ref).max() / np.abs(y_ref).max()) <= 1e-12
+
+
 def test_lanczos_zero_noise_and_not_converged():
     import paper_2510_02135_amd as rpy
     say("case lanczos edge cases")
