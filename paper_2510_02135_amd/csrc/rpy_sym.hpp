@@ -281,28 +281,30 @@ __device__ __forceinline__ void sym_block_task(const typename P::Args &args, int
     // plus a constant per step.  Source-side sums travel with their source
     // through the lanes (registers rotated by one lane per step) and land in
     // jl[bf][wave][k][q] at the end of the chunk
-    // float64 records are kept as two 16-byte planes (x, y) and (z, w): lanes
-    // reading consecutive 32-byte records would put lanes l and l + 4 on the
-    // same LDS banks; with 16-byte planes each group of 8 lanes covers the 32
-    // banks once
+    // float64 records are kept as a 16-byte plane (x, y) and an 8-byte plane
+    // z (w is never read): lanes reading consecutive 32-byte records would put
+    // lanes l and l + 4 on the same LDS banks, and a (z, w) plane read for z
+    // alone lanes l and l + 8; with these planes every read is consecutive
     constexpr int HP = std::is_same<Real, double>::value ? 2 : 1;
     using H = typename std::conditional<HP == 2, double2, R4>::type;
-    __shared__ H rec[2][NR][HP][2 * kSymChunk];
+    constexpr int ZC = HP == 2 ? 2 * kSymChunk : 1;
+    __shared__ H rec[2][NR][2 * kSymChunk];
+    __shared__ Real recz[2][NR][ZC];
     __shared__ Real jl[2][kWaves][NC][kSymChunk];
     auto put_rec = [&](int bf, int r, int col, const R4 &v) {
         if constexpr (HP == 2) {
-            rec[bf][r][0][col] = H{v.x, v.y};
-            rec[bf][r][1][col] = H{v.z, v.w};
+            rec[bf][r][col] = H{v.x, v.y};
+            recz[bf][r][col] = v.z;
         } else {
-            rec[bf][r][0][col] = v;
+            rec[bf][r][col] = v;
         }
     };
     auto get_rec = [&](int bf, int r, int col) -> R4 {
         if constexpr (HP == 2) {
-            const H a = rec[bf][r][0][col], b = rec[bf][r][1][col];
-            return R4{a.x, a.y, b.x, b.y};
+            const H a = rec[bf][r][col];
+            return R4{a.x, a.y, recz[bf][r][col], Real(0)};
         } else {
-            return rec[bf][r][0][col];
+            return rec[bf][r][col];
         }
     };
 
