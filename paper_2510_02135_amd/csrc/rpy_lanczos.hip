@@ -5,7 +5,8 @@
 // M v_k use the solver's pair precision (float32 pairs for float32
 // solvers).  Per iteration k (v_k = column k-1 of the basis V):
 //   w = M v_k;  w -= beta_{k-1} v_{k-1};  alpha_k = v_k . w;  w -= alpha_k v_k
-//   two passes of classical Gram-Schmidt against V_k (w -= V_k (V_k^T w))
+//   classical Gram-Schmidt against V_k (w -= V_k (V_k^T w)), a second pass
+//     when the first removed more than half of |w|^2
 //   beta_k = |w|
 //   T_k = tridiag(beta, alpha, beta) = Q diag(lambda) Q^T on one workgroup
 //     (implicit-shift QL), s_k = Q diag(sqrt(lambda)) Q^T e_1, and the
@@ -13,9 +14,11 @@
 //     |y_k - y_{k-1}| / |y_k| for y_k = beta_0 V_k s_k because V_k is
 //     orthonormal;
 //   v_{k+1} = w / beta_k.
-// The host reads a small status block after each iteration to decide
-// whether to stop (first k >= 2 with increment < tol; a clearly negative
-// Ritz value; beta_k ~ 0 meaning the Krylov space is invariant).  s_{k-1}
+// The host reads a small status block after each iteration, written by the
+// device to pinned host memory, to decide whether to stop (first k >= 2
+// with increment < tol; a clearly negative Ritz value; beta_k ~ 0 meaning
+// the Krylov space is invariant); with one recurrence the next basis vector
+// and, while far from tol, its product are already enqueued meanwhile.  s_{k-1}
 // and s_k come from a quadrature estimate of T^{1/2} e_1 that is exact to
 // rounding for safely positive definite T_k; the eigensolver runs only where
 // that estimate cannot decide.  The final y = prefactor * beta_0 V_k s_k is
@@ -45,12 +48,10 @@ namespace {
 constexpr int kRedBlocks = 256;    // blocks of the first reduction stage
 constexpr int kRedThreads = 256;
 
-// status block (double): [0] beta0, [1] relative increment, [2] flags,
-// [3] running max(|alpha|, beta), [4] first breakdown iteration (0 = none),
-// [5] estimated relative increment (monitor)
-// status block: beta0, increment, flags, scale of T, breakdown step, stopping
-// estimate, |w|^2 before Gram-Schmidt, skip flag of the second pass, bytes
-// of skipped passes
+// status block (double): beta0, relative increment, flags, running
+// max(|alpha|, beta), first breakdown iteration (0 = none), estimated
+// relative increment (monitor), |w|^2 before Gram-Schmidt, skip flag of the
+// second pass, bytes of skipped passes
 enum { ST_BETA0 = 0, ST_INCR = 1, ST_FLAGS = 2, ST_TSCALE = 3, ST_BREAK = 4, ST_EST = 5, ST_NW = 6, ST_SKIP = 7,
        ST_SKIPPED = 8, ST_SIZE = 10 };
 enum { FLAG_NOT_SPD = 1, FLAG_NONFINITE = 2 };
