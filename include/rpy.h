@@ -549,9 +549,9 @@ rpy_status rpy_get_tile_config(const rpy_solver *s, int angular, int *targets_pe
  * with HIP events on hip_stream, for the
  * translational product and, with include_angular, the angular one: a
  * screen of single products, then the fastest split of each targets-per-lane
- * value re-timed in interleaved rounds of back-to-back bursts (about 100 ms
- * each), whose median rate under
- * sustained load decides; the winner becomes the solver's tile
+ * value (each span of the symmetric mode separately) re-timed in
+ * interleaved rounds of back-to-back bursts (about 100 ms each), whose
+ * median rate under sustained load decides; the winner becomes the solver's tile
  * configuration (<ms> below is its time per product).  With cache_path
  * != NULL the choice is looked up in / added to a text file of lines
  *   <arch>|<f32|f64>|<lin|ang>|<round(log2 N)> <targets_per_lane> <splits> <ms>

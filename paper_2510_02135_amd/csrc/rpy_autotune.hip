@@ -228,7 +228,9 @@ rpy_status tune_mode(rpy_solver *s, bool ang, hipStream_t st, Entry *best) {
             screened.push_back({ms, c});
         }
     }
-    // stage 2: the fastest screened split of each targets-per-lane value,
+    // stage 2: the fastest screened split of each targets-per-lane value
+    // (each span of the symmetric mode counting as its own value: the
+    // screen's three single products do not separate them reliably),
     // re-timed in interleaved rounds of bursts of back-to-back products (so
     // clock and thermal drift affect them alike and the sustained rate
     // decides); the median round time picks the winner
@@ -239,9 +241,10 @@ rpy_status tune_mode(rpy_solver *s, bool ang, hipStream_t st, Entry *best) {
                       return x.first < y.first;
                   });
         std::vector<std::pair<double, TileConfig>> fin;
+        auto family = [](const TileConfig &c) { return c.tm == 0 ? -c.n_split : c.tm; };
         for (const auto &e : screened) {
             bool seen = false;
-            for (const auto &f : fin) seen = seen || f.second.tm == e.second.tm;
+            for (const auto &f : fin) seen = seen || family(f.second) == family(e.second);
             if (!seen) fin.push_back(e);
         }
         screened.swap(fin);
