@@ -523,7 +523,8 @@ void rpy_batch_destroy(rpy_batch *b);
  * targets_per_lane = 0 selects the symmetric pair mode instead: every
  * unordered pair is evaluated once and applied in both directions (blocks
  * of 512 particles, two targets per lane), source_splits then being the
- * number of 512-particle source blocks per task (0 = automatic); its
+ * number of 512-particle source blocks per task (0 = automatic: 1 up to
+ * N = 65536, 2 above); its
  * partials ((N/512) x 6 x N source-side values plus the target-side ones)
  * are produced and reduced in slabs of target blocks of at most about
  * 8 GiB of workspace each (the environment variable RPY_SYM_SLAB_BLOCKS=m
