@@ -751,6 +751,9 @@ rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t w
             HIP_TRY(s, hipGetLastError());
         }
         if (monitor) {
+            // iteration k - 1's estimate, read before this iteration's monitor
+            // rewrites the pinned mirror (the host waited for that monitor)
+            const double prev_est = lookahead ? hstat[(act[0]->status - status_all) + ST_EST] : 0.0;
             for (LzRec *R : act) {
                 const unsigned lds = k <= kMonLdsRows ? (unsigned)(sizeof(double) * k * kMonNodes) : 0u;
                 hipLaunchKernelGGL(lanczos_monitor_kernel, dim3(2), dim3(kMonThreads), lds, st, R->alpha, R->beta, k,
@@ -761,7 +764,6 @@ rpy_status lanczos_run_multi(rpy_solver *s, const Tio *w_in, int nrhs, int64_t w
             if (lookahead) {
                 // the previous estimate (k >= 3) decides whether the product goes ahead too
                 LzRec &R = *act[0];
-                const double prev_est = hstat[(R.status - status_all) + ST_EST];
                 HIP_TRY(s, hipEventRecord(mon_done, st));
                 enqueue_next_basis(R, 0, k);
                 basis_ahead = true;
