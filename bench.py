@@ -506,7 +506,10 @@ def main():
         tiles = sol.autotune(args.tile_cache)
     if tiles[1][0] == 0:   # the symmetric pair mode (each unordered pair once)
         kernel_name = "sym_kernel<float, FwdPairs<float, true>>"
-        kernel_label = f"{kernel_name} (angular, symmetric mode, {tiles[1][1]} source blocks per task)"
+        span = tiles[1][1]
+        span_text = ("automatic span" if span == 0 else
+                     f"{span} source block{'s' if span > 1 else ''} per task")
+        kernel_label = f"{kernel_name} (angular, symmetric mode, {span_text})"
     else:
         kernel_name = f"pair_kernel<float, true, {tiles[1][0]}>"
         kernel_label = f"{kernel_name} (angular, {tiles[1][1]} source splits)"
