@@ -404,8 +404,8 @@ def bench_sweep(rpy, workloads, dev, stream, sizes=None):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
-              "the multi-GPU layout is a design note, not an implementation.", file=sys.stderr)
+        print(f"bench.py: the solver runs on a single GPU (asked for {args.gpus}); "
+              "sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
