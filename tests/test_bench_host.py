@@ -20,7 +20,7 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
-    assert "one GPU" in r.stderr
+    assert "single GPU" in r.stderr
 
 
 def _summary(tmp_path, files, entries, top_files):
