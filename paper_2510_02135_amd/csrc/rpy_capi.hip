@@ -290,8 +290,8 @@ void rpy_destroy(rpy_solver *s) {
     if (!s) return;
     for (DevBuf *b : {&s->pos, &s->f, &s->t, &s->part, &s->flag, &s->lz_basis, &s->lz_w, &s->lz_scal, &s->lz_red,
                       &s->lz_q, &s->lz_vec, &s->lz_mon, &s->drift, &s->cg_vec, &s->cg_scal, &s->sym_fwd.task,
-                      &s->sym_fwd.slot, &s->sym_adj.task, &s->sym_adj.slot, &s->sym_jpart,
-                      &s->sym_state})
+                      &s->sym_fwd.slot, &s->sym_fwd.order, &s->sym_adj.task, &s->sym_adj.slot, &s->sym_adj.order,
+                      &s->sym_jpart, &s->sym_state})
         b->release();
     for (auto &v : s->ev)
         for (auto &pr : v) {

@@ -38,6 +38,7 @@ struct DevBuf {
 // Task list of the symmetric pair mode (rpy_sym.hip), cached for (n, span, block).
 struct SymTasks {
     DevBuf task, slot;
+    DevBuf order;                 // the same tasks, those holding a diagonal block last
     std::vector<int> slot_host;   // first task of each target block, and the total
     int64_t n = -1;
     int span = 0, blk = 0, ntasks = 0;

@@ -185,6 +185,14 @@ rpy_status sym_tasks(rpy_solver *s, SymTasks &T, int blk, int span) {
     HIP_TRY(s, T.task.ensure(sizeof(int4) * tasks.size()));
     HIP_TRY(s, T.slot.ensure(sizeof(int) * slot0.size()));
     HIP_TRY(s, hipMemcpy(T.task.p, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice));
+    // Launch order when one launch covers every task: the tasks that hold a
+    // diagonal block (its pairs evaluated one-sided, the cheaper loop) after
+    // all others, so that the last wave of workgroups is made of the shorter
+    // tasks.  A task's partials go to its own slot wherever it is launched,
+    // so the results do not depend on the order.
+    std::stable_partition(tasks.begin(), tasks.end(), [](const int4 &t) { return t.y != t.x; });
+    HIP_TRY(s, T.order.ensure(sizeof(int4) * tasks.size()));
+    HIP_TRY(s, hipMemcpy(T.order.p, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice));
     HIP_TRY(s, hipMemcpy(T.slot.p, slot0.data(), sizeof(int) * slot0.size(), hipMemcpyHostToDevice));
     T.slot_host = std::move(slot0);
     T.n = n;
@@ -247,8 +255,9 @@ rpy_status run_sym(rpy_solver *s, SymTasks &T, int span, const typename P::Args 
     for (int q = 0; q < nslab; ++q) {
         const int s0 = slab[q], s1 = slab[q + 1];
         const int t0 = T.slot_host[s0], t1 = T.slot_host[s1];
+        const int4 *list = nslab == 1 ? T.order.as<int4>() : T.task.as<int4>() + t0;
         hipLaunchKernelGGL((sym_kernel<Real, P>), dim3((unsigned)(t1 - t0)), dim3(kSymThreads), 0, st, args, (int)n,
-                           T.task.as<int4>() + t0, t0, s0, c, s->part.as<Real>(), s->sym_jpart.as<Real>());
+                           list, t0, s0, c, s->part.as<Real>(), s->sym_jpart.as<Real>());
         HIP_TRY(s, hipGetLastError());
         if (q == nslab - 1)
             if (hipEvent_t e1 = timing_end(s, kind)) HIP_TRY(s, hipEventRecord(e1, st));
