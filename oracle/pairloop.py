@@ -58,6 +58,18 @@ def _c64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
 
 
+def _inputs(x, forces, torques):
+    """Contiguous float64 copies, each checked to be N x 3 (the C loop reads
+    3 N values of every array it is given)."""
+    x, f, t = _c64(x), _c64(forces), _c64(torques)
+    if x.ndim != 2 or x.shape[1] != 3:
+        raise ValueError(f"positions must be N x 3, got shape {x.shape}")
+    for name, v in (("forces", f), ("torques", t)):
+        if v is not None and v.shape != x.shape:
+            raise ValueError(f"{name} must have the positions' shape {x.shape}, got {v.shape}")
+    return x, f, t
+
+
 def threads() -> int:
     return int(load().oracle_threads())
 
@@ -65,7 +77,7 @@ def threads() -> int:
 def mdot(x, forces=None, torques=None, a: float = 1.0, eta: float = 1.0 / (6 * math.pi)):
     """(U, Omega) for every particle; Omega is None without torques."""
     lib = load()
-    x, f, t = _c64(x), _c64(forces), _c64(torques)
+    x, f, t = _inputs(x, forces, torques)
     n = x.shape[0]
     u = np.empty((n, 3))
     w = np.empty((n, 3)) if t is not None else None
@@ -77,8 +89,13 @@ def mdot_rows(x, rows, forces=None, torques=None, a: float = 1.0,
               eta: float = 1.0 / (6 * math.pi)):
     """(U, Omega) for the target particles ``rows`` only (in that order)."""
     lib = load()
-    x, f, t = _c64(x), _c64(forces), _c64(torques)
+    x, f, t = _inputs(x, forces, torques)
+    rows = np.asarray(rows)
+    if rows.ndim != 1 or (rows.size and not np.issubdtype(rows.dtype, np.integer)):
+        raise ValueError("rows must be a 1-D array of particle indices")
     rows = np.ascontiguousarray(rows, dtype=np.int64)
+    if rows.size and (rows.min() < 0 or rows.max() >= x.shape[0]):
+        raise ValueError(f"rows must lie in [0, {x.shape[0]})")
     m = rows.shape[0]
     u = np.empty((m, 3))
     w = np.empty((m, 3)) if t is not None else None
