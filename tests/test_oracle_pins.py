@@ -297,3 +297,25 @@ def test_dense_rows_and_c_pairloop_agree(pairloop):
     U0, W0 = mob.mdot_dense(x, None, T, a, eta)
     np.testing.assert_allclose(Ut, U0, atol=1e-13)
     np.testing.assert_allclose(Wt, W0, atol=1e-13)
+
+
+def test_pairloop_binding_rejects_malformed_inputs(pairloop):
+    """The C loop reads 3N values of every array and any row index it is
+    given: the binding refuses shapes and rows that would take it outside."""
+    rng = np.random.default_rng(11)
+    x = rng.random((6, 3))
+    f = rng.standard_normal((6, 3))
+    for call in (lambda: pairloop.mdot(x, f[:5]),
+                 lambda: pairloop.mdot(x.reshape(-1), f),
+                 lambda: pairloop.mdot(x, f, f[:, :2]),
+                 lambda: pairloop.mdot_rows(x, [6], f),
+                 lambda: pairloop.mdot_rows(x, [-1], f),
+                 lambda: pairloop.mdot_rows(x, [0.0], f),
+                 lambda: pairloop.mdot_rows(x, [[0, 1]], f)):
+        with pytest.raises(ValueError):
+            call()
+    u, _ = pairloop.mdot_rows(x, np.array([], dtype=np.int64), f)
+    assert u.shape == (0, 3)
+    u_all, _ = pairloop.mdot(x, f)
+    u5, _ = pairloop.mdot_rows(x, [5, 0], f)
+    assert np.array_equal(u5, u_all[[5, 0]])
